@@ -1,0 +1,173 @@
+/*
+ * idp.h -- C-ABI of the MI355X library for the second-order
+ * invariant-domain-preserving (IDP) Q1 finite-element scheme for the
+ * compressible Euler equations (Maier & Kronbichler, arXiv:2007.00094).
+ *
+ * The problem (Section 3): given admissible conserved states U^n on the
+ * nodes of a Q1 mesh (rho > 0, internal energy > 0), compute the time step
+ * tau_n (Section 3.3) and U^{n+1} by SSP-RK3 (eq. ssprk3) over the limited
+ * forward-Euler update of Alg. 1 (low-order graph-viscosity update, high-
+ * order update with the entropy-viscosity indicator of Section 3.8, convex
+ * limiting of Section 3.9 with Alg. 2/3, two limiter passes).  The mesh
+ * matrices m_ij, c_ij, m_i (eq. matrices) are computed once, at create time.
+ *
+ * Conventions shared by every call:
+ *  - dim is 2 or 3; nc = dim + 2 conserved components per node, in the
+ *    order (rho, m_1..m_dim, E).
+ *  - State arrays are FP64, array-of-struct [n_nodes][nc], row-major,
+ *    contiguous, in the caller's node numbering, and live in DEVICE memory
+ *    of the device that was current at idp_create.  The library never keeps
+ *    a state pointer beyond the call and never aliases it.
+ *  - Mesh arrays given to idp_create are HOST memory, read during the call.
+ *  - Every device call is ordered on the HIP stream given at idp_create.
+ *    idp_step synchronises that stream at its end unless IDP_FLAG_ASYNC is
+ *    set; idp_max_dt always synchronises.
+ *  - A context is not thread-safe: one caller at a time.
+ *  - Return codes: 0 success, +1 warning (the step completed but tau
+ *    exceeded the stability bound m_i/(-2 d_ii) of stage 2 or 3), negative
+ *    values are errors (see IDP_E*); idp_strerror names them.
+ */
+#ifndef IDP_H
+#define IDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IDP_OK 0
+#define IDP_WARN_CFL 1          /* stage-2/3 tau exceeded m_i/(-2 d_ii)     */
+#define IDP_EINVAL (-1)         /* bad argument (null pointer, size, index)  */
+#define IDP_EMESH (-2)          /* det J <= 0 at a quadrature point          */
+#define IDP_ENOMEM (-3)         /* device or host allocation failed          */
+#define IDP_EHIP (-4)           /* HIP runtime error                         */
+#define IDP_ESTATE (-5)         /* input state not admissible (rho<=0, eps<=0, NaN) */
+#define IDP_EDT (-6)            /* given dt > min_i m_i/(-2 d_ii) at stage 1 */
+#define IDP_ENOTSUP (-7)        /* option not supported by this build        */
+
+/* flags for idp_params.flags */
+#define IDP_FLAG_ASYNC 1        /* idp_step does not synchronise; errors are
+                                   sticky and read with idp_get_status     */
+
+/* Parameters of the scheme.  gamma: ratio of specific heats (Section 2);
+ * cfl: c_cfl of Section 3.3 (0 < cfl <= 1); limiter_passes: 1 or 2
+ * (Section 3.5 asks for at least two); newton_max_iter, newton_tol: the
+ * iteration cap and the tolerance TOL of Alg. 2 (the paper gives no
+ * values; defaults 2 and 1e-10); relax_bounds must be 0 (the relaxation
+ * of the remark in Section 3.9 is not part of this build).              */
+typedef struct {
+    int dim;
+    double gamma;
+    double cfl;
+    int limiter_passes;
+    int newton_max_iter;
+    double newton_tol;
+    int relax_bounds;
+    int flags;
+} idp_params;
+
+typedef struct idp_ctx idp_ctx;
+
+/* Fill p with the defaults for dimension dim (gamma 1.4, cfl 0.5, two
+ * passes, 2 Newton steps, TOL 1e-10, no relaxation, synchronous).
+ * Returns IDP_EINVAL if dim is not 2 or 3.                               */
+int idp_default_params(idp_params *p, int dim);
+
+/* Build the solver for a Q1 mesh (Section 3.1-3.2).
+ *  coords    host [n_nodes][dim] node coordinates;
+ *  cells     host [n_cells][2^dim] node ids of each cell, vertex
+ *            b = bx + 2 by (+ 4 bz) at the reference corner (bx, by, bz);
+ *  dirichlet host [n_nodes] or NULL: 1 = the node keeps its step-initial
+ *            state after every stage (boundary values held);
+ *  hip_stream hipStream_t (may be NULL = default stream) used by every call.
+ * Builds the stencil graph I(i) (nodes sharing a cell, diagonal included),
+ * m_ij and c_ij by 3-point Gauss quadrature per direction, m_i = sum_j m_ij,
+ * and the device work buffers.  On success *out owns all of it; destroy
+ * with idp_destroy.  Errors: IDP_EINVAL (sizes, ids out of range, bad
+ * params), IDP_EMESH (an inverted or degenerate cell), IDP_ENOMEM, IDP_EHIP.*/
+int idp_create(idp_ctx **out, const idp_params *p, int64_t n_nodes,
+               const double *coords, int64_t n_cells, const int64_t *cells,
+               const uint8_t *dirichlet, void *hip_stream);
+
+/* tau = cfl * min_i m_i/(-2 d_ii(U)) (Section 3.3) for the device state
+ * U_dev; synchronises the stream.  IDP_ESTATE if U is not admissible.    */
+int idp_max_dt(idp_ctx *ctx, const double *U_dev, double *dt_out);
+
+/* One SSP-RK3 step (eq. ssprk3, increment form U^n + theta (E(U) - U^n))
+ * of the limited forward-Euler update E (Alg. 1), in place on U_dev.
+ * dt <= 0: tau = cfl * (stage-1 bound), computed on the device;
+ * dt > 0: tau = dt, IDP_EDT if dt exceeds the stage-1 bound (U untouched).
+ * dt_used (host, may be NULL) receives tau.  Returns IDP_OK, IDP_WARN_CFL,
+ * IDP_ESTATE (U untouched), IDP_EDT, or IDP_EHIP.  With IDP_FLAG_ASYNC the
+ * call returns IDP_OK after enqueueing and dt_used is not written.       */
+int idp_step(idp_ctx *ctx, double *U_dev, double dt, double *dt_used);
+
+/* One limited forward-Euler update Uout = E(U) with step tau (> 0), no
+ * boundary hold (the building block of idp_step, Alg. 1).  U_dev and
+ * Uout_dev must not overlap.  Synchronises.  Returns IDP_OK or
+ * IDP_WARN_CFL (tau > min_i m_i/(-2 d_ii)), IDP_ESTATE, IDP_EINVAL.      */
+int idp_euler_stage(idp_ctx *ctx, const double *U_dev, double tau,
+                    double *Uout_dev);
+
+/* Sticky status of asynchronous steps (synchronises, then clears it).    */
+int idp_get_status(idp_ctx *ctx);
+
+/* Sizes: nodes, stencil entries (CSR nonzeros incl. diagonal), bytes of
+ * device memory the context holds.  Any pointer may be NULL.            */
+int idp_info(const idp_ctx *ctx, int64_t *n_nodes, int64_t *nnz,
+             size_t *device_bytes);
+
+/* Host copies of the graph and matrices in CSR form (rows in the caller's
+ * node order, columns ascending): row_ptr [n+1], col [nnz], m_i [n],
+ * m_ij [nnz], c_ij [nnz][dim].  Any pointer may be NULL.  Synchronises.  */
+int idp_export_matrices(const idp_ctx *ctx, int64_t *row_ptr, int32_t *col,
+                        double *m_i, double *m_ij, double *c_ij);
+
+/* Host copy of an intermediate of the last forward-Euler stage run
+ * (idp_euler_stage, or the last stage of idp_step), CSR / node order:
+ *  IDP_DBG_D      d^L_ij [nnz] (diagonal: d_ii)
+ *  IDP_DBG_ALPHA  alpha_i [n]          IDP_DBG_R      R_i [n][nc]
+ *  IDP_DBG_UL     U^L_i [n][nc]        IDP_DBG_BOUNDS (rho_min, rho_max,
+ *                                                      phi_min) [n][3]
+ *  IDP_DBG_L1     l_ij pass 1 [nnz]    IDP_DBG_L2     l_ij pass 2 [nnz]
+ *  IDP_DBG_UPASS  state after pass 1 [n][nc]
+ *  IDP_DBG_TAUI   m_i/(-2 d_ii) [n]
+ * Synchronises.                                                          */
+#define IDP_DBG_D 0
+#define IDP_DBG_ALPHA 1
+#define IDP_DBG_R 2
+#define IDP_DBG_UL 3
+#define IDP_DBG_BOUNDS 4
+#define IDP_DBG_L1 5
+#define IDP_DBG_L2 6
+#define IDP_DBG_UPASS 7
+#define IDP_DBG_TAUI 8
+int idp_debug_export(idp_ctx *ctx, int what, double *host_out);
+
+/* Per-kernel timing with HIP events on the context's stream: on = 1 starts
+ * recording every kernel launch (and clears the totals), 0 stops.        */
+int idp_set_timing(idp_ctx *ctx, int on);
+
+/* Kernel names and accumulated event-timed milliseconds / launch counts.
+ * Fills at most max entries; returns the number of kernels, or < 0.      */
+int idp_kernel_times(idp_ctx *ctx, int max, const char **names,
+                     double *total_ms, int64_t *launches);
+
+/* Evaluate the device arithmetic on n values (device arrays): kind 0
+ * x^y (the library's fixed-method power), 1 sqrt(x), 2 x / y.  Used to
+ * check that device and host arithmetic agree bit for bit.  Synchronises. */
+int idp_device_math(idp_ctx *ctx, int kind, int64_t n, const double *x_dev,
+                    const double *y_dev, double *out_dev);
+
+/* Text of a return code.                                                 */
+const char *idp_strerror(int code);
+
+/* Free the context and its device memory (NULL is allowed).              */
+void idp_destroy(idp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IDP_H */

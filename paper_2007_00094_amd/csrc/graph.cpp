@@ -1,0 +1,166 @@
+// Host-side construction of the stencil graph and the SELL-64 layout.
+#include "graph.h"
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/idp.h"
+
+namespace idp {
+
+static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
+                 const int64_t *cells)
+{
+    const int nv = 1 << dim;
+    g.dim = dim;
+    g.nv = nv;
+    g.n = n;
+    g.ncells = ncells;
+    if (n <= 0 || ncells <= 0 || n >= (int64_t(1) << 31) ||
+        ncells * nv >= (int64_t(1) << 31))
+        return IDP_EINVAL;
+    const int64_t inc = ncells * nv;
+    int bad = 0;
+#pragma omp parallel for reduction(| : bad)
+    for (int64_t t = 0; t < inc; ++t)
+        if (cells[t] < 0 || cells[t] >= n) bad = 1;
+    if (bad) return IDP_EINVAL;
+
+    // node -> cells (ascending cell id): counting sort of the incidences
+    g.nc_ptr.assign(n + 1, 0);
+    for (int64_t t = 0; t < inc; ++t) g.nc_ptr[cells[t] + 1]++;
+    for (int64_t i = 0; i < n; ++i) g.nc_ptr[i + 1] += g.nc_ptr[i];
+    g.nc_list.resize(inc);
+    {
+        std::vector<int64_t> fill(g.nc_ptr.begin(), g.nc_ptr.end() - 1);
+        for (int64_t c = 0; c < ncells; ++c)
+            for (int b = 0; b < nv; ++b)
+                g.nc_list[fill[cells[c * nv + b]]++] = int32_t(c);
+    }
+
+    // rows: sorted unique vertices of the cells around each node
+    g.row_ptr.assign(n + 1, 0);
+    int maxlen = 0;
+#pragma omp parallel reduction(max : maxlen)
+    {
+        std::vector<int32_t> cand;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            cand.clear();
+            for (int64_t q = g.nc_ptr[i]; q < g.nc_ptr[i + 1]; ++q) {
+                const int64_t c = g.nc_list[q];
+                for (int b = 0; b < nv; ++b) cand.push_back(int32_t(cells[c * nv + b]));
+            }
+            std::sort(cand.begin(), cand.end());
+            const int len = int(std::unique(cand.begin(), cand.end()) - cand.begin());
+            g.row_ptr[i + 1] = len;
+            maxlen = std::max(maxlen, len);
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) g.row_ptr[i + 1] += g.row_ptr[i];
+    g.nnz = g.row_ptr[n];
+    g.max_len = maxlen;
+    g.col.resize(g.nnz);
+#pragma omp parallel
+    {
+        std::vector<int32_t> cand;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            cand.clear();
+            for (int64_t q = g.nc_ptr[i]; q < g.nc_ptr[i + 1]; ++q) {
+                const int64_t c = g.nc_list[q];
+                for (int b = 0; b < nv; ++b) cand.push_back(int32_t(cells[c * nv + b]));
+            }
+            std::sort(cand.begin(), cand.end());
+            auto end = std::unique(cand.begin(), cand.end());
+            std::copy(cand.begin(), end, g.col.begin() + g.row_ptr[i]);
+        }
+    }
+    // transposed positions: the stencil relation is symmetric
+    g.tpos.resize(g.nnz);
+    bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t q = g.row_ptr[i]; q < g.row_ptr[i + 1]; ++q) {
+            const int32_t j = g.col[q];
+            auto b = g.col.begin() + g.row_ptr[j], e = g.col.begin() + g.row_ptr[j + 1];
+            auto it = std::lower_bound(b, e, int32_t(i));
+            if (it == e || *it != i) { bad = 1; continue; }
+            g.tpos[q] = it - g.col.begin();
+        }
+    if (bad) return IDP_EINVAL;
+
+    // SELL-64: rows by length, longest first, stable in node id
+    g.nslices = (n + kSellC - 1) / kSellC;
+    const int64_t nrows = g.nslices * kSellC;
+    g.perm.assign(nrows, -1);
+    g.row_len.assign(nrows, 0);
+    g.diag_k.assign(nrows, 0);
+    {
+        std::vector<int64_t> cnt(maxlen + 2, 0);
+        for (int64_t i = 0; i < n; ++i) cnt[g.row_ptr[i + 1] - g.row_ptr[i]]++;
+        std::vector<int64_t> start(maxlen + 2, 0);
+        int64_t acc = 0;
+        for (int L = maxlen; L >= 0; --L) { start[L] = acc; acc += cnt[L]; }
+        for (int64_t i = 0; i < n; ++i) {
+            const int L = int(g.row_ptr[i + 1] - g.row_ptr[i]);
+            const int64_t r = start[L]++;
+            g.perm[r] = int32_t(i);
+            g.row_len[r] = L;
+        }
+    }
+    g.slice_w.resize(g.nslices);
+    g.slice_off.resize(g.nslices);
+    int64_t off = 0;
+    for (int64_t s = 0; s < g.nslices; ++s) {
+        g.slice_w[s] = g.row_len[s * kSellC];
+        g.slice_off[s] = off;
+        off += int64_t(g.slice_w[s]) * kSellC;
+    }
+    g.sell_size = off;
+    if (g.sell_size >= (int64_t(1) << 31)) return IDP_EINVAL;
+    g.sell_of_csr.resize(g.nnz);
+    g.scol.resize(g.sell_size);
+    g.stpos.resize(g.sell_size);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t s = r / kSellC, lane = r % kSellC;
+        const int32_t i = g.perm[r];
+        for (int k = 0; k < g.slice_w[s]; ++k) {
+            const int64_t e = g.slice_off[s] + int64_t(k) * kSellC + lane;
+            if (i >= 0 && k < g.row_len[r]) {
+                const int64_t q = g.row_ptr[i] + k;
+                g.sell_of_csr[q] = e;
+                g.scol[e] = g.col[q];
+                if (g.col[q] == i) g.diag_k[r] = k;
+            } else {
+                g.scol[e] = i >= 0 ? i : 0;  // padding: a valid node id
+            }
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t s = r / kSellC, lane = r % kSellC;
+        const int32_t i = g.perm[r];
+        for (int k = 0; k < g.slice_w[s]; ++k) {
+            const int64_t e = g.slice_off[s] + int64_t(k) * kSellC + lane;
+            if (i >= 0 && k < g.row_len[r])
+                g.stpos[e] = int32_t(g.sell_of_csr[g.tpos[g.row_ptr[i] + k]]);
+            else
+                g.stpos[e] = int32_t(e);
+        }
+    }
+    return IDP_OK;
+}
+
+int build_graph(HostGraph &g, int dim, int64_t n, int64_t ncells,
+                const int64_t *cells)
+{
+    try {
+        return build(g, dim, n, ncells, cells);
+    } catch (const std::bad_alloc &) {
+        return IDP_ENOMEM;
+    }
+}
+
+}  // namespace idp

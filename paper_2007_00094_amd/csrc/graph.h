@@ -1,0 +1,54 @@
+// Host-side stencil graph of a Q1 mesh and its SELL-64 device layout.
+//
+// The stencil I(i) (Section 3.1) is the set of nodes that share a cell with
+// node i, i included.  Rows are kept in CSR with ascending columns; for the
+// device the rows are additionally packed as SELL-C-sigma with C = 64 (one
+// wavefront lane per row) and sigma = all rows: rows sorted by length,
+// longest first, stable in node id, so that the slices of full-stencil
+// interior rows carry no padding (the paper's SELL-C-sigma layout, Section
+// 4.3, with the slice height set to the wavefront width instead of the
+// SIMD width).  Entry k of the row in lane l of slice s sits at
+// slice_off[s] + 64 k + l.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace idp {
+
+constexpr int kSellC = 64;
+
+struct HostGraph {
+    int dim = 0;
+    int nv = 0;              // vertices per cell, 2^dim
+    int64_t n = 0;           // nodes
+    int64_t ncells = 0;
+    int64_t nnz = 0;         // CSR entries, diagonal included
+    int max_len = 0;         // longest row
+
+    std::vector<int64_t> row_ptr;   // [n+1]
+    std::vector<int32_t> col;       // [nnz] ascending within a row
+    std::vector<int64_t> tpos;      // [nnz] CSR position of (j,i)
+
+    std::vector<int64_t> nc_ptr;    // [n+1] node -> cells, ascending cell id
+    std::vector<int32_t> nc_list;   // [ncells*nv]
+
+    // SELL-64
+    int64_t nslices = 0;
+    int64_t sell_size = 0;          // entries incl. padding
+    std::vector<int32_t> perm;      // [nslices*64] sorted row -> node (-1 pad)
+    std::vector<int32_t> row_len;   // [nslices*64] length of sorted row (0 pad)
+    std::vector<int32_t> diag_k;    // [nslices*64] position of i in its row
+    std::vector<int32_t> slice_w;   // [nslices]
+    std::vector<int64_t> slice_off; // [nslices]
+    std::vector<int64_t> sell_of_csr;  // [nnz]
+    std::vector<int32_t> scol;      // [sell_size] column node id (pad: own)
+    std::vector<int32_t> stpos;     // [sell_size] SELL position of (j,i)
+};
+
+// Returns 0 or a negative idp error code (IDP_EINVAL for ids out of range,
+// IDP_ENOMEM).  cells is [ncells][2^dim] (int64 node ids).
+int build_graph(HostGraph &g, int dim, int64_t n, int64_t ncells,
+                const int64_t *cells);
+
+}  // namespace idp

@@ -1,0 +1,670 @@
+// HIP kernels of the IDP Q1 Euler scheme (arXiv:2007.00094) for gfx950.
+//
+// One forward-Euler stage of Alg. 1 is five sweeps over the SELL-64 stencil
+// layout plus one node kernel:
+//   k_node    step 0   per node: p, c, eta/rho, v = m/rho, phi   (pack A)
+//   k_visc    steps 1-2 d_ij (both orientations, the larger), d_ii, tau_i,
+//                       indicator alpha_i (Section 3.8)
+//   k_low     step 3   R_i, U^L_i, bounds rho_min, rho_max, phi_min
+//   k_lim1    step 4   P_ij (eq. def-p, recomputed), l_ij pass 1 (Alg. 2)
+//   k_pass1   step 5   U_i += sum lambda_i min(l_ij,l_ji) P_ij; candidates
+//                       of pass 2 on the rescaled P
+//   k_pass2   step 6   final pass, then SSP-RK3 combination and boundary hold
+// One wavefront lane owns one stencil row (SELL slice of 64 rows) and sums
+// its columns in ascending order, sequentially, like the CPU oracle, so that
+// every row-level reduction has one writer and a fixed order.  Neighbour
+// data are gathered from node-major packs (128 bytes per node).  Blocks are
+// renumbered so that consecutive slices run on the same XCD (L2 locality of
+// the neighbour gathers).  No MFMA: the sweeps are sparse, FP64 and
+// gather-bound.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "idp_device.h"
+#include "kernels.h"
+
+namespace idp {
+
+__device__ __forceinline__ int64_t logical_block(int per)
+{
+    const int b = blockIdx.x;
+    return int64_t(b % kXcd) * per + b / kXcd;
+}
+
+#define ROW_SETUP(P)                                                         \
+    const int64_t s_ = logical_block(P.per) * (kBlock / kSlice) +            \
+                       threadIdx.x / kSlice;                                 \
+    if (s_ >= P.nslices) return;                                             \
+    const int lane_ = threadIdx.x % kSlice;                                  \
+    const int64_t r_ = s_ * kSlice + lane_;                                  \
+    const int i = P.perm[r_];                                                \
+    if (i < 0) return;                                                       \
+    const int L = P.row_len[r_];                                             \
+    const int64_t off_ = P.slice_off[s_] + lane_;
+
+#define ENTRY(k) (off_ + int64_t(k) * kSlice)
+
+__device__ __forceinline__ bool failed(const StageArgs &P)
+{
+    return (*P.status & kErrMask) != 0;
+}
+
+// ------------------------------------------------------------ matrices
+// Eq. matrices by 3-point Gauss quadrature per direction on each cell;
+// the row of node i accumulates the cell contributions in ascending cell
+// order.  For each cell the local row of i is integrated point by point.
+template <int D>
+__global__ void __launch_bounds__(kBlock)
+k_matrices(StageArgs P, const double *__restrict__ coords,
+           const int32_t *__restrict__ cells, const int64_t *__restrict__ nc_ptr,
+           const int32_t *__restrict__ nc_list, double gx0, double gx1, double gx2,
+           int *__restrict__ err)
+{
+    ROW_SETUP(P)
+    constexpr int NV = 1 << D;
+    constexpr int NQ = D == 2 ? 9 : 27;
+    const double gx[3] = {gx0, gx1, gx2};
+    const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = ENTRY(k);
+        P.mij[e] = 0.0;
+        P.c0[e] = 0.0;
+        P.c1[e] = 0.0;
+        if (D == 3) P.c2[e] = 0.0;
+    }
+    for (int64_t q = nc_ptr[i]; q < nc_ptr[i + 1]; ++q) {
+        const int32_t T = nc_list[q];
+        int vx[NV];
+        int a = 0;
+        for (int b = 0; b < NV; ++b) {
+            vx[b] = cells[int64_t(T) * NV + b];
+            if (vx[b] == i) a = b;
+        }
+        double xb[NV][D];
+        for (int b = 0; b < NV; ++b)
+            for (int p = 0; p < D; ++p) xb[b][p] = coords[int64_t(vx[b]) * D + p];
+        double mloc[NV], cloc[NV][D];
+        for (int b = 0; b < NV; ++b) {
+            mloc[b] = 0.0;
+            for (int p = 0; p < D; ++p) cloc[b][p] = 0.0;
+        }
+        for (int qp = 0; qp < NQ; ++qp) {
+            double xi[D];
+            double w = 1.0;
+            int qq = qp;
+            for (int k = 0; k < D; ++k) {
+                xi[k] = gx[qq % 3];
+                w *= gw[qq % 3];
+                qq /= 3;
+            }
+            double J[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+            double gr[NV][D], ph[NV];
+            for (int b = 0; b < NV; ++b) {
+                for (int k = 0; k < D; ++k) {
+                    double v = ((b >> k) & 1) ? 1.0 : -1.0;
+                    for (int l = 0; l < D; ++l)
+                        if (l != k) v *= ((b >> l) & 1) ? xi[l] : 1.0 - xi[l];
+                    gr[b][k] = v;
+                }
+                double v = 1.0;
+                for (int k = 0; k < D; ++k) v *= ((b >> k) & 1) ? xi[k] : 1.0 - xi[k];
+                ph[b] = v;
+                for (int p = 0; p < D; ++p)
+                    for (int k = 0; k < D; ++k) J[p][k] += xb[b][p] * gr[b][k];
+            }
+            double det, Ji[3][3];
+            if (D == 2) {
+                det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+                Ji[0][0] = J[1][1] / det;  Ji[0][1] = -J[0][1] / det;
+                Ji[1][0] = -J[1][0] / det; Ji[1][1] = J[0][0] / det;
+            } else {
+                det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                      J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+                Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+                Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+                Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+                Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+                Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+                Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+                Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+                Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+            }
+            if (!(det > 0.0)) atomicOr(err, 1);
+            const double wd = w * det;
+            for (int b = 0; b < NV; ++b) {
+                double gp[D];
+                for (int p = 0; p < D; ++p) {
+                    double s = 0.0;
+                    for (int k = 0; k < D; ++k) s += Ji[k][p] * gr[b][k];
+                    gp[p] = s;
+                }
+                mloc[b] += wd * (ph[a] * ph[b]);
+                for (int p = 0; p < D; ++p) cloc[b][p] += wd * ph[a] * gp[p];
+            }
+        }
+        for (int b = 0; b < NV; ++b) {
+            int kk = 0;
+            for (int k = 0; k < L; ++k)
+                if (P.scol[ENTRY(k)] == vx[b]) kk = k;
+            const int64_t e = ENTRY(kk);
+            P.mij[e] += mloc[b];
+            P.c0[e] += cloc[b][0];
+            P.c1[e] += cloc[b][1];
+            if (D == 3) P.c2[e] += cloc[b][D - 1];
+        }
+    }
+}
+
+// m_i = sum_j m_ij (ascending columns), lambda_i = 1/(card I(i) - 1)
+__global__ void __launch_bounds__(kBlock) k_lumped(StageArgs P)
+{
+    ROW_SETUP(P)
+    double s = 0.0;
+    for (int k = 0; k < L; ++k) s += P.mij[ENTRY(k)];
+    P.mi[i] = s;
+    P.lam[i] = 1.0 / double(L - 1);
+}
+
+// ------------------------------------------------------------ helpers
+__global__ void k_begin(StageArgs P, int clear_status)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (clear_status) *P.status = 0;
+        *P.taumin = 0x7FF0000000000000ull;  // +inf
+    }
+}
+
+// mode 1 (stage 1 of a step): tau = dt if given (error if dt exceeds the
+// bound) else cfl * bound; mode 2: tau = dt, warn if it exceeds the bound;
+// mode 0 (stages 2, 3): warn if the held tau exceeds this stage's bound.
+__global__ void k_tau(StageArgs P, double dt_in, int mode)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double bound = __longlong_as_double((long long)*P.taumin);
+    *P.bound = bound;
+    if (mode == 1) {
+        if (dt_in > 0.0 && dt_in > bound) atomicOr(P.status, kErrDt);
+        *P.tau = dt_in > 0.0 ? dt_in : P.cfl * bound;
+    } else if (mode == 2) {
+        *P.tau = dt_in;
+        if (dt_in > bound) atomicOr(P.status, kWarnCfl);
+    } else {
+        if (*P.tau > bound) atomicOr(P.status, kWarnCfl);
+    }
+}
+
+// ------------------------------------------------------------- k_node
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_node(StageArgs P, const double *__restrict__ U,
+                                                 int check)
+{
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= P.n) return;
+    if (failed(P)) return;
+    constexpr int NC = D + 2;
+    double u[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) u[k] = U[i * NC + k];
+    const double g = P.gamma;
+    const double eps = internal_energy<D>(u);
+    const double p = pressure<D>(u, g);
+    const double c = speed_of_sound<D>(u, g);
+    const double er = harten_entropy<D>(u, g) / u[0];
+    const double phi = specific_entropy<D>(u, g);
+    double *A = P.packA + i * kPack;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) A[k] = u[k];
+    A[NC + 0] = p;
+    A[NC + 1] = c;
+    A[NC + 2] = er;
+#pragma unroll
+    for (int k = 0; k < D; ++k) A[NC + 3 + k] = u[1 + k] / u[0];
+    A[NC + 3 + D] = phi;
+    if (check) {
+        bool ok = u[0] > 0.0 && eps > 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) ok = ok && isfinite(u[k]);
+        if (!ok) atomicOr(P.status, kErrState);
+    }
+}
+
+template <int D>
+struct NodeA {
+    double U[D + 2];
+    double p, c, er, v[D], phi;
+};
+
+template <int D>
+__device__ __forceinline__ void load_a(const double *__restrict__ A, NodeA<D> &o)
+{
+    constexpr int NC = D + 2;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) o.U[k] = A[k];
+    o.p = A[NC];
+    o.c = A[NC + 1];
+    o.er = A[NC + 2];
+#pragma unroll
+    for (int k = 0; k < D; ++k) o.v[k] = A[NC + 3 + k];
+    o.phi = A[NC + 3 + D];
+}
+
+// ------------------------------------------------------------- k_visc
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_visc(StageArgs P, int with_alpha)
+{
+    ROW_SETUP(P)
+    if (failed(P)) return;
+    constexpr int NC = D + 2;
+    const double g = P.gamma;
+    NodeA<D> Ai;
+    load_a<D>(P.packA + int64_t(i) * kPack, Ai);
+    double Fi[NC][D];
+    flux<D>(Ai.U, Ai.v, Ai.p, Fi);
+    double dsum = 0.0, a = 0.0;
+    double b[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) b[r] = 0.0;
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = ENTRY(k);
+        const int j = P.scol[e];
+        NodeA<D> Aj;
+        load_a<D>(P.packA + int64_t(j) * kPack, Aj);
+        double c[D];
+        c[0] = P.c0[e];
+        c[1] = P.c1[e];
+        if (D == 3) c[D - 1] = P.c2[e];
+        if (j != i) {
+            const int64_t t = P.stpos[e];
+            double ct[D];
+            ct[0] = P.c0[t];
+            ct[1] = P.c1[t];
+            if (D == 3) ct[D - 1] = P.c2[t];
+            double aij = 0.0, aji = 0.0;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                aij += c[q] * c[q];
+                aji += ct[q] * ct[q];
+            }
+            aij = sqrt(aij);
+            aji = sqrt(aji);
+            double t1 = 0.0, t2 = 0.0;
+            if (aij > 0.0) {
+                const double inv = 1.0 / aij;
+                double nn[D];
+#pragma unroll
+                for (int q = 0; q < D; ++q) nn[q] = c[q] * inv;
+                t1 = lambda_max<D>(nn, Ai.U, Ai.p, Ai.c, Aj.U, Aj.p, Aj.c, g) * aij;
+            }
+            if (aji > 0.0) {
+                const double inv = 1.0 / aji;
+                double nn[D];
+#pragma unroll
+                for (int q = 0; q < D; ++q) nn[q] = ct[q] * inv;
+                t2 = lambda_max<D>(nn, Aj.U, Aj.p, Aj.c, Ai.U, Ai.p, Ai.c, g) * aji;
+            }
+            const double dd = t1 > t2 ? t1 : t2;
+            P.d[e] = dd;
+            dsum += dd;
+        }
+        if (with_alpha) {
+            double mc = 0.0;
+#pragma unroll
+            for (int q = 0; q < D; ++q) mc += Aj.U[1 + q] * c[q];
+            a += (Aj.er - Ai.er) * mc;
+            double Fj[NC][D], fd[NC];
+            flux<D>(Aj.U, Aj.v, Aj.p, Fj);
+            flux_diff_dot<D>(Fi, Fj, c, fd);
+#pragma unroll
+            for (int r = 0; r < NC; ++r) b[r] += fd[r];
+        }
+    }
+    const double dii = -dsum;
+    P.d[ENTRY(P.diag_k[r_])] = dii;
+    const double ti = P.mi[i] / (-2.0 * dii);
+    P.taui[i] = ti;
+    atomicMin(P.taumin, (unsigned long long)__double_as_longlong(ti));
+    if (with_alpha) {
+        double etap[NC];
+        harten_entropy_derivative<D>(Ai.U, g, etap);
+        double etab = 0.0;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) etab += etap[r] * b[r];
+        const double N = fabs(a - etab + Ai.er * b[0]);
+        double Dn = fabs(a);
+#pragma unroll
+        for (int r = 0; r < NC; ++r) Dn += fabs(etap[r] - (r == 0 ? Ai.er : 0.0)) * fabs(b[r]);
+        P.alpha[i] = Dn > 0.0 ? N / Dn : 0.0;
+    }
+}
+
+// -------------------------------------------------------------- k_low
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
+{
+    ROW_SETUP(P)
+    if (failed(P)) return;
+    constexpr int NC = D + 2;
+    NodeA<D> Ai;
+    load_a<D>(P.packA + int64_t(i) * kPack, Ai);
+    const double alpha_i = P.alpha[i];
+    const double tau = *P.tau;
+    double Fi[NC][D];
+    flux<D>(Ai.U, Ai.v, Ai.p, Fi);
+    double R[NC], Lw[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) { R[r] = 0.0; Lw[r] = 0.0; }
+    double rho_min = Ai.U[0], rho_max = Ai.U[0], phi_min = Ai.phi;
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = ENTRY(k);
+        const int j = P.scol[e];
+        if (j == i) continue;
+        NodeA<D> Aj;
+        load_a<D>(P.packA + int64_t(j) * kPack, Aj);
+        const double alpha_j = P.alpha[j];
+        double c[D];
+        c[0] = P.c0[e];
+        c[1] = P.c1[e];
+        if (D == 3) c[D - 1] = P.c2[e];
+        const double dL = P.d[e];
+        const double dH = dL * (alpha_i + alpha_j) / 2.0;
+        double Fj[NC][D], fd[NC];
+        flux<D>(Aj.U, Aj.v, Aj.p, Fj);
+        flux_diff_dot<D>(Fi, Fj, c, fd);
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            R[r] += -fd[r] + dH * (Aj.U[r] - Ai.U[r]);
+            Lw[r] += -fd[r] + dL * (Aj.U[r] - Ai.U[r]);
+        }
+        double rbar = 0.5 * (Ai.U[0] + Aj.U[0]);
+        if (dL > 0.0) rbar -= fd[0] / (2.0 * dL);
+        if (rbar < rho_min) rho_min = rbar;
+        if (rbar > rho_max) rho_max = rbar;
+        if (Aj.phi < phi_min) phi_min = Aj.phi;
+    }
+    const double mi = P.mi[i];
+    double *B = P.packB + int64_t(i) * kPack;
+    double *W = P.rowB + int64_t(i) * kRowB;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        B[r] = Ai.U[r];
+        B[NC + r] = R[r];
+        W[r] = Ai.U[r] + tau / mi * Lw[r];
+    }
+    B[2 * NC] = alpha_i;
+    B[2 * NC + 1] = mi;
+    W[NC + 0] = rho_min;
+    W[NC + 1] = rho_max;
+    W[NC + 2] = phi_min;
+}
+
+template <int D>
+struct NodeB {
+    double U[D + 2], R[D + 2], alpha, m;
+};
+
+template <int D>
+__device__ __forceinline__ void load_b(const double *__restrict__ B, NodeB<D> &o)
+{
+    constexpr int NC = D + 2;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        o.U[k] = B[k];
+        o.R[k] = B[NC + k];
+    }
+    o.alpha = B[2 * NC];
+    o.m = B[2 * NC + 1];
+}
+
+// eq. def-p: P_ij = tau/(lambda_i m_i) (b_ij R_j - b_ji R_i + (d^H - d^L)(U_j - U_i)),
+// b_ij = -m_ij/m_j, b_ji = -m_ij/m_i (j != i)
+template <int D>
+__device__ __forceinline__ void direction(const NodeB<D> &Bi, const NodeB<D> &Bj,
+                                          double coef, double dL, double mij,
+                                          double *Pd)
+{
+    const double dH = dL * (Bi.alpha + Bj.alpha) / 2.0;
+    const double bij = -mij / Bj.m;
+    const double bji = -mij / Bi.m;
+#pragma unroll
+    for (int r = 0; r < D + 2; ++r)
+        Pd[r] = coef * (bij * Bj.R[r] - bji * Bi.R[r] + (dH - dL) * (Bj.U[r] - Bi.U[r]));
+}
+
+// ------------------------------------------------------------- k_lim1
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_lim1(StageArgs P)
+{
+    ROW_SETUP(P)
+    if (failed(P)) return;
+    constexpr int NC = D + 2;
+    NodeB<D> Bi;
+    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
+    const double *W = P.rowB + int64_t(i) * kRowB;
+    double UL[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) UL[r] = W[r];
+    const double rmin = W[NC], rmax = W[NC + 1], pmin = W[NC + 2];
+    const double tau = *P.tau;
+    const double coef = tau / (P.lam[i] * Bi.m);
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = ENTRY(k);
+        const int j = P.scol[e];
+        if (j == i) { P.l1[e] = 1.0; continue; }
+        NodeB<D> Bj;
+        load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+        double Pd[NC];
+        direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
+        P.l1[e] = limiter<D>(UL, Pd, rmin, rmax, pmin, P.gamma, P.newton_max, P.tol);
+    }
+}
+
+// ------------------------------------------------------------ k_pass1
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_pass1(StageArgs P)
+{
+    ROW_SETUP(P)
+    if (failed(P)) return;
+    constexpr int NC = D + 2;
+    NodeB<D> Bi;
+    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
+    const double *W = P.rowB + int64_t(i) * kRowB;
+    double V[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) V[r] = W[r];
+    const double rmin = W[NC], rmax = W[NC + 1], pmin = W[NC + 2];
+    const double tau = *P.tau;
+    const double lam = P.lam[i];
+    const double coef = tau / (lam * Bi.m);
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = ENTRY(k);
+        const int j = P.scol[e];
+        if (j == i) continue;
+        const double lij = P.l1[e], lji = P.l1[P.stpos[e]];
+        const double l = lij < lji ? lij : lji;
+        NodeB<D> Bj;
+        load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+        double Pd[NC];
+        direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
+#pragma unroll
+        for (int r = 0; r < NC; ++r) V[r] += lam * l * Pd[r];
+    }
+    double *Up = P.upass + int64_t(i) * kRowU;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) Up[r] = V[r];
+    if (P.passes < 2) return;
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = ENTRY(k);
+        const int j = P.scol[e];
+        if (j == i) { P.l2[e] = 1.0; continue; }
+        const double lij = P.l1[e], lji = P.l1[P.stpos[e]];
+        const double l = lij < lji ? lij : lji;
+        NodeB<D> Bj;
+        load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+        double Pd[NC];
+        direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
+#pragma unroll
+        for (int r = 0; r < NC; ++r) Pd[r] = (1.0 - l) * Pd[r];
+        P.l2[e] = limiter<D>(V, Pd, rmin, rmax, pmin, P.gamma, P.newton_max, P.tol);
+    }
+}
+
+// ------------------------------------------------------------ k_pass2
+// mode 0: out = E(U); 1: out = E (stage 1); 2: out = U0 + 1/4 (E - U0);
+// 3: out = U0 + 2/3 (E - U0); modes 1-3 keep held nodes at U0.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0, double *out,
+                                                  int mode)
+{
+    ROW_SETUP(P)
+    if (failed(P)) return;
+    constexpr int NC = D + 2;
+    NodeB<D> Bi;
+    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
+    double V[NC];
+    const double *Up = P.upass + int64_t(i) * kRowU;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) V[r] = Up[r];
+    if (P.passes >= 2) {
+        const double tau = *P.tau;
+        const double lam = P.lam[i];
+        const double coef = tau / (lam * Bi.m);
+        for (int k = 0; k < L; ++k) {
+            const int64_t e = ENTRY(k);
+            const int j = P.scol[e];
+            if (j == i) continue;
+            const int64_t t = P.stpos[e];
+            const double a1 = P.l1[e], b1 = P.l1[t];
+            const double s1 = a1 < b1 ? a1 : b1;
+            const double a2 = P.l2[e], b2 = P.l2[t];
+            const double s2 = a2 < b2 ? a2 : b2;
+            NodeB<D> Bj;
+            load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+            double Pd[NC];
+            direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
+#pragma unroll
+            for (int r = 0; r < NC; ++r) {
+                const double P2 = (1.0 - s1) * Pd[r];
+                V[r] += lam * s2 * P2;
+            }
+        }
+    }
+    double *o = out + int64_t(i) * NC;
+    if (mode == 0) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) o[r] = V[r];
+        return;
+    }
+    const double *u0 = U0 + int64_t(i) * NC;
+    double w[NC];
+    if (P.hold && P.hold[i]) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) w[r] = u0[r];
+    } else if (mode == 1) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) w[r] = V[r];
+    } else if (mode == 2) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) w[r] = u0[r] + 0.25 * (V[r] - u0[r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) w[r] = u0[r] + (2.0 / 3.0) * (V[r] - u0[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < NC; ++r) o[r] = w[r];
+}
+
+// ------------------------------------------------------- device math
+__global__ void k_math(int kind, int64_t n, const double *x, const double *y, double *out)
+{
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (kind == 0) out[i] = fpow(x[i], y[i]);
+    else if (kind == 1) out[i] = sqrt(x[i]);
+    else out[i] = x[i] / y[i];
+}
+
+// ------------------------------------------------------------ launches
+static inline int grid_rows(const StageArgs &P) { return P.per * kXcd; }
+static inline int grid_nodes(int64_t n) { return int((n + kBlock - 1) / kBlock); }
+
+void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
+                     const int32_t *cells, const int64_t *nc_ptr,
+                     const int32_t *nc_list, const double gx[3], int *err)
+{
+    if (P.dim == 2)
+        hipLaunchKernelGGL(k_matrices<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P,
+                           coords, cells, nc_ptr, nc_list, gx[0], gx[1], gx[2], err);
+    else
+        hipLaunchKernelGGL(k_matrices<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P,
+                           coords, cells, nc_ptr, nc_list, gx[0], gx[1], gx[2], err);
+    hipLaunchKernelGGL(k_lumped, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+}
+
+void launch_begin(const StageArgs &P, hipStream_t st, int clear_status)
+{
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, P, clear_status);
+}
+
+void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode)
+{
+    hipLaunchKernelGGL(k_tau, dim3(1), dim3(64), 0, st, P, dt_in, mode);
+}
+
+void launch_node(const StageArgs &P, hipStream_t st, const double *U, int check)
+{
+    if (P.dim == 2)
+        hipLaunchKernelGGL(k_node<2>, dim3(grid_nodes(P.n)), dim3(kBlock), 0, st, P, U, check);
+    else
+        hipLaunchKernelGGL(k_node<3>, dim3(grid_nodes(P.n)), dim3(kBlock), 0, st, P, U, check);
+}
+
+void launch_visc(const StageArgs &P, hipStream_t st, int with_alpha)
+{
+    if (P.dim == 2)
+        hipLaunchKernelGGL(k_visc<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P, with_alpha);
+    else
+        hipLaunchKernelGGL(k_visc<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P, with_alpha);
+}
+
+void launch_low(const StageArgs &P, hipStream_t st)
+{
+    if (P.dim == 2)
+        hipLaunchKernelGGL(k_low<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    else
+        hipLaunchKernelGGL(k_low<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+}
+
+void launch_lim1(const StageArgs &P, hipStream_t st)
+{
+    if (P.dim == 2)
+        hipLaunchKernelGGL(k_lim1<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    else
+        hipLaunchKernelGGL(k_lim1<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+}
+
+void launch_pass1(const StageArgs &P, hipStream_t st)
+{
+    if (P.dim == 2)
+        hipLaunchKernelGGL(k_pass1<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    else
+        hipLaunchKernelGGL(k_pass1<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+}
+
+void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out,
+                  int mode)
+{
+    if (P.dim == 2)
+        hipLaunchKernelGGL(k_pass2<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P, U0, out, mode);
+    else
+        hipLaunchKernelGGL(k_pass2<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P, U0, out, mode);
+}
+
+void launch_math(hipStream_t st, int kind, int64_t n, const double *x, const double *y,
+                 double *out)
+{
+    hipLaunchKernelGGL(k_math, dim3(grid_nodes(n)), dim3(kBlock), 0, st, kind, n, x, y, out);
+}
+
+}  // namespace idp

@@ -1,0 +1,156 @@
+"""Python face of the library: a Solver over one Q1 mesh.
+
+State tensors are torch.float64 on the current HIP device, [n_nodes, dim+2]
+contiguous, in the caller's node order; calls are ordered on the torch
+stream that was current when the Solver was created.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import capi
+
+
+def _require_torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the IDP library needs a HIP device (none visible)")
+    return torch
+
+
+class Solver:
+    def __init__(self, mesh=None, *, dim=None, coords=None, cells=None,
+                 dirichlet=None, gamma=1.4, cfl=0.5, passes=2, newton_max=2,
+                 newton_tol=1e-10, asynchronous=False, stream=None):
+        torch = _require_torch_gpu()
+        if mesh is not None:
+            dim, coords, cells = mesh.dim, mesh.coords, mesh.cells
+            if dirichlet is None:
+                dirichlet = mesh.boundary
+        self.dim = int(dim)
+        self.nc = self.dim + 2
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        self.n = int(coords.shape[0])
+        L = capi.lib()
+        p = capi.idp_params()
+        capi.check("idp_default_params", L.idp_default_params(C.byref(p), self.dim))
+        p.gamma, p.cfl = float(gamma), float(cfl)
+        p.limiter_passes, p.newton_max_iter = int(passes), int(newton_max)
+        p.newton_tol = float(newton_tol)
+        p.flags = capi.IDP_FLAG_ASYNC if asynchronous else 0
+        self.params = p
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        hd = None
+        if dirichlet is not None:
+            hd = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        h = C.c_void_p()
+        rc = L.idp_create(C.byref(h), C.byref(p), self.n,
+                          coords.ctypes.data_as(capi._dp), int(cells.shape[0]),
+                          cells.ctypes.data_as(capi._i64p),
+                          hd.ctypes.data_as(capi._u8p) if hd is not None else None,
+                          C.c_void_p(self._stream.cuda_stream))
+        capi.check("idp_create", rc)
+        self._h = h
+        nn, nz, nb = C.c_int64(), C.c_int64(), C.c_size_t()
+        capi.check("idp_info", L.idp_info(h, C.byref(nn), C.byref(nz), C.byref(nb)))
+        self.nnz = int(nz.value)
+        self.device_bytes = int(nb.value)
+
+    # ---------------------------------------------------------------- life
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            capi.lib().idp_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _u(self, U):
+        torch = _require_torch_gpu()
+        if not (isinstance(U, torch.Tensor) and U.is_cuda and U.dtype == torch.float64
+                and U.is_contiguous() and tuple(U.shape) == (self.n, self.nc)):
+            raise ValueError(f"state must be a contiguous float64 device tensor "
+                             f"of shape ({self.n}, {self.nc})")
+        return C.c_void_p(U.data_ptr())
+
+    # ------------------------------------------------------------- calls
+    def max_dt(self, U) -> float:
+        out = C.c_double()
+        capi.check("idp_max_dt", capi.lib().idp_max_dt(self._h, self._u(U), C.byref(out)))
+        return out.value
+
+    def step(self, U, dt: float = 0.0):
+        """One SSP-RK3 step in place; returns (dt_used, status)."""
+        used = C.c_double(0.0)
+        rc = capi.lib().idp_step(self._h, self._u(U), float(dt), C.byref(used))
+        capi.check("idp_step", rc)
+        return used.value, rc
+
+    def euler_stage(self, U, tau: float, out=None):
+        """E(U) with step tau into out (allocated if None); returns (out, status)."""
+        torch = _require_torch_gpu()
+        if out is None:
+            out = torch.empty_like(U)
+        rc = capi.lib().idp_euler_stage(self._h, self._u(U), float(tau), self._u(out))
+        capi.check("idp_euler_stage", rc)
+        return out, rc
+
+    def status(self) -> int:
+        return capi.check("idp_get_status", capi.lib().idp_get_status(self._h))
+
+    # ----------------------------------------------------------- exports
+    def matrices(self):
+        n, z, d = self.n, self.nnz, self.dim
+        rp = np.empty(n + 1, np.int64)
+        col = np.empty(z, np.int32)
+        mi = np.empty(n)
+        mij = np.empty(z)
+        cij = np.empty((z, d))
+        capi.check("idp_export_matrices", capi.lib().idp_export_matrices(
+            self._h, rp.ctypes.data_as(capi._i64p), col.ctypes.data_as(capi._i32p),
+            mi.ctypes.data_as(capi._dp), mij.ctypes.data_as(capi._dp),
+            cij.ctypes.data_as(capi._dp)))
+        return {"row_ptr": rp, "col": col, "m_i": mi, "m_ij": mij, "c_ij": cij}
+
+    _DBG_SHAPE = {
+        capi.IDP_DBG_D: "z", capi.IDP_DBG_L1: "z", capi.IDP_DBG_L2: "z",
+        capi.IDP_DBG_ALPHA: "n", capi.IDP_DBG_TAUI: "n", capi.IDP_DBG_R: "nc",
+        capi.IDP_DBG_UL: "nc", capi.IDP_DBG_UPASS: "nc", capi.IDP_DBG_BOUNDS: "n3",
+    }
+
+    def debug(self, what: int) -> np.ndarray:
+        kind = self._DBG_SHAPE[what]
+        shape = {"z": (self.nnz,), "n": (self.n,), "nc": (self.n, self.nc),
+                 "n3": (self.n, 3)}[kind]
+        out = np.empty(shape)
+        capi.check("idp_debug_export", capi.lib().idp_debug_export(
+            self._h, int(what), out.ctypes.data_as(capi._dp)))
+        return out
+
+    # ------------------------------------------------------------ timing
+    def set_timing(self, on: bool):
+        capi.check("idp_set_timing", capi.lib().idp_set_timing(self._h, int(bool(on))))
+
+    def kernel_times(self):
+        names = (C.c_char_p * 32)()
+        ms = np.zeros(32)
+        cnt = np.zeros(32, np.int64)
+        k = capi.check("idp_kernel_times", capi.lib().idp_kernel_times(
+            self._h, 32, names, ms.ctypes.data_as(capi._dp), cnt.ctypes.data_as(capi._i64p)))
+        return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
+
+    def device_math(self, kind: int, x, y=None):
+        torch = _require_torch_gpu()
+        out = torch.empty_like(x)
+        yp = C.c_void_p(y.data_ptr()) if y is not None else None
+        capi.check("idp_device_math", capi.lib().idp_device_math(
+            self._h, int(kind), int(x.numel()), C.c_void_p(x.data_ptr()), yp,
+            C.c_void_p(out.data_ptr())))
+        return out

@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every function include/idp.h declares;
+host-side argument checks answer without a GPU (no device calls here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2007_00094_amd import capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "idp.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(idp_\w+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("idp_create", "idp_step", "idp_max_dt", "idp_destroy",
+                     "idp_export_matrices", "idp_debug_export"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = capi.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+        assert name in capi.SIGNATURES, name
+
+
+def test_strerror_and_defaults_on_host():
+    L = capi.lib()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
+        assert L.idp_strerror(code)
+    p = capi.idp_params()
+    assert L.idp_default_params(C.byref(p), 3) == 0
+    assert (p.dim, p.gamma, p.cfl, p.limiter_passes, p.newton_max_iter) == (3, 1.4, 0.5, 2, 2)
+    assert p.newton_tol == 1e-10 and p.relax_bounds == 0 and p.flags == 0
+    assert L.idp_default_params(C.byref(p), 4) == capi.IDP_EINVAL
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("dim", 4, capi.IDP_EINVAL), ("cfl", 1.5, capi.IDP_EINVAL),
+    ("gamma", 1.0, capi.IDP_EINVAL), ("limiter_passes", 3, capi.IDP_EINVAL),
+    ("relax_bounds", 1, capi.IDP_ENOTSUP)])
+def test_create_rejects_bad_params_before_any_device_call(field, value, code):
+    L = capi.lib()
+    p = capi.idp_params()
+    L.idp_default_params(C.byref(p), 2)
+    setattr(p, field, value)
+    h = C.c_void_p()
+    xy = (C.c_double * 8)()
+    cells = (C.c_int64 * 4)(0, 1, 2, 3)
+    assert L.idp_create(C.byref(h), C.byref(p), 4, xy, 1, cells, None, None) == code
+    assert L.idp_create(None, C.byref(p), 4, xy, 1, cells, None, None) == capi.IDP_EINVAL
+    assert L.idp_step(None, None, 0.0, None) == capi.IDP_EINVAL
+    assert L.idp_max_dt(None, None, None) == capi.IDP_EINVAL
