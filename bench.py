@@ -1,0 +1,207 @@
+"""Throughput benchmark: SSP-RK3 steps of the IDP Q1 Euler scheme on one GPU.
+
+Default workload: 3D Q1 hex grid 257^3 nodes (16,974,593 nodes), interior
+nodes jittered by up to 0.2 h, Morton node order, uniform Mach 3 flow
+(rho 1.4, p 1, u 3 e_x) with a seeded density blob field of amplitude 0.2,
+boundary held, FP64.  A step is three forward-Euler stages (every sweep of
+the method); the metric is node updates per second per stage.
+
+Prints one JSON line (stdout); progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+KERNEL_SOURCES = ["paper_2007_00094_amd/csrc/idp_kernels.hip",
+                  "paper_2007_00094_amd/csrc/idp_device.h",
+                  "paper_2007_00094_amd/csrc/kernels.h"]
+COUNTERS = os.path.join(ROOT, "profiles", "counters_mach3_257_morton.md")
+FP64_VECTOR_PEAK = 78.6e12   # MI355X FP64 vector, flop/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(dim, n, nnz):
+    """Compulsory bytes per launch of each kernel: every array the kernel
+    reads or writes counted once (neighbour gathers and transposed reads
+    assumed cached), from the data layout of the library."""
+    nc = dim + 2
+    pack = 8 * (2 * dim + 6)        # node pack A / B: used doubles
+    packb = 8 * (2 * nc + 2)
+    rowb = 8 * (nc + 3)
+    cb = 8 * dim
+    return {
+        "node_pack": n * (8 * nc + pack),
+        "sweep_viscosity": nnz * (4 + 4 + cb + 8) + n * (pack + 8 + 8 + 8),
+        "sweep_low_order": nnz * (4 + cb + 8) + n * (pack + 8 + 8 + packb + rowb),
+        "sweep_limiter1": nnz * (4 + 8 + 8 + 8) + n * (packb + rowb + 8),
+        "sweep_pass1": nnz * (4 + 4 + 8 + 8 + 8 + 8) + n * (packb + rowb + 8 + 8 * nc),
+        "sweep_pass2": nnz * (4 + 4 + 8 + 8 + 8 + 8) + n * (packb + 8 * nc + 8 + 3 * 8 * nc + 1),
+    }
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (scaled FETCH_SIZE + WRITE_SIZE), or None if the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    text = open(COUNTERS).read().split()
+    try:
+        if text[text.index("source_hash:") + 1] != h.hexdigest()[:16]:
+            return None
+    except ValueError:
+        return None
+    for i, w in enumerate(text):
+        if w == "traffic_bytes_per_launch:" and text[i + 1] == kernel:
+            return float(text[i + 2])
+    return None
+
+
+def cpu_baseline(mesh, U0, radius, steps):
+    """The oracle, as it stands, on a patch of the same mesh and state:
+    nodes within graph distance ``radius`` of the mesh centre."""
+    import oracle
+    from paper_2007_00094_amd import inputs
+    centre = int(np.argmin(np.sum((mesh.coords - 0.5) ** 2, axis=1)))
+    sub, nodes, _ = inputs.extract_patch(mesh, [centre], radius)
+    threads = oracle.set_threads(0)
+    o = oracle.Oracle(sub, dirichlet=sub.boundary)
+    U = U0[nodes].copy()
+    dt = o.max_dt(U)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        U, _, _ = o.step(U, dt=dt)
+    t = time.perf_counter() - t0
+    return {"value": sub.n_nodes * 3 * steps / t, "unit": "node-updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 step(s) on a {sub.n_nodes}-node patch "
+                      f"(graph radius {radius} around the centre) of the same mesh "
+                      f"and state, fixed dt, {threads} OpenMP threads, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=257, help="nodes per side")
+    ap.add_argument("--order", default="morton", choices=["morton", "random", "lex"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-radius", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of GIB GiB (counter calibration)")
+    args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = int(args.copy_calibration * 2**30 // 8)
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n}))
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2007_00094_amd import inputs
+    from paper_2007_00094_amd.solver import Solver
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    t = time.perf_counter()
+    mesh, U0 = inputs.workload("mach3_3d", n=args.n, order=args.order)
+    log(f"mesh {mesh.n_nodes} nodes, {mesh.n_cells} cells in {time.perf_counter() - t:.1f} s")
+    t = time.perf_counter()
+    s = Solver(mesh, asynchronous=True)
+    torch.cuda.synchronize()
+    log(f"solver created: nnz {s.nnz}, {s.device_bytes / 2**30:.1f} GiB device, "
+        f"{time.perf_counter() - t:.1f} s")
+    U = torch.tensor(U0, device="cuda")
+    for _ in range(args.warmup):
+        s.step(U)
+    torch.cuda.synchronize()
+    assert s.status() in (0, 1), "warm-up steps failed"
+    log(f"{args.warmup} warm-up steps done")
+
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step(U)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = s.status()
+    assert st in (0, 1), f"timed steps failed: {st}"
+    times = s.kernel_times()
+    s.set_timing(False)
+    log(f"{args.steps} timed steps in {elapsed:.3f} s")
+    for k, (ms, cnt) in times.items():
+        if cnt:
+            log(f"  {k:18s} {ms / cnt:9.3f} ms/launch x {cnt}")
+
+    stages = 3 * args.steps
+    value = mesh.n_nodes * stages / elapsed
+    algo = algorithmic_bytes(mesh.dim, mesh.n_nodes, s.nnz)
+    dom = max(algo, key=lambda k: times[k][0])
+    avg_s = times[dom][0] / times[dom][1] / 1e3
+    achieved = algo[dom] / avg_s / 1e9
+    kernels = {k: {"ms_per_launch": round(times[k][0] / times[k][1], 4),
+                   "GB_per_s": round(algo[k] / (times[k][0] / times[k][1] / 1e3) / 1e9, 1)}
+               for k in algo if times[k][1]}
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "algorithmic_bytes_per_launch": algo[dom]}
+    if args.n == 257 and args.order == "morton":
+        roofline["traffic"] = measured_traffic(dom)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a patch)")
+        cpu = cpu_baseline(mesh, U0, args.cpu_radius, args.cpu_steps)
+    out = {
+        "metric": "Q1 node-updates/s per RK stage FP64; HBM GB/s; adjoint/forward time ratio",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"mach3_3d_{args.n}^3_{args.order}",
+                   "nodes": mesh.n_nodes, "nnz": s.nnz, "stages": stages,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -246,6 +246,9 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     TRY(dalloc(c, &P.c0, S));
     TRY(dalloc(c, &P.c1, S));
     if (dim == 3) TRY(dalloc(c, &P.c2, S));
+    TRY(dalloc(c, &P.ct0, S));
+    TRY(dalloc(c, &P.ct1, S));
+    if (dim == 3) TRY(dalloc(c, &P.ct2, S));
     TRY(dalloc(c, &P.mij, S));
     TRY(dalloc(c, &P.d, S));
     TRY(dalloc(c, &P.l1, S));

@@ -167,6 +167,20 @@ __global__ void __launch_bounds__(kBlock) k_lumped(StageArgs P)
     P.lam[i] = 1.0 / double(L - 1);
 }
 
+// c_ji stored at the position of c_ij (coalesced reads of the transpose)
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_transpose_c(StageArgs P)
+{
+    ROW_SETUP(P)
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = ENTRY(k);
+        const int64_t t = P.stpos[e];
+        P.ct0[e] = P.c0[t];
+        P.ct1[e] = P.c1[t];
+        if (D == 3) P.ct2[e] = P.c2[t];
+    }
+}
+
 // ------------------------------------------------------------ helpers
 __global__ void k_begin(StageArgs P, int clear_status)
 {
@@ -276,11 +290,10 @@ __global__ void __launch_bounds__(kBlock) k_visc(StageArgs P, int with_alpha)
         c[1] = P.c1[e];
         if (D == 3) c[D - 1] = P.c2[e];
         if (j != i) {
-            const int64_t t = P.stpos[e];
-            double ct[D];
-            ct[0] = P.c0[t];
-            ct[1] = P.c1[t];
-            if (D == 3) ct[D - 1] = P.c2[t];
+            double ct[D];   // c_ji, stored at the position of c_ij
+            ct[0] = P.ct0[e];
+            ct[1] = P.ct1[e];
+            if (D == 3) ct[D - 1] = P.ct2[e];
             double aij = 0.0, aji = 0.0;
 #pragma unroll
             for (int q = 0; q < D; ++q) {
@@ -600,6 +613,10 @@ void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
         hipLaunchKernelGGL(k_matrices<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P,
                            coords, cells, nc_ptr, nc_list, gx[0], gx[1], gx[2], err);
     hipLaunchKernelGGL(k_lumped, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    if (P.dim == 2)
+        hipLaunchKernelGGL(k_transpose_c<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    else
+        hipLaunchKernelGGL(k_transpose_c<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
 }
 
 void launch_begin(const StageArgs &P, hipStream_t st, int clear_status)

@@ -34,6 +34,7 @@ struct StageArgs {
     const int32_t *scol, *stpos;
     // matrices (SELL order); written by the precompute only
     double *c0, *c1, *c2, *mij;
+    double *ct0, *ct1, *ct2;    // c_ji at the position of c_ij
     double *mi, *lam;
     const uint8_t *hold;
     // per-stage work
