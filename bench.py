@@ -42,13 +42,18 @@ def algorithmic_bytes(dim, n, nnz):
     packb = 8 * (2 * nc + 2)
     rowb = 8 * (nc + 3)
     cb = 8 * dim
+    npairs = (nnz - n) // 2
     return {
         "node_pack": n * (8 * nc + pack),
-        "sweep_viscosity": nnz * (4 + 4 + cb + 8) + n * (pack + 8 + 8 + 8),
-        "sweep_low_order": nnz * (4 + cb + 8) + n * (pack + 8 + 8 + packb + rowb),
-        "sweep_limiter1": nnz * (4 + 8 + 8 + 8) + n * (packb + rowb + 8),
-        "sweep_pass1": nnz * (4 + 4 + 8 + 8 + 8 + 8) + n * (packb + rowb + 8 + 8 * nc),
-        "sweep_pass2": nnz * (4 + 4 + 8 + 8 + 8 + 8) + n * (packb + 8 * nc + 8 + 3 * 8 * nc + 1),
+        # per pair: 4 ids, c_ij and c_ji, d written twice
+        "pair_viscosity": npairs * (16 + 2 * cb + 16) + n * pack,
+        "row_diagonal": nnz * (4 + cb + 8) + n * (pack + 8 + 8 + 8),
+        "row_low_order": nnz * (4 + cb + 8) + n * (pack + 8 + 8 + packb + rowb),
+        # per pair: 4 ids, d, m_ij, s written twice
+        "pair_limiter1": npairs * (16 + 8 + 8 + 16) + n * (packb + rowb + 8),
+        "row_pass1": nnz * (4 + 8 + 8 + 8) + n * (packb + rowb + 8 + 8 * nc),
+        "pair_limiter2": npairs * (16 + 8 + 8 + 8 + 16) + n * (packb + rowb + 8 + 8 * nc),
+        "row_pass2": nnz * (4 + 8 + 8 + 8 + 8) + n * (packb + 8 * nc + 8 + 3 * 8 * nc + 1),
     }
 
 

@@ -131,7 +131,8 @@ int idp_export_matrices(const idp_ctx *ctx, int64_t *row_ptr, int32_t *col,
  *  IDP_DBG_ALPHA  alpha_i [n]          IDP_DBG_R      R_i [n][nc]
  *  IDP_DBG_UL     U^L_i [n][nc]        IDP_DBG_BOUNDS (rho_min, rho_max,
  *                                                      phi_min) [n][3]
- *  IDP_DBG_L1     l_ij pass 1 [nnz]    IDP_DBG_L2     l_ij pass 2 [nnz]
+ *  IDP_DBG_L1     min(l_ij, l_ji) of pass 1 [nnz]  (diagonal: 1)
+ *  IDP_DBG_L2     min(l_ij, l_ji) of pass 2 [nnz]  (diagonal: 1)
  *  IDP_DBG_UPASS  state after pass 1 [n][nc]
  *  IDP_DBG_TAUI   m_i/(-2 d_ii) [n]
  * Synchronises.                                                          */

@@ -150,6 +150,47 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
                 g.stpos[e] = int32_t(e);
         }
     }
+    // pairs: the entries (i, j) with j > i, slice by slice in SELL order
+    {
+        std::vector<int64_t> cnt(g.nslices + 1, 0);
+#pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < g.nslices; ++s) {
+            int64_t c = 0;
+            for (int k = 0; k < g.slice_w[s]; ++k)
+                for (int lane = 0; lane < kSellC; ++lane) {
+                    const int64_t r = s * kSellC + lane;
+                    const int32_t i = g.perm[r];
+                    if (i < 0 || k >= g.row_len[r]) continue;
+                    if (g.scol[g.slice_off[s] + int64_t(k) * kSellC + lane] > i) ++c;
+                }
+            cnt[s + 1] = c;
+        }
+        for (int64_t s = 0; s < g.nslices; ++s) cnt[s + 1] += cnt[s];
+        g.npairs = cnt[g.nslices];
+        if (2 * g.npairs + n != g.nnz) return IDP_EINVAL;  // stencil not symmetric
+        g.pair_e.resize(g.npairs);
+        g.pair_t.resize(g.npairs);
+        g.pair_i.resize(g.npairs);
+        g.pair_j.resize(g.npairs);
+#pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < g.nslices; ++s) {
+            int64_t p = cnt[s];
+            for (int k = 0; k < g.slice_w[s]; ++k)
+                for (int lane = 0; lane < kSellC; ++lane) {
+                    const int64_t r = s * kSellC + lane;
+                    const int32_t i = g.perm[r];
+                    if (i < 0 || k >= g.row_len[r]) continue;
+                    const int64_t e = g.slice_off[s] + int64_t(k) * kSellC + lane;
+                    const int32_t j = g.scol[e];
+                    if (j <= i) continue;
+                    g.pair_e[p] = int32_t(e);
+                    g.pair_t[p] = g.stpos[e];
+                    g.pair_i[p] = i;
+                    g.pair_j[p] = j;
+                    ++p;
+                }
+        }
+    }
     return IDP_OK;
 }
 

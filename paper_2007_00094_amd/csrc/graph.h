@@ -44,6 +44,11 @@ struct HostGraph {
     std::vector<int64_t> sell_of_csr;  // [nnz]
     std::vector<int32_t> scol;      // [sell_size] column node id (pad: own)
     std::vector<int32_t> stpos;     // [sell_size] SELL position of (j,i)
+
+    // unordered pairs {i, j}, i < j, in SELL order of the entry (i, j):
+    // SELL positions of (i,j) and (j,i) and the two nodes
+    int64_t npairs = 0;
+    std::vector<int32_t> pair_e, pair_t, pair_i, pair_j;
 };
 
 // Returns 0 or a negative idp error code (IDP_EINVAL for ids out of range,

@@ -15,10 +15,13 @@ static_assert(idp::kSellC == idp::kSlice, "SELL slice height = wavefront width")
 
 namespace {
 
-enum KernelId { K_BEGIN, K_NODE, K_VISC, K_TAU, K_LOW, K_LIM1, K_PASS1, K_PASS2, K_COUNT };
-const char *kKernelNames[K_COUNT] = {"begin", "node_pack", "sweep_viscosity", "tau",
-                                     "sweep_low_order", "sweep_limiter1", "sweep_pass1",
-                                     "sweep_pass2"};
+enum KernelId {
+    K_BEGIN, K_NODE, K_DPAIR, K_DIAG, K_TAU, K_LOW, K_LIM1P, K_PASS1A, K_LIM2P, K_PASS2,
+    K_COUNT
+};
+const char *kKernelNames[K_COUNT] = {"begin", "node_pack", "pair_viscosity", "row_diagonal",
+                                     "tau", "row_low_order", "pair_limiter1", "row_pass1",
+                                     "pair_limiter2", "row_pass2"};
 
 struct Pending {
     int id;
@@ -154,11 +157,13 @@ void stage(idp_ctx *c, const double *in, const double *U0, double *out, int mode
     hipStream_t st = c->stream;
     timed(c, K_BEGIN, [&] { idp::launch_begin(P, st, clear); });
     timed(c, K_NODE, [&] { idp::launch_node(P, st, in, check); });
-    timed(c, K_VISC, [&] { idp::launch_visc(P, st, 1); });
+    timed(c, K_DPAIR, [&] { idp::launch_dpair(P, st); });
+    timed(c, K_DIAG, [&] { idp::launch_diag(P, st, 1); });
     timed(c, K_TAU, [&] { idp::launch_tau(P, st, dt_in, tau_mode); });
     timed(c, K_LOW, [&] { idp::launch_low(P, st); });
-    timed(c, K_LIM1, [&] { idp::launch_lim1(P, st); });
-    timed(c, K_PASS1, [&] { idp::launch_pass1(P, st); });
+    timed(c, K_LIM1P, [&] { idp::launch_lim1p(P, st); });
+    timed(c, K_PASS1A, [&] { idp::launch_pass1a(P, st); });
+    if (P.passes >= 2) timed(c, K_LIM2P, [&] { idp::launch_lim2p(P, st); });
     timed(c, K_PASS2, [&] { idp::launch_pass2(P, st, U0, out, mode); });
 }
 
@@ -232,6 +237,7 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     P.passes = p.limiter_passes;
 
     int32_t *perm, *row_len, *diag_k, *scol, *stpos;
+    int32_t *pe, *pt, *pi, *pj;
     int64_t *slice_off;
     const int64_t S = g.sell_size;
     int e = IDP_OK;
@@ -243,6 +249,10 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     TRY(dalloc(c, &slice_off, g.nslices));
     TRY(dalloc(c, &scol, S));
     TRY(dalloc(c, &stpos, S));
+    TRY(dalloc(c, &pe, g.npairs));
+    TRY(dalloc(c, &pt, g.npairs));
+    TRY(dalloc(c, &pi, g.npairs));
+    TRY(dalloc(c, &pj, g.npairs));
     TRY(dalloc(c, &P.c0, S));
     TRY(dalloc(c, &P.c1, S));
     if (dim == 3) TRY(dalloc(c, &P.c2, S));
@@ -275,6 +285,12 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     P.slice_off = slice_off;
     P.scol = scol;
     P.stpos = stpos;
+    P.npairs = g.npairs;
+    P.pper = int(((g.npairs + idp::kBlock - 1) / idp::kBlock + idp::kXcd - 1) / idp::kXcd);
+    P.pair_e = pe;
+    P.pair_t = pt;
+    P.pair_i = pi;
+    P.pair_j = pj;
     P.taumin = &c->scal->taumin;
     P.tau = &c->scal->tau;
     P.bound = &c->scal->bound;
@@ -285,6 +301,10 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     HIPTRY(hipMemcpyAsync(slice_off, g.slice_off.data(), g.nslices * 8, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemcpyAsync(scol, g.scol.data(), S * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemcpyAsync(stpos, g.stpos.data(), S * 4, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(hipMemcpyAsync(pe, g.pair_e.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(hipMemcpyAsync(pt, g.pair_t.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(hipMemcpyAsync(pi, g.pair_i.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(hipMemcpyAsync(pj, g.pair_j.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemsetAsync(c->scal, 0, sizeof(Scalars), c->stream));
 
     // matrices on the device (temporary mesh arrays)
@@ -379,7 +399,8 @@ int idp_max_dt(idp_ctx *c, const double *U, double *dt_out)
     const idp::StageArgs &P = c->P;
     timed(c, K_BEGIN, [&] { idp::launch_begin(P, c->stream, 1); });
     timed(c, K_NODE, [&] { idp::launch_node(P, c->stream, U, 1); });
-    timed(c, K_VISC, [&] { idp::launch_visc(P, c->stream, 0); });
+    timed(c, K_DPAIR, [&] { idp::launch_dpair(P, c->stream); });
+    timed(c, K_DIAG, [&] { idp::launch_diag(P, c->stream, 0); });
     Scalars h{};
     int rc = read_scalars(c, &h);
     if (rc != IDP_OK) return rc;

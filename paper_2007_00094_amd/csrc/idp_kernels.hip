@@ -1,22 +1,25 @@
 // HIP kernels of the IDP Q1 Euler scheme (arXiv:2007.00094) for gfx950.
 //
-// One forward-Euler stage of Alg. 1 is five sweeps over the SELL-64 stencil
-// layout plus one node kernel:
+// One forward-Euler stage of Alg. 1 is a node kernel, four row sweeps over
+// the SELL-64 stencil layout and three sweeps over the unordered pairs:
 //   k_node    step 0   per node: p, c, eta/rho, v = m/rho, phi   (pack A)
-//   k_visc    steps 1-2 d_ij (both orientations, the larger), d_ii, tau_i,
-//                       indicator alpha_i (Section 3.8)
-//   k_low     step 3   R_i, U^L_i, bounds rho_min, rho_max, phi_min
-//   k_lim1    step 4   P_ij (eq. def-p, recomputed), l_ij pass 1 (Alg. 2)
-//   k_pass1   step 5   U_i += sum lambda_i min(l_ij,l_ji) P_ij; candidates
-//                       of pass 2 on the rescaled P
-//   k_pass2   step 6   final pass, then SSP-RK3 combination and boundary hold
-// One wavefront lane owns one stencil row (SELL slice of 64 rows) and sums
-// its columns in ascending order, sequentially, like the CPU oracle, so that
-// every row-level reduction has one writer and a fixed order.  Neighbour
-// data are gathered from node-major packs (128 bytes per node).  Blocks are
-// renumbered so that consecutive slices run on the same XCD (L2 locality of
-// the neighbour gathers).  No MFMA: the sweeps are sparse, FP64 and
-// gather-bound.
+//   k_dpair   step 1   per pair: d_ij = d_ji (both orientations, the larger)
+//   k_diag    step 2   per row: d_ii, tau_i, min tau; indicator alpha_i
+//   k_low     step 3   per row: R_i, U^L_i, bounds rho_min, rho_max, phi_min
+//   k_lim1p   step 4   per pair: P_ij, P_ji (eq. def-p), l_ij, l_ji (Alg. 2),
+//                       s_ij = s_ji = min(l_ij, l_ji)
+//   k_pass1a  step 5   per row: U_i = U^L_i + sum lambda_i s_ij P_ij
+//   k_lim2p   step 5   per pair: candidates of pass 2 on (1 - s_ij) P_ij
+//   k_pass2   step 6   per row: final pass, SSP-RK3 combination, hold
+// A row sweep gives one wavefront lane one stencil row (a SELL slice holds
+// 64 rows) and sums its columns in ascending order, sequentially, like the
+// CPU oracle, so every row reduction has one writer and a fixed order.  A
+// pair sweep evaluates each symmetric quantity once, with the operation
+// order its two rows would use, and stores it at (i,j) and (j,i): no row
+// ever reads a transposed entry.  Neighbour data are gathered from
+// node-major packs (128 bytes per node).  Blocks are renumbered so that
+// consecutive slices or pairs run on the same XCD (L2 locality of the
+// gathers).  No MFMA: the sweeps are sparse, FP64 and gather-bound.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -264,9 +267,66 @@ __device__ __forceinline__ void load_a(const double *__restrict__ A, NodeA<D> &o
     o.phi = A[NC + 3 + D];
 }
 
-// ------------------------------------------------------------- k_visc
+#define PAIR_SETUP(P)                                                        \
+    const int64_t p_ = logical_block(P.pper) * kBlock + threadIdx.x;         \
+    if (p_ >= P.npairs) return;                                              \
+    const int64_t e = P.pair_e[p_];                                          \
+    const int64_t t = P.pair_t[p_];                                          \
+    const int i = P.pair_i[p_];                                              \
+    const int j = P.pair_j[p_];
+
+// ------------------------------------------------------------ k_dpair
+// Step 1, once per unordered pair {i, j}: d_ij = d_ji = max of
+// lambda~(n_ij, U_i, U_j)|c_ij| and lambda~(n_ji, U_j, U_i)|c_ji|.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_visc(StageArgs P, int with_alpha)
+__global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
+{
+    PAIR_SETUP(P)
+    if (failed(P)) return;
+    const double g = P.gamma;
+    NodeA<D> Ai, Aj;
+    load_a<D>(P.packA + int64_t(i) * kPack, Ai);
+    load_a<D>(P.packA + int64_t(j) * kPack, Aj);
+    double c[D], ct[D];   // c_ij, and c_ji stored at the position of c_ij
+    c[0] = P.c0[e];
+    c[1] = P.c1[e];
+    if (D == 3) c[D - 1] = P.c2[e];
+    ct[0] = P.ct0[e];
+    ct[1] = P.ct1[e];
+    if (D == 3) ct[D - 1] = P.ct2[e];
+    double aij = 0.0, aji = 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        aij += c[q] * c[q];
+        aji += ct[q] * ct[q];
+    }
+    aij = sqrt(aij);
+    aji = sqrt(aji);
+    double t1 = 0.0, t2 = 0.0;
+    if (aij > 0.0) {
+        const double inv = 1.0 / aij;
+        double nn[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) nn[q] = c[q] * inv;
+        t1 = lambda_max<D>(nn, Ai.U, Ai.p, Ai.c, Aj.U, Aj.p, Aj.c, g) * aij;
+    }
+    if (aji > 0.0) {
+        const double inv = 1.0 / aji;
+        double nn[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) nn[q] = ct[q] * inv;
+        t2 = lambda_max<D>(nn, Aj.U, Aj.p, Aj.c, Ai.U, Ai.p, Ai.c, g) * aji;
+    }
+    const double dd = t1 > t2 ? t1 : t2;
+    P.d[e] = dd;
+    P.d[t] = dd;
+}
+
+// ------------------------------------------------------------- k_diag
+// Step 2: d_ii = -sum_{j != i} d_ij (columns ascending), tau_i, min tau_i;
+// indicator alpha_i (Section 3.8) over all j in I(i).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
 {
     ROW_SETUP(P)
     if (failed(P)) return;
@@ -283,45 +343,14 @@ __global__ void __launch_bounds__(kBlock) k_visc(StageArgs P, int with_alpha)
     for (int k = 0; k < L; ++k) {
         const int64_t e = ENTRY(k);
         const int j = P.scol[e];
-        NodeA<D> Aj;
-        load_a<D>(P.packA + int64_t(j) * kPack, Aj);
-        double c[D];
-        c[0] = P.c0[e];
-        c[1] = P.c1[e];
-        if (D == 3) c[D - 1] = P.c2[e];
-        if (j != i) {
-            double ct[D];   // c_ji, stored at the position of c_ij
-            ct[0] = P.ct0[e];
-            ct[1] = P.ct1[e];
-            if (D == 3) ct[D - 1] = P.ct2[e];
-            double aij = 0.0, aji = 0.0;
-#pragma unroll
-            for (int q = 0; q < D; ++q) {
-                aij += c[q] * c[q];
-                aji += ct[q] * ct[q];
-            }
-            aij = sqrt(aij);
-            aji = sqrt(aji);
-            double t1 = 0.0, t2 = 0.0;
-            if (aij > 0.0) {
-                const double inv = 1.0 / aij;
-                double nn[D];
-#pragma unroll
-                for (int q = 0; q < D; ++q) nn[q] = c[q] * inv;
-                t1 = lambda_max<D>(nn, Ai.U, Ai.p, Ai.c, Aj.U, Aj.p, Aj.c, g) * aij;
-            }
-            if (aji > 0.0) {
-                const double inv = 1.0 / aji;
-                double nn[D];
-#pragma unroll
-                for (int q = 0; q < D; ++q) nn[q] = ct[q] * inv;
-                t2 = lambda_max<D>(nn, Aj.U, Aj.p, Aj.c, Ai.U, Ai.p, Ai.c, g) * aji;
-            }
-            const double dd = t1 > t2 ? t1 : t2;
-            P.d[e] = dd;
-            dsum += dd;
-        }
+        if (j != i) dsum += P.d[e];
         if (with_alpha) {
+            NodeA<D> Aj;
+            load_a<D>(P.packA + int64_t(j) * kPack, Aj);
+            double c[D];
+            c[0] = P.c0[e];
+            c[1] = P.c1[e];
+            if (D == 3) c[D - 1] = P.c2[e];
             double mc = 0.0;
 #pragma unroll
             for (int q = 0; q < D; ++q) mc += Aj.U[1 + q] * c[q];
@@ -445,37 +474,52 @@ __device__ __forceinline__ void direction(const NodeB<D> &Bi, const NodeB<D> &Bj
         Pd[r] = coef * (bij * Bj.R[r] - bji * Bi.R[r] + (dH - dL) * (Bj.U[r] - Bi.U[r]));
 }
 
-// ------------------------------------------------------------- k_lim1
+// Candidate of row i on the line U + t P_ij under the bounds of row i.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_lim1(StageArgs P)
+__device__ __forceinline__ double row_limiter(const double *Urow, const double *W,
+                                              const double *Pd, const StageArgs &P)
 {
-    ROW_SETUP(P)
-    if (failed(P)) return;
     constexpr int NC = D + 2;
-    NodeB<D> Bi;
-    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
-    const double *W = P.rowB + int64_t(i) * kRowB;
-    double UL[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) UL[r] = W[r];
-    const double rmin = W[NC], rmax = W[NC + 1], pmin = W[NC + 2];
-    const double tau = *P.tau;
-    const double coef = tau / (P.lam[i] * Bi.m);
-    for (int k = 0; k < L; ++k) {
-        const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        if (j == i) { P.l1[e] = 1.0; continue; }
-        NodeB<D> Bj;
-        load_b<D>(P.packB + int64_t(j) * kPack, Bj);
-        double Pd[NC];
-        direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
-        P.l1[e] = limiter<D>(UL, Pd, rmin, rmax, pmin, P.gamma, P.newton_max, P.tol);
-    }
+    return limiter<D>(Urow, Pd, W[NC], W[NC + 1], W[NC + 2], P.gamma, P.newton_max, P.tol);
 }
 
-// ------------------------------------------------------------ k_pass1
+// ------------------------------------------------------------ k_lim1p
+// Step 4, once per unordered pair: l_ij from (U^L_i, P_ij, bounds_i) and
+// l_ji from (U^L_j, P_ji, bounds_j), each evaluated exactly as its own row
+// would; s_ij = s_ji = min(l_ij, l_ji) stored at (i,j) and (j,i).
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_pass1(StageArgs P)
+__global__ void __launch_bounds__(kBlock) k_lim1p(StageArgs P)
+{
+    PAIR_SETUP(P)
+    if (failed(P)) return;
+    constexpr int NC = D + 2;
+    NodeB<D> Bi, Bj;
+    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
+    load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+    const double *Wi = P.rowB + int64_t(i) * kRowB;
+    const double *Wj = P.rowB + int64_t(j) * kRowB;
+    const double tau = *P.tau;
+    const double coef_i = tau / (P.lam[i] * Bi.m);
+    const double coef_j = tau / (P.lam[j] * Bj.m);
+    const double dL = P.d[e], m = P.mij[e];
+    double Pd[NC], U[NC];
+    direction<D>(Bi, Bj, coef_i, dL, m, Pd);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) U[r] = Wi[r];
+    const double lij = row_limiter<D>(U, Wi, Pd, P);
+    direction<D>(Bj, Bi, coef_j, dL, m, Pd);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) U[r] = Wj[r];
+    const double lji = row_limiter<D>(U, Wj, Pd, P);
+    const double sv = lij < lji ? lij : lji;
+    P.l1[e] = sv;
+    P.l1[t] = sv;
+}
+
+// ----------------------------------------------------------- k_pass1a
+// Step 5, first half: U_i = U^L_i + sum_{j != i} lambda_i s_ij P_ij.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_pass1a(StageArgs P)
 {
     ROW_SETUP(P)
     if (failed(P)) return;
@@ -486,16 +530,14 @@ __global__ void __launch_bounds__(kBlock) k_pass1(StageArgs P)
     double V[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) V[r] = W[r];
-    const double rmin = W[NC], rmax = W[NC + 1], pmin = W[NC + 2];
     const double tau = *P.tau;
     const double lam = P.lam[i];
     const double coef = tau / (lam * Bi.m);
     for (int k = 0; k < L; ++k) {
         const int64_t e = ENTRY(k);
         const int j = P.scol[e];
-        if (j == i) continue;
-        const double lij = P.l1[e], lji = P.l1[P.stpos[e]];
-        const double l = lij < lji ? lij : lji;
+        if (j == i) { P.l1[e] = 1.0; continue; }
+        const double l = P.l1[e];
         NodeB<D> Bj;
         load_b<D>(P.packB + int64_t(j) * kPack, Bj);
         double Pd[NC];
@@ -506,24 +548,45 @@ __global__ void __launch_bounds__(kBlock) k_pass1(StageArgs P)
     double *Up = P.upass + int64_t(i) * kRowU;
 #pragma unroll
     for (int r = 0; r < NC; ++r) Up[r] = V[r];
-    if (P.passes < 2) return;
-    for (int k = 0; k < L; ++k) {
-        const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        if (j == i) { P.l2[e] = 1.0; continue; }
-        const double lij = P.l1[e], lji = P.l1[P.stpos[e]];
-        const double l = lij < lji ? lij : lji;
-        NodeB<D> Bj;
-        load_b<D>(P.packB + int64_t(j) * kPack, Bj);
-        double Pd[NC];
-        direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
+}
+
+// ------------------------------------------------------------ k_lim2p
+// Step 5, second half, once per unordered pair: candidates of pass 2 on the
+// rescaled directions (1 - s_ij) P_ij from the pass-1 states.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
+{
+    PAIR_SETUP(P)
+    if (failed(P)) return;
+    constexpr int NC = D + 2;
+    NodeB<D> Bi, Bj;
+    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
+    load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+    const double *Wi = P.rowB + int64_t(i) * kRowB;
+    const double *Wj = P.rowB + int64_t(j) * kRowB;
+    const double *Ui = P.upass + int64_t(i) * kRowU;
+    const double *Uj = P.upass + int64_t(j) * kRowU;
+    const double tau = *P.tau;
+    const double coef_i = tau / (P.lam[i] * Bi.m);
+    const double coef_j = tau / (P.lam[j] * Bj.m);
+    const double dL = P.d[e], m = P.mij[e];
+    const double l = P.l1[e];
+    double Pd[NC], U[NC];
+    direction<D>(Bi, Bj, coef_i, dL, m, Pd);
 #pragma unroll
-        for (int r = 0; r < NC; ++r) Pd[r] = (1.0 - l) * Pd[r];
-        P.l2[e] = limiter<D>(V, Pd, rmin, rmax, pmin, P.gamma, P.newton_max, P.tol);
-    }
+    for (int r = 0; r < NC; ++r) { Pd[r] = (1.0 - l) * Pd[r]; U[r] = Ui[r]; }
+    const double lij = row_limiter<D>(U, Wi, Pd, P);
+    direction<D>(Bj, Bi, coef_j, dL, m, Pd);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) { Pd[r] = (1.0 - l) * Pd[r]; U[r] = Uj[r]; }
+    const double lji = row_limiter<D>(U, Wj, Pd, P);
+    const double sv = lij < lji ? lij : lji;
+    P.l2[e] = sv;
+    P.l2[t] = sv;
 }
 
 // ------------------------------------------------------------ k_pass2
+// Step 6: U_i += sum_{j != i} lambda_i s2_ij (1 - s1_ij) P_ij, then
 // mode 0: out = E(U); 1: out = E (stage 1); 2: out = U0 + 1/4 (E - U0);
 // 3: out = U0 + 2/3 (E - U0); modes 1-3 keep held nodes at U0.
 template <int D>
@@ -546,12 +609,9 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
         for (int k = 0; k < L; ++k) {
             const int64_t e = ENTRY(k);
             const int j = P.scol[e];
-            if (j == i) continue;
-            const int64_t t = P.stpos[e];
-            const double a1 = P.l1[e], b1 = P.l1[t];
-            const double s1 = a1 < b1 ? a1 : b1;
-            const double a2 = P.l2[e], b2 = P.l2[t];
-            const double s2 = a2 < b2 ? a2 : b2;
+            if (j == i) { P.l2[e] = 1.0; continue; }
+            const double s1 = P.l1[e];
+            const double s2 = P.l2[e];
             NodeB<D> Bj;
             load_b<D>(P.packB + int64_t(j) * kPack, Bj);
             double Pd[NC];
@@ -637,45 +697,28 @@ void launch_node(const StageArgs &P, hipStream_t st, const double *U, int check)
         hipLaunchKernelGGL(k_node<3>, dim3(grid_nodes(P.n)), dim3(kBlock), 0, st, P, U, check);
 }
 
-void launch_visc(const StageArgs &P, hipStream_t st, int with_alpha)
-{
-    if (P.dim == 2)
-        hipLaunchKernelGGL(k_visc<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P, with_alpha);
-    else
-        hipLaunchKernelGGL(k_visc<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P, with_alpha);
-}
+static inline int grid_pairs(const StageArgs &P) { return P.pper * kXcd; }
 
-void launch_low(const StageArgs &P, hipStream_t st)
-{
-    if (P.dim == 2)
-        hipLaunchKernelGGL(k_low<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
-    else
-        hipLaunchKernelGGL(k_low<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
-}
+#define LAUNCH_D(K, grid, ...)                                                          \
+    do {                                                                                \
+        if (P.dim == 2)                                                                 \
+            hipLaunchKernelGGL(K<2>, dim3(grid), dim3(kBlock), 0, st, __VA_ARGS__);     \
+        else                                                                            \
+            hipLaunchKernelGGL(K<3>, dim3(grid), dim3(kBlock), 0, st, __VA_ARGS__);     \
+    } while (0)
 
-void launch_lim1(const StageArgs &P, hipStream_t st)
+void launch_dpair(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_dpair, grid_pairs(P), P); }
+void launch_diag(const StageArgs &P, hipStream_t st, int with_alpha)
 {
-    if (P.dim == 2)
-        hipLaunchKernelGGL(k_lim1<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
-    else
-        hipLaunchKernelGGL(k_lim1<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    LAUNCH_D(k_diag, grid_rows(P), P, with_alpha);
 }
-
-void launch_pass1(const StageArgs &P, hipStream_t st)
+void launch_low(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_low, grid_rows(P), P); }
+void launch_lim1p(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_lim1p, grid_pairs(P), P); }
+void launch_pass1a(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_pass1a, grid_rows(P), P); }
+void launch_lim2p(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_lim2p, grid_pairs(P), P); }
+void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out, int mode)
 {
-    if (P.dim == 2)
-        hipLaunchKernelGGL(k_pass1<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
-    else
-        hipLaunchKernelGGL(k_pass1<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
-}
-
-void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out,
-                  int mode)
-{
-    if (P.dim == 2)
-        hipLaunchKernelGGL(k_pass2<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P, U0, out, mode);
-    else
-        hipLaunchKernelGGL(k_pass2<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P, U0, out, mode);
+    LAUNCH_D(k_pass2, grid_rows(P), P, U0, out, mode);
 }
 
 void launch_math(hipStream_t st, int kind, int64_t n, const double *x, const double *y,

@@ -32,13 +32,18 @@ struct StageArgs {
     const int32_t *perm, *row_len, *diag_k;
     const int64_t *slice_off;
     const int32_t *scol, *stpos;
+    // unordered pairs {i < j}: SELL positions of (i,j), (j,i); nodes
+    int64_t npairs;
+    int pper;                   // pair blocks per XCD
+    const int32_t *pair_e, *pair_t, *pair_i, *pair_j;
     // matrices (SELL order); written by the precompute only
     double *c0, *c1, *c2, *mij;
     double *ct0, *ct1, *ct2;    // c_ji at the position of c_ij
     double *mi, *lam;
     const uint8_t *hold;
     // per-stage work
-    double *d, *l1, *l2;        // [sell]
+    double *d;                  // [sell] d_ij, diagonal d_ii
+    double *l1, *l2;            // [sell] min(l_ij, l_ji) of pass 1, 2
     double *packA, *alpha, *packB, *rowB, *upass, *taui;
     unsigned long long *taumin; // bits of min_i m_i/(-2 d_ii)
     double *tau, *bound;
@@ -51,10 +56,12 @@ void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
 void launch_begin(const StageArgs &P, hipStream_t st, int clear_status);
 void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode);
 void launch_node(const StageArgs &P, hipStream_t st, const double *U, int check);
-void launch_visc(const StageArgs &P, hipStream_t st, int with_alpha);
+void launch_dpair(const StageArgs &P, hipStream_t st);
+void launch_diag(const StageArgs &P, hipStream_t st, int with_alpha);
 void launch_low(const StageArgs &P, hipStream_t st);
-void launch_lim1(const StageArgs &P, hipStream_t st);
-void launch_pass1(const StageArgs &P, hipStream_t st);
+void launch_lim1p(const StageArgs &P, hipStream_t st);
+void launch_pass1a(const StageArgs &P, hipStream_t st);
+void launch_lim2p(const StageArgs &P, hipStream_t st);
 void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out,
                   int mode);
 void launch_math(hipStream_t st, int kind, int64_t n, const double *x, const double *y,
