@@ -262,45 +262,60 @@ def workload(name: str, n: int | None = None, order: str | None = None):
 
 # --------------------------------------------------------------- patches
 
-def extract_patch(mesh: Mesh, centre_nodes, radius: int):
-    """Sub-mesh holding every cell that touches a node within graph distance
-    ``radius`` of ``centre_nodes`` (neighbours = nodes sharing a cell).
+class PatchExtractor:
+    """Sub-meshes around chosen nodes (node -> cell adjacency built once).
 
-    Node and cell relative orders are preserved, so each row of a node whose
-    support lies inside the patch sees the same columns, in the same order,
-    as in the full mesh.  Returns (sub_mesh, node_map) with node_map[k] the
-    full-mesh id of patch node k, and ``dist`` the graph distance of every
-    patch node (radius+1 for the outer layer).
+    ``extract(centres, radius)`` returns the cells that touch a node within
+    graph distance ``radius`` of the centres (neighbours = nodes sharing a
+    cell).  Node and cell relative orders are preserved, so the row of any
+    node whose support lies inside the patch has the same columns, in the
+    same order, as in the full mesh.  Returns (sub_mesh, node_map, dist):
+    node_map[k] is the full-mesh id of patch node k and dist its graph
+    distance to the centres (radius + 1 for the outer layer).
     """
-    N = mesh.n_nodes
-    cells = mesh.cells
-    nv = cells.shape[1]
-    # node -> cells adjacency
-    flat = cells.reshape(-1)
-    owner = np.repeat(np.arange(cells.shape[0], dtype=np.int64), nv)
-    srt = np.argsort(flat, kind="stable")
-    ptr = np.zeros(N + 1, dtype=np.int64)
-    np.add.at(ptr, flat + 1, 1)
-    ptr = np.cumsum(ptr)
-    cell_of = owner[srt]
-    dist = np.full(N, -1, dtype=np.int64)
-    front = np.unique(np.asarray(centre_nodes, dtype=np.int64))
-    dist[front] = 0
-    for r in range(1, radius + 2):
-        cs = np.unique(np.concatenate(
-            [cell_of[ptr[v]:ptr[v + 1]] for v in front]))
-        nb = np.unique(cells[cs].reshape(-1))
-        nb = nb[dist[nb] < 0]
-        dist[nb] = r
-        front = nb
-    inner = np.nonzero((dist >= 0) & (dist <= radius))[0]
-    cs = np.unique(np.concatenate([cell_of[ptr[v]:ptr[v + 1]] for v in inner]))
-    nodes = np.unique(cells[cs].reshape(-1))          # ascending full ids
-    remap = np.full(N, -1, dtype=np.int64)
-    remap[nodes] = np.arange(nodes.shape[0], dtype=np.int64)
-    sub = Mesh(dim=mesh.dim, n_side=mesh.n_side,
-               coords=np.ascontiguousarray(mesh.coords[nodes]),
-               cells=np.ascontiguousarray(remap[cells[cs]]),
-               boundary=mesh.boundary[nodes].copy(),
-               grid_id=mesh.grid_id[nodes].copy())
-    return sub, nodes, dist[nodes]
+
+    def __init__(self, mesh: Mesh):
+        self.mesh = mesh
+        cells = mesh.cells
+        nv = cells.shape[1]
+        flat = cells.reshape(-1)
+        srt = np.argsort(flat, kind="stable")
+        self.cell_of = (srt // nv).astype(np.int64)
+        cnt = np.bincount(flat, minlength=mesh.n_nodes)
+        self.ptr = np.zeros(mesh.n_nodes + 1, dtype=np.int64)
+        np.cumsum(cnt, out=self.ptr[1:])
+
+    def _cells_around(self, nodes):
+        return np.unique(np.concatenate(
+            [self.cell_of[self.ptr[v]:self.ptr[v + 1]] for v in nodes]))
+
+    def extract(self, centre_nodes, radius: int):
+        mesh = self.mesh
+        cells = mesh.cells
+        dist = {}
+        front = np.unique(np.asarray(centre_nodes, dtype=np.int64))
+        for v in front:
+            dist[int(v)] = 0
+        for r in range(1, radius + 2):
+            nb = np.unique(cells[self._cells_around(front)].reshape(-1))
+            nb = np.array([v for v in nb if int(v) not in dist], dtype=np.int64)
+            for v in nb:
+                dist[int(v)] = r
+            front = nb
+        inner = np.array([v for v, d in dist.items() if d <= radius], dtype=np.int64)
+        cs = self._cells_around(inner)
+        nodes = np.unique(cells[cs].reshape(-1))          # ascending full ids
+        remap = {int(v): k for k, v in enumerate(nodes)}
+        sub_cells = np.vectorize(remap.__getitem__, otypes=[np.int64])(cells[cs])
+        sub = Mesh(dim=mesh.dim, n_side=mesh.n_side,
+                   coords=np.ascontiguousarray(mesh.coords[nodes]),
+                   cells=np.ascontiguousarray(sub_cells),
+                   boundary=mesh.boundary[nodes].copy(),
+                   grid_id=mesh.grid_id[nodes].copy())
+        d = np.array([dist.get(int(v), radius + 1) for v in nodes], dtype=np.int64)
+        return sub, nodes, d
+
+
+def extract_patch(mesh: Mesh, centre_nodes, radius: int):
+    """One-off PatchExtractor(mesh).extract(centre_nodes, radius)."""
+    return PatchExtractor(mesh).extract(centre_nodes, radius)
