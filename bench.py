@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-radius", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--newton-max", type=int, default=2,
+                    help="Newton iterations of the limiter (the method's default is 2)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -138,7 +140,7 @@ def main():
     mesh, U0 = inputs.workload("mach3_3d", n=args.n, order=args.order)
     log(f"mesh {mesh.n_nodes} nodes, {mesh.n_cells} cells in {time.perf_counter() - t:.1f} s")
     t = time.perf_counter()
-    s = Solver(mesh, asynchronous=True)
+    s = Solver(mesh, asynchronous=True, newton_max=args.newton_max)
     torch.cuda.synchronize()
     log(f"solver created: nnz {s.nnz}, {s.device_bytes / 2**30:.1f} GiB device, "
         f"{time.perf_counter() - t:.1f} s")
@@ -198,6 +200,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"mach3_3d_{args.n}^3_{args.order}",
+                   "newton_max_iter": args.newton_max,
                    "nodes": mesh.n_nodes, "nnz": s.nnz, "stages": stages,
                    "parallelism": "single GPU"},
         "roofline": roofline,

@@ -253,6 +253,9 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     TRY(dalloc(c, &pt, g.npairs));
     TRY(dalloc(c, &pi, g.npairs));
     TRY(dalloc(c, &pj, g.npairs));
+    TRY(dalloc(c, &P.mp, g.npairs));
+    TRY(dalloc(c, &P.dp, g.npairs));
+    TRY(dalloc(c, &P.l1p, g.npairs));
     TRY(dalloc(c, &P.c0, S));
     TRY(dalloc(c, &P.c1, S));
     if (dim == 3) TRY(dalloc(c, &P.c2, S));

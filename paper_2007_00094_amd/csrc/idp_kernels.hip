@@ -184,6 +184,14 @@ __global__ void __launch_bounds__(kBlock) k_transpose_c(StageArgs P)
     }
 }
 
+// m_ij in pair order (the pair sweeps read it without the position lookup)
+__global__ void __launch_bounds__(kBlock) k_pair_mass(StageArgs P)
+{
+    const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (p >= P.npairs) return;
+    P.mp[p] = P.mij[P.pair_e[p]];
+}
+
 // ------------------------------------------------------------ helpers
 __global__ void k_begin(StageArgs P, int clear_status)
 {
@@ -320,6 +328,7 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
     const double dd = t1 > t2 ? t1 : t2;
     P.d[e] = dd;
     P.d[t] = dd;
+    P.dp[p_] = dd;
 }
 
 // ------------------------------------------------------------- k_diag
@@ -377,7 +386,9 @@ __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
         double Dn = fabs(a);
 #pragma unroll
         for (int r = 0; r < NC; ++r) Dn += fabs(etap[r] - (r == 0 ? Ai.er : 0.0)) * fabs(b[r]);
-        P.alpha[i] = Dn > 0.0 ? N / Dn : 0.0;
+        const double al = Dn > 0.0 ? N / Dn : 0.0;
+        P.alpha[i] = al;
+        P.packA[int64_t(i) * kPack + kPackAlpha] = al;
     }
 }
 
@@ -404,7 +415,7 @@ __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
         if (j == i) continue;
         NodeA<D> Aj;
         load_a<D>(P.packA + int64_t(j) * kPack, Aj);
-        const double alpha_j = P.alpha[j];
+        const double alpha_j = P.packA[int64_t(j) * kPack + kPackAlpha];
         double c[D];
         c[0] = P.c0[e];
         c[1] = P.c1[e];
@@ -436,6 +447,7 @@ __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
     }
     B[2 * NC] = alpha_i;
     B[2 * NC + 1] = mi;
+    B[kPackCoef] = tau / (P.lam[i] * mi);   // tau/(lambda_i m_i) of eq. def-p
     W[NC + 0] = rho_min;
     W[NC + 1] = rho_max;
     W[NC + 2] = phi_min;
@@ -443,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
 
 template <int D>
 struct NodeB {
-    double U[D + 2], R[D + 2], alpha, m;
+    double U[D + 2], R[D + 2], alpha, m, coef;
 };
 
 template <int D>
@@ -457,6 +469,7 @@ __device__ __forceinline__ void load_b(const double *__restrict__ B, NodeB<D> &o
     }
     o.alpha = B[2 * NC];
     o.m = B[2 * NC + 1];
+    o.coef = B[kPackCoef];
 }
 
 // eq. def-p: P_ij = tau/(lambda_i m_i) (b_ij R_j - b_ji R_i + (d^H - d^L)(U_j - U_i)),
@@ -498,22 +511,20 @@ __global__ void __launch_bounds__(kBlock) k_lim1p(StageArgs P)
     load_b<D>(P.packB + int64_t(j) * kPack, Bj);
     const double *Wi = P.rowB + int64_t(i) * kRowB;
     const double *Wj = P.rowB + int64_t(j) * kRowB;
-    const double tau = *P.tau;
-    const double coef_i = tau / (P.lam[i] * Bi.m);
-    const double coef_j = tau / (P.lam[j] * Bj.m);
-    const double dL = P.d[e], m = P.mij[e];
+    const double dL = P.dp[p_], m = P.mp[p_];
     double Pd[NC], U[NC];
-    direction<D>(Bi, Bj, coef_i, dL, m, Pd);
+    direction<D>(Bi, Bj, Bi.coef, dL, m, Pd);
 #pragma unroll
     for (int r = 0; r < NC; ++r) U[r] = Wi[r];
     const double lij = row_limiter<D>(U, Wi, Pd, P);
-    direction<D>(Bj, Bi, coef_j, dL, m, Pd);
+    direction<D>(Bj, Bi, Bj.coef, dL, m, Pd);
 #pragma unroll
     for (int r = 0; r < NC; ++r) U[r] = Wj[r];
     const double lji = row_limiter<D>(U, Wj, Pd, P);
     const double sv = lij < lji ? lij : lji;
     P.l1[e] = sv;
     P.l1[t] = sv;
+    P.l1p[p_] = sv;
 }
 
 // ----------------------------------------------------------- k_pass1a
@@ -566,17 +577,14 @@ __global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
     const double *Wj = P.rowB + int64_t(j) * kRowB;
     const double *Ui = P.upass + int64_t(i) * kRowU;
     const double *Uj = P.upass + int64_t(j) * kRowU;
-    const double tau = *P.tau;
-    const double coef_i = tau / (P.lam[i] * Bi.m);
-    const double coef_j = tau / (P.lam[j] * Bj.m);
-    const double dL = P.d[e], m = P.mij[e];
-    const double l = P.l1[e];
+    const double dL = P.dp[p_], m = P.mp[p_];
+    const double l = P.l1p[p_];
     double Pd[NC], U[NC];
-    direction<D>(Bi, Bj, coef_i, dL, m, Pd);
+    direction<D>(Bi, Bj, Bi.coef, dL, m, Pd);
 #pragma unroll
     for (int r = 0; r < NC; ++r) { Pd[r] = (1.0 - l) * Pd[r]; U[r] = Ui[r]; }
     const double lij = row_limiter<D>(U, Wi, Pd, P);
-    direction<D>(Bj, Bi, coef_j, dL, m, Pd);
+    direction<D>(Bj, Bi, Bj.coef, dL, m, Pd);
 #pragma unroll
     for (int r = 0; r < NC; ++r) { Pd[r] = (1.0 - l) * Pd[r]; U[r] = Uj[r]; }
     const double lji = row_limiter<D>(U, Wj, Pd, P);
@@ -677,6 +685,9 @@ void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
         hipLaunchKernelGGL(k_transpose_c<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
     else
         hipLaunchKernelGGL(k_transpose_c<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    if (P.npairs > 0)
+        hipLaunchKernelGGL(k_pair_mass, dim3(int((P.npairs + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, st, P);
 }
 
 void launch_begin(const StageArgs &P, hipStream_t st, int clear_status)

@@ -11,6 +11,8 @@ constexpr int kSlice = 64;    // SELL slice height = wavefront width
 constexpr int kXcd = 8;       // XCDs of an MI355X; blocks are renumbered so
                               // that each XCD walks a contiguous slice range
 constexpr int kPack = 16;     // doubles per node in the gather packs
+constexpr int kPackAlpha = 12;  // pack A slot of alpha_i (written by k_diag)
+constexpr int kPackCoef = 12;   // pack B slot of tau/(lambda_i m_i)
 constexpr int kRowB = 8;      // doubles per node: U^L (nc), bounds (3)
 constexpr int kRowU = 8;      // doubles per node: state after pass 1
 
@@ -36,6 +38,8 @@ struct StageArgs {
     int64_t npairs;
     int pper;                   // pair blocks per XCD
     const int32_t *pair_e, *pair_t, *pair_i, *pair_j;
+    double *mp;                 // [npairs] m_ij in pair order
+    double *dp, *l1p;           // [npairs] d_ij, min(l_ij, l_ji) pass 1
     // matrices (SELL order); written by the precompute only
     double *c0, *c1, *c2, *mij;
     double *ct0, *ct1, *ct2;    // c_ji at the position of c_ij
