@@ -17,9 +17,11 @@
 // pair sweep evaluates each symmetric quantity once, with the operation
 // order its two rows would use, and stores it at (i,j) and (j,i): no row
 // ever reads a transposed entry.  Neighbour data are gathered from
-// node-major packs (128 bytes per node).  Blocks are renumbered so that
-// consecutive slices or pairs run on the same XCD (L2 locality of the
-// gathers).  No MFMA: the sweeps are sparse, FP64 and gather-bound.
+// node-major packs (128 bytes per node), mostly by whole wavefronts at once
+// (one cache line per record and load instruction, exchanged through LDS).
+// Blocks are renumbered so that consecutive slices or pairs run on the same
+// XCD (L2 locality of the gathers).  No MFMA: the sweeps are sparse, FP64
+// and bound by the L1 address path of their gathers and by FP64 issue.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -275,13 +277,106 @@ __device__ __forceinline__ void load_a(const double *__restrict__ A, NodeA<D> &o
     o.phi = A[NC + 3 + D];
 }
 
-#define PAIR_SETUP(P)                                                        \
+// ------------------------------------------------- cooperative gathers
+// A lane that fetches a neighbour's record with its own 16-byte loads
+// touches a different cache line per lane, so every load instruction costs
+// the L1 address path 64 line lookups, and a 104-byte record costs seven
+// instructions.  Instead the 64 lanes of a wavefront fetch the records of
+// all its lanes together: lane l loads chunk l % LPR of the record wanted
+// by lane it * (64 / LPR) + l / LPR, so one instruction covers 64 / LPR
+// records (one line each), and the chunks reach their owners through a
+// per-wavefront LDS tile.  All loads are issued before the first is used.
+// Every lane of the wavefront must call it (node < 0: nothing wanted).
+constexpr int kLdsRow = kSlice + 1;   // double2 per chunk row (+1: bank skew)
+
+template <int NCH>
+__device__ __forceinline__ void gather(const double *__restrict__ base, int stride, int node,
+                                       double2 *lds, double *out)
+{
+    static_assert(NCH >= 1 && NCH <= 8, "record of 1 to 8 chunks");
+    constexpr int LPR = NCH > 4 ? 8 : (NCH > 2 ? 4 : (NCH > 1 ? 2 : 1));
+    constexpr int RPI = kSlice / LPR;
+    const int lane = threadIdx.x % kSlice;
+    const int c = lane % LPR;
+    const int cc = c < NCH ? c : NCH - 1;   // spare lanes repeat the last chunk
+    int nd[LPR];
+#pragma unroll
+    for (int it = 0; it < LPR; ++it) {
+        const int v = __shfl(node, it * RPI + lane / LPR);
+        nd[it] = v < 0 ? 0 : v;
+    }
+    double2 val[LPR];
+#pragma unroll
+    for (int it = 0; it < LPR; ++it)
+        val[it] = *reinterpret_cast<const double2 *>(base + int64_t(nd[it]) * stride + 2 * cc);
+#pragma unroll
+    for (int it = 0; it < LPR; ++it) lds[cc * kLdsRow + it * RPI + lane / LPR] = val[it];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+        const double2 v = lds[k * kLdsRow + lane];
+        out[2 * k] = v.x;
+        out[2 * k + 1] = v.y;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// LDS tile of the calling wavefront (NCH chunk rows)
+#define WAVE_TILE(NCH)                                                       \
+    __shared__ double2 lds_[kBlock / kSlice][(NCH) * kLdsRow];               \
+    double2 *const lw = lds_[threadIdx.x / kSlice];
+
+// Row sweeps with gathers: every lane stays to the end of the slice's
+// longest row; lanes past the node count take node 0 and write nothing.
+#define WAVE_ROW_SETUP(P)                                                    \
+    const int64_t s_ = logical_block(P.per) * (kBlock / kSlice) +            \
+                       threadIdx.x / kSlice;                                 \
+    if (s_ >= P.nslices) return;                                             \
+    const int lane_ = threadIdx.x % kSlice;                                  \
+    const int64_t r_ = s_ * kSlice + lane_;                                  \
+    const int iraw_ = P.perm[r_];                                            \
+    const bool valid_ = iraw_ >= 0;                                          \
+    const int i = valid_ ? iraw_ : 0;                                        \
+    const int L = valid_ ? P.row_len[r_] : 0;                                \
+    const int64_t off_ = P.slice_off[s_] + lane_;                            \
+    int Lmax_ = L;                                                           \
+    for (int o_ = kSlice / 2; o_ > 0; o_ /= 2) {                             \
+        const int v_ = __shfl_xor(Lmax_, o_);                                \
+        Lmax_ = v_ > Lmax_ ? v_ : Lmax_;                                     \
+    }
+
+// Pair sweeps: lanes past the pair count take pair 0 and write nothing.
+#define WAVE_PAIR_SETUP(P)                                                   \
     const int64_t p_ = logical_block(P.pper) * kBlock + threadIdx.x;         \
-    if (p_ >= P.npairs) return;                                              \
-    const int64_t e = P.pair_e[p_];                                          \
-    const int64_t t = P.pair_t[p_];                                          \
-    const int i = P.pair_i[p_];                                              \
-    const int j = P.pair_j[p_];
+    if (p_ - threadIdx.x % kSlice >= P.npairs) return;                       \
+    const bool valid_ = p_ < P.npairs;                                       \
+    const int64_t pq_ = valid_ ? p_ : 0;                                     \
+    const int64_t e = P.pair_e[pq_];                                         \
+    const int64_t t = P.pair_t[pq_];                                         \
+    const int i = P.pair_i[pq_];                                             \
+    const int j = P.pair_j[pq_];
+
+template <int D>
+__device__ __forceinline__ void unpack_a(const double *o, NodeA<D> &A)
+{
+    constexpr int NC = D + 2;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) A.U[k] = o[k];
+    A.p = o[NC];
+    A.c = o[NC + 1];
+    A.er = o[NC + 2];
+#pragma unroll
+    for (int k = 0; k < D; ++k) A.v[k] = o[NC + 3 + k];
+    A.phi = o[NC + 3 + D];
+}
+
+template <int D>
+__device__ __forceinline__ void load_c(const StageArgs &P, int64_t e, double *c)
+{
+    c[0] = P.c0[e];
+    c[1] = P.c1[e];
+    if (D == 3) c[D - 1] = P.c2[e];
+}
 
 // ------------------------------------------------------------ k_dpair
 // Step 1, once per unordered pair {i, j}: d_ij = d_ji = max of
@@ -289,19 +384,21 @@ __device__ __forceinline__ void load_a(const double *__restrict__ A, NodeA<D> &o
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
 {
-    PAIR_SETUP(P)
+    WAVE_PAIR_SETUP(P)
     if (failed(P)) return;
+    constexpr int NC = D + 2;
+    constexpr int NCH = (NC + 3) / 2;   // U, p, c
+    WAVE_TILE(NCH)
     const double g = P.gamma;
-    NodeA<D> Ai, Aj;
-    load_a<D>(P.packA + int64_t(i) * kPack, Ai);
-    load_a<D>(P.packA + int64_t(j) * kPack, Aj);
     double c[D], ct[D];   // c_ij, and c_ji stored at the position of c_ij
-    c[0] = P.c0[e];
-    c[1] = P.c1[e];
-    if (D == 3) c[D - 1] = P.c2[e];
+    load_c<D>(P, e, c);
     ct[0] = P.ct0[e];
     ct[1] = P.ct1[e];
     if (D == 3) ct[D - 1] = P.ct2[e];
+    double Ai[2 * NCH], Aj[2 * NCH];
+    gather<NCH>(P.packA, kPack, i, lw, Ai);
+    gather<NCH>(P.packA, kPack, j, lw, Aj);
+    if (!valid_) return;
     double aij = 0.0, aji = 0.0;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
@@ -316,14 +413,14 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
         double nn[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) nn[q] = c[q] * inv;
-        t1 = lambda_max<D>(nn, Ai.U, Ai.p, Ai.c, Aj.U, Aj.p, Aj.c, g) * aij;
+        t1 = lambda_max<D>(nn, Ai, Ai[NC], Ai[NC + 1], Aj, Aj[NC], Aj[NC + 1], g) * aij;
     }
     if (aji > 0.0) {
         const double inv = 1.0 / aji;
         double nn[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) nn[q] = ct[q] * inv;
-        t2 = lambda_max<D>(nn, Aj.U, Aj.p, Aj.c, Ai.U, Ai.p, Ai.c, g) * aji;
+        t2 = lambda_max<D>(nn, Aj, Aj[NC], Aj[NC + 1], Ai, Ai[NC], Ai[NC + 1], g) * aji;
     }
     const double dd = t1 > t2 ? t1 : t2;
     P.d[e] = dd;
@@ -337,9 +434,11 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
 {
-    ROW_SETUP(P)
+    WAVE_ROW_SETUP(P)
     if (failed(P)) return;
     constexpr int NC = D + 2;
+    constexpr int NCH = (NC + 4 + D) / 2;   // U, p, c, eta/rho, v, phi
+    WAVE_TILE(NCH)
     const double g = P.gamma;
     NodeA<D> Ai;
     load_a<D>(P.packA + int64_t(i) * kPack, Ai);
@@ -349,17 +448,22 @@ __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
     double b[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) b[r] = 0.0;
-    for (int k = 0; k < L; ++k) {
+    int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+    for (int k = 0; k < Lmax_; ++k) {
         const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        if (j != i) dsum += P.d[e];
+        const int j = jn;
+        if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
+        const bool in = k < L;
+        const double dd = P.d[e];
+        if (in && j != i) dsum += dd;
         if (with_alpha) {
-            NodeA<D> Aj;
-            load_a<D>(P.packA + int64_t(j) * kPack, Aj);
             double c[D];
-            c[0] = P.c0[e];
-            c[1] = P.c1[e];
-            if (D == 3) c[D - 1] = P.c2[e];
+            load_c<D>(P, e, c);
+            double rec[2 * NCH];
+            gather<NCH>(P.packA, kPack, in ? j : -1, lw, rec);
+            if (!in) continue;
+            NodeA<D> Aj;
+            unpack_a<D>(rec, Aj);
             double mc = 0.0;
 #pragma unroll
             for (int q = 0; q < D; ++q) mc += Aj.U[1 + q] * c[q];
@@ -371,6 +475,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
             for (int r = 0; r < NC; ++r) b[r] += fd[r];
         }
     }
+    if (!valid_) return;
     const double dii = -dsum;
     P.d[ENTRY(P.diag_k[r_])] = dii;
     const double ti = P.mi[i] / (-2.0 * dii);
@@ -393,10 +498,12 @@ __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
 }
 
 // -------------------------------------------------------------- k_low
+// Step 3.  Its per-entry arithmetic (two fluxes, a division) hides the
+// latency of plain per-lane record loads better than a cooperative gather.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
 {
-    ROW_SETUP(P)
+    WAVE_ROW_SETUP(P)
     if (failed(P)) return;
     constexpr int NC = D + 2;
     NodeA<D> Ai;
@@ -409,18 +516,19 @@ __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
 #pragma unroll
     for (int r = 0; r < NC; ++r) { R[r] = 0.0; Lw[r] = 0.0; }
     double rho_min = Ai.U[0], rho_max = Ai.U[0], phi_min = Ai.phi;
-    for (int k = 0; k < L; ++k) {
+    int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+    for (int k = 0; k < Lmax_; ++k) {
         const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        if (j == i) continue;
+        const int j = jn;
+        if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
+        const bool act = k < L && j != i;
+        double c[D];
+        load_c<D>(P, e, c);
+        const double dL = P.d[e];
+        if (!act) continue;
         NodeA<D> Aj;
         load_a<D>(P.packA + int64_t(j) * kPack, Aj);
         const double alpha_j = P.packA[int64_t(j) * kPack + kPackAlpha];
-        double c[D];
-        c[0] = P.c0[e];
-        c[1] = P.c1[e];
-        if (D == 3) c[D - 1] = P.c2[e];
-        const double dL = P.d[e];
         const double dH = dL * (alpha_i + alpha_j) / 2.0;
         double Fj[NC][D], fd[NC];
         flux<D>(Aj.U, Aj.v, Aj.p, Fj);
@@ -436,6 +544,7 @@ __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
         if (rbar > rho_max) rho_max = rbar;
         if (Aj.phi < phi_min) phi_min = Aj.phi;
     }
+    if (!valid_) return;
     const double mi = P.mi[i];
     double *B = P.packB + int64_t(i) * kPack;
     double *W = P.rowB + int64_t(i) * kRowB;
@@ -472,6 +581,22 @@ __device__ __forceinline__ void load_b(const double *__restrict__ B, NodeB<D> &o
     o.coef = B[kPackCoef];
 }
 
+// pack B record as gathered: U, R, alpha, m (and the coefficient if
+// WITH_COEF, i.e. if the gather reached slot kPackCoef)
+template <int D, bool WITH_COEF>
+__device__ __forceinline__ void unpack_b(const double *o, NodeB<D> &B)
+{
+    constexpr int NC = D + 2;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        B.U[k] = o[k];
+        B.R[k] = o[NC + k];
+    }
+    B.alpha = o[2 * NC];
+    B.m = o[2 * NC + 1];
+    B.coef = WITH_COEF ? o[kPackCoef] : 0.0;
+}
+
 // eq. def-p: P_ij = tau/(lambda_i m_i) (b_ij R_j - b_ji R_i + (d^H - d^L)(U_j - U_i)),
 // b_ij = -m_ij/m_j, b_ji = -m_ij/m_i (j != i)
 template <int D>
@@ -496,6 +621,15 @@ __device__ __forceinline__ double row_limiter(const double *Urow, const double *
     return limiter<D>(Urow, Pd, W[NC], W[NC + 1], W[NC + 2], P.gamma, P.newton_max, P.tol);
 }
 
+// record sizes in 16-byte chunks
+template <int D> struct Chunks {
+    static constexpr int NC = D + 2;
+    static constexpr int packB = kPackCoef / 2 + 1;   // U, R, alpha, m, coefficient
+    static constexpr int packBrow = NC + 1;           // U, R, alpha, m
+    static constexpr int rowB = (NC + 4) / 2;         // U^L, bounds
+    static constexpr int upass = (NC + 1) / 2;        // pass-1 state
+};
+
 // ------------------------------------------------------------ k_lim1p
 // Step 4, once per unordered pair: l_ij from (U^L_i, P_ij, bounds_i) and
 // l_ji from (U^L_j, P_ji, bounds_j), each evaluated exactly as its own row
@@ -503,15 +637,21 @@ __device__ __forceinline__ double row_limiter(const double *Urow, const double *
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_lim1p(StageArgs P)
 {
-    PAIR_SETUP(P)
+    WAVE_PAIR_SETUP(P)
     if (failed(P)) return;
     constexpr int NC = D + 2;
+    using CH = Chunks<D>;
+    WAVE_TILE(CH::packB)
+    const double dL = P.dp[pq_], m = P.mp[pq_];
     NodeB<D> Bi, Bj;
-    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
-    load_b<D>(P.packB + int64_t(j) * kPack, Bj);
-    const double *Wi = P.rowB + int64_t(i) * kRowB;
-    const double *Wj = P.rowB + int64_t(j) * kRowB;
-    const double dL = P.dp[p_], m = P.mp[p_];
+    double rec[2 * CH::packB], Wi[2 * CH::rowB], Wj[2 * CH::rowB];
+    gather<CH::packB>(P.packB, kPack, i, lw, rec);
+    unpack_b<D, true>(rec, Bi);
+    gather<CH::packB>(P.packB, kPack, j, lw, rec);
+    unpack_b<D, true>(rec, Bj);
+    gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
+    gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
+    if (!valid_) return;
     double Pd[NC], U[NC];
     direction<D>(Bi, Bj, Bi.coef, dL, m, Pd);
 #pragma unroll
@@ -532,9 +672,11 @@ __global__ void __launch_bounds__(kBlock) k_lim1p(StageArgs P)
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_pass1a(StageArgs P)
 {
-    ROW_SETUP(P)
+    WAVE_ROW_SETUP(P)
     if (failed(P)) return;
     constexpr int NC = D + 2;
+    using CH = Chunks<D>;
+    WAVE_TILE(CH::packBrow)
     NodeB<D> Bi;
     load_b<D>(P.packB + int64_t(i) * kPack, Bi);
     const double *W = P.rowB + int64_t(i) * kRowB;
@@ -544,18 +686,25 @@ __global__ void __launch_bounds__(kBlock) k_pass1a(StageArgs P)
     const double tau = *P.tau;
     const double lam = P.lam[i];
     const double coef = tau / (lam * Bi.m);
-    for (int k = 0; k < L; ++k) {
+    int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+    for (int k = 0; k < Lmax_; ++k) {
         const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        if (j == i) { P.l1[e] = 1.0; continue; }
-        const double l = P.l1[e];
+        const int j = jn;
+        if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
+        const double l = P.l1[e], dL = P.d[e], m = P.mij[e];
+        const bool act = k < L && j != i;
+        if (k < L && j == i) P.l1[e] = 1.0;
+        double rec[2 * CH::packBrow];
+        gather<CH::packBrow>(P.packB, kPack, act ? j : -1, lw, rec);
+        if (!act) continue;
         NodeB<D> Bj;
-        load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+        unpack_b<D, false>(rec, Bj);
         double Pd[NC];
-        direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
+        direction<D>(Bi, Bj, coef, dL, m, Pd);
 #pragma unroll
         for (int r = 0; r < NC; ++r) V[r] += lam * l * Pd[r];
     }
+    if (!valid_) return;
     double *Up = P.upass + int64_t(i) * kRowU;
 #pragma unroll
     for (int r = 0; r < NC; ++r) Up[r] = V[r];
@@ -567,18 +716,25 @@ __global__ void __launch_bounds__(kBlock) k_pass1a(StageArgs P)
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
 {
-    PAIR_SETUP(P)
+    WAVE_PAIR_SETUP(P)
     if (failed(P)) return;
     constexpr int NC = D + 2;
+    using CH = Chunks<D>;
+    WAVE_TILE(CH::packB)
+    const double dL = P.dp[pq_], m = P.mp[pq_];
+    const double l = P.l1p[pq_];
     NodeB<D> Bi, Bj;
-    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
-    load_b<D>(P.packB + int64_t(j) * kPack, Bj);
-    const double *Wi = P.rowB + int64_t(i) * kRowB;
-    const double *Wj = P.rowB + int64_t(j) * kRowB;
-    const double *Ui = P.upass + int64_t(i) * kRowU;
-    const double *Uj = P.upass + int64_t(j) * kRowU;
-    const double dL = P.dp[p_], m = P.mp[p_];
-    const double l = P.l1p[p_];
+    double rec[2 * CH::packB], Wi[2 * CH::rowB], Wj[2 * CH::rowB];
+    double Ui[2 * CH::upass], Uj[2 * CH::upass];
+    gather<CH::packB>(P.packB, kPack, i, lw, rec);
+    unpack_b<D, true>(rec, Bi);
+    gather<CH::packB>(P.packB, kPack, j, lw, rec);
+    unpack_b<D, true>(rec, Bj);
+    gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
+    gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
+    gather<CH::upass>(P.upass, kRowU, i, lw, Ui);
+    gather<CH::upass>(P.upass, kRowU, j, lw, Uj);
+    if (!valid_) return;
     double Pd[NC], U[NC];
     direction<D>(Bi, Bj, Bi.coef, dL, m, Pd);
 #pragma unroll
@@ -601,9 +757,11 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0, double *out,
                                                   int mode)
 {
-    ROW_SETUP(P)
+    WAVE_ROW_SETUP(P)
     if (failed(P)) return;
     constexpr int NC = D + 2;
+    using CH = Chunks<D>;
+    WAVE_TILE(CH::packBrow)
     NodeB<D> Bi;
     load_b<D>(P.packB + int64_t(i) * kPack, Bi);
     double V[NC];
@@ -614,16 +772,21 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
         const double tau = *P.tau;
         const double lam = P.lam[i];
         const double coef = tau / (lam * Bi.m);
-        for (int k = 0; k < L; ++k) {
+        int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+        for (int k = 0; k < Lmax_; ++k) {
             const int64_t e = ENTRY(k);
-            const int j = P.scol[e];
-            if (j == i) { P.l2[e] = 1.0; continue; }
-            const double s1 = P.l1[e];
-            const double s2 = P.l2[e];
+            const int j = jn;
+            if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
+            const double s1 = P.l1[e], s2 = P.l2[e], dL = P.d[e], m = P.mij[e];
+            const bool act = k < L && j != i;
+            if (k < L && j == i) P.l2[e] = 1.0;
+            double rec[2 * CH::packBrow];
+            gather<CH::packBrow>(P.packB, kPack, act ? j : -1, lw, rec);
+            if (!act) continue;
             NodeB<D> Bj;
-            load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+            unpack_b<D, false>(rec, Bj);
             double Pd[NC];
-            direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
+            direction<D>(Bi, Bj, coef, dL, m, Pd);
 #pragma unroll
             for (int r = 0; r < NC; ++r) {
                 const double P2 = (1.0 - s1) * Pd[r];
@@ -631,6 +794,7 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
             }
         }
     }
+    if (!valid_) return;
     double *o = out + int64_t(i) * NC;
     if (mode == 0) {
 #pragma unroll
