@@ -231,6 +231,7 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     const int64_t blocks = (g.nslices + (idp::kBlock / idp::kSlice) - 1) / (idp::kBlock / idp::kSlice);
     P.per = int((blocks + idp::kXcd - 1) / idp::kXcd);
     P.gamma = p.gamma;
+    P.gas = idp::make_gas(p.gamma);
     P.cfl = p.cfl;
     P.tol = p.newton_tol;
     P.newton_max = p.newton_max_iter;

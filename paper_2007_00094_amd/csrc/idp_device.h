@@ -180,11 +180,33 @@ __device__ __forceinline__ double psi_branch(double rho, double ps, double cs, d
     return (fpow(p / ps, (g - 1.0) / (2.0 * g)) - 1.0) * 2.0 * cs / (g - 1.0);
 }
 
+// Constants of the bound that depend on gamma only, evaluated once per
+// launch with exactly the expressions the formula uses.
+struct GasC {
+    double g;
+    double half_gm1;   // (g - 1)/2 as 0.5 * (g - 1)
+    double e_den;      // -(g - 1)/(2 g)
+    double e_p;        // 2 g/(g - 1)
+    double f;          // (g + 1)/(2 g)
+};
+
+__host__ __device__ inline GasC make_gas(double g)
+{
+    GasC G;
+    G.g = g;
+    G.half_gm1 = 0.5 * (g - 1.0);
+    G.e_den = -(g - 1.0) / (2.0 * g);
+    G.e_p = 2.0 * g / (g - 1.0);
+    G.f = (g + 1.0) / (2.0 * g);
+    return G;
+}
+
 template <int D>
 __device__ __forceinline__ double lambda_max(const double *n, const double *Ui,
                                              double pi, double ci, const double *Uj,
-                                             double pj, double cj, double g)
+                                             double pj, double cj, const GasC &G)
 {
+    const double g = G.g;
     double mti = 0.0, mtj = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) mti += n[k] * Ui[1 + k];
@@ -192,9 +214,9 @@ __device__ __forceinline__ double lambda_max(const double *n, const double *Ui,
     for (int k = 0; k < D; ++k) mtj += n[k] * Uj[1 + k];
     const double ui = mti / Ui[0];
     const double uj = mtj / Uj[0];
-    const double num = ci + cj - 0.5 * (g - 1.0) * (uj - ui);
-    const double den = ci * fpow(pi / pj, -(g - 1.0) / (2.0 * g)) + cj;
-    const double ptilde = pj * fpow(pos_part(num) / den, 2.0 * g / (g - 1.0));
+    const double num = ci + cj - G.half_gm1 * (uj - ui);
+    const double den = ci * fpow(pi / pj, G.e_den) + cj;
+    const double ptilde = pj * fpow(pos_part(num) / den, G.e_p);
     const double pmax = pi > pj ? pi : pj;
     const double psi = psi_branch<D>(Ui[0], pi, ci, pmax, g) +
                        psi_branch<D>(Uj[0], pj, cj, pmax, g) + uj - ui;
@@ -203,9 +225,8 @@ __device__ __forceinline__ double lambda_max(const double *n, const double *Ui,
         pstar = ptilde;
     else
         pstar = pmax < ptilde ? pmax : ptilde;
-    const double f = (g + 1.0) / (2.0 * g);
-    const double lam1 = ui - ci * sqrt(1.0 + f * pos_part((pstar - pi) / pi));
-    const double lam3 = uj + cj * sqrt(1.0 + f * pos_part((pstar - pj) / pj));
+    const double lam1 = ui - ci * sqrt(1.0 + G.f * pos_part((pstar - pi) / pi));
+    const double lam3 = uj + cj * sqrt(1.0 + G.f * pos_part((pstar - pj) / pj));
     const double a = neg_part(lam1), b = pos_part(lam3);
     return a > b ? a : b;
 }

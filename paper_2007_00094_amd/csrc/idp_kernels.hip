@@ -389,7 +389,6 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
     constexpr int NC = D + 2;
     constexpr int NCH = (NC + 3) / 2;   // U, p, c
     WAVE_TILE(NCH)
-    const double g = P.gamma;
     double c[D], ct[D];   // c_ij, and c_ji stored at the position of c_ij
     load_c<D>(P, e, c);
     ct[0] = P.ct0[e];
@@ -413,14 +412,14 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
         double nn[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) nn[q] = c[q] * inv;
-        t1 = lambda_max<D>(nn, Ai, Ai[NC], Ai[NC + 1], Aj, Aj[NC], Aj[NC + 1], g) * aij;
+        t1 = lambda_max<D>(nn, Ai, Ai[NC], Ai[NC + 1], Aj, Aj[NC], Aj[NC + 1], P.gas) * aij;
     }
     if (aji > 0.0) {
         const double inv = 1.0 / aji;
         double nn[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) nn[q] = ct[q] * inv;
-        t2 = lambda_max<D>(nn, Aj, Aj[NC], Aj[NC + 1], Ai, Ai[NC], Ai[NC + 1], g) * aji;
+        t2 = lambda_max<D>(nn, Aj, Aj[NC], Aj[NC + 1], Ai, Ai[NC], Ai[NC + 1], P.gas) * aji;
     }
     const double dd = t1 > t2 ? t1 : t2;
     P.d[e] = dd;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "idp_device.h"
+
 namespace idp {
 
 constexpr int kBlock = 256;   // threads per block: 4 wavefronts = 4 slices
@@ -29,6 +31,7 @@ struct StageArgs {
     int64_t nslices;
     int per;                    // logical blocks per XCD
     double gamma, cfl, tol;
+    GasC gas;                   // gamma-only constants of the wave-speed bound
     int newton_max, passes;
     // SELL-64 graph
     const int32_t *perm, *row_len, *diag_k;
