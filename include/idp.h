@@ -46,6 +46,8 @@ extern "C" {
 #define IDP_ESTATE (-5)         /* input state not admissible (rho<=0, eps<=0, NaN) */
 #define IDP_EDT (-6)            /* given dt > min_i m_i/(-2 d_ii) at stage 1 */
 #define IDP_ENOTSUP (-7)        /* option not supported by this build        */
+#define IDP_EWAIT (-8)          /* a persistent batch launch gave up waiting
+                                   on a dependency (its results are void)  */
 
 /* flags for idp_params.flags */
 #define IDP_FLAG_ASYNC 1        /* idp_step does not synchronise; errors are
@@ -161,6 +163,62 @@ int idp_kernel_times(idp_ctx *ctx, int max, const char **names,
  * check that device and host arithmetic agree bit for bit.  Synchronises. */
 int idp_device_math(idp_ctx *ctx, int kind, int64_t n, const double *x_dev,
                     const double *y_dev, double *out_dev);
+
+/* ------------------------------------------------------------ batches
+ * Many independent meshes of uneven sizes advanced together, each with its
+ * own tau (the same scheme per instance, Section 3).  Instance k owns the
+ * nodes [off[k], off[k+1]) of one concatenated state U_dev [N][nc]
+ * (off from idp_batch_info); its results are bit-identical to a context
+ * created for that mesh alone.  idp_step, idp_euler_stage and idp_max_dt
+ * answer IDP_ENOTSUP on a context with more than one instance.           */
+
+/* Build a batch context: n_inst meshes, each given like idp_create's
+ * (host arrays n_nodes[k], coords[k], n_cells[k], cells[k], dirichlet[k]
+ * or dirichlet == NULL / dirichlet[k] == NULL for none).  Node ids inside
+ * cells[k] are local to instance k.  Errors as idp_create.                */
+int idp_create_batch(idp_ctx **out, const idp_params *p, int n_inst,
+                     const int64_t *n_nodes, const double *const *coords,
+                     const int64_t *n_cells, const int64_t *const *cells,
+                     const uint8_t *const *dirichlet, void *hip_stream);
+
+/* Number of instances and host [n_inst + 1] node offsets (may be NULL).  */
+int idp_batch_info(const idp_ctx *ctx, int *n_inst, int64_t *node_offsets);
+
+/* How idp_batch_steps runs: IDP_SCHED_LAUNCHES, one kernel launch per
+ * sweep covering every instance; IDP_SCHED_PERSISTENT, one persistent
+ * launch for all n_steps steps in which every wavefront pops work items of
+ * `tile` units (a unit: 64 nodes, 64 pairs or one 64-row stencil slice of
+ * one instance) from a queue, each item waiting only on the earlier sweeps
+ * of its own instance.  Both give the same bits.                         */
+#define IDP_SCHED_LAUNCHES 1
+#define IDP_SCHED_PERSISTENT 2
+typedef struct {
+    int kind;
+    int tile;     /* persistent: units per work item, 1..1024 */
+} idp_schedule;
+
+/* n_steps SSP-RK3 steps of every instance, in place on U_dev.
+ * dt: host [n_inst] fixed per-instance tau (IDP_EDT if one exceeds its
+ * stage-1 bound), or NULL for tau_k = cfl * (stage-1 bound of instance k)
+ * at every step.  dt_used: host [n_steps][n_inst] or NULL.  sched: NULL =
+ * the schedule chosen by idp_batch_tune (else IDP_SCHED_LAUNCHES).
+ * Synchronises.  Returns IDP_OK, IDP_WARN_CFL, IDP_ESTATE, IDP_EDT,
+ * IDP_EWAIT, IDP_EINVAL or IDP_EHIP; after an error U_dev is undefined.  */
+int idp_batch_steps(idp_ctx *ctx, double *U_dev, int n_steps, const double *dt,
+                    double *dt_used, const idp_schedule *sched);
+
+/* tau_k = cfl * min_{i in instance k} m_i/(-2 d_ii(U)) for every instance:
+ * host dt_out [n_inst].  Synchronises.                                   */
+int idp_batch_max_dt(idp_ctx *ctx, const double *U_dev, double *dt_out);
+
+/* Autotuner: times n_steps steps from U_dev (left unchanged: the runs use
+ * a scratch copy) under each candidate schedule (one launch per sweep;
+ * persistent with tile 4, 16, 32, 64, 128, 256), keeps the fastest for
+ * idp_batch_steps(sched = NULL) and returns it in *best (may be NULL).
+ * ms_out (host, may be NULL) receives the time of each candidate, in that
+ * order, and *n_candidates their number.  Synchronises.                  */
+int idp_batch_tune(idp_ctx *ctx, const double *U_dev, int n_steps, idp_schedule *best,
+                   double *ms_out, int *n_candidates);
 
 /* Text of a return code.                                                 */
 const char *idp_strerror(int code);

@@ -21,7 +21,10 @@ IDP_EHIP = -4
 IDP_ESTATE = -5
 IDP_EDT = -6
 IDP_ENOTSUP = -7
+IDP_EWAIT = -8
 IDP_FLAG_ASYNC = 1
+IDP_SCHED_LAUNCHES = 1
+IDP_SCHED_PERSISTENT = 2
 
 IDP_DBG_D = 0
 IDP_DBG_ALPHA = 1
@@ -39,6 +42,10 @@ class idp_params(C.Structure):
                 ("limiter_passes", C.c_int), ("newton_max_iter", C.c_int),
                 ("newton_tol", C.c_double), ("relax_bounds", C.c_int),
                 ("flags", C.c_int)]
+
+
+class idp_schedule(C.Structure):
+    _fields_ = [("kind", C.c_int), ("tile", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -62,6 +69,14 @@ SIGNATURES = {
     "idp_set_timing": (C.c_int, [_vp, C.c_int]),
     "idp_kernel_times": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_char_p), _dp, _i64p]),
     "idp_device_math": (C.c_int, [_vp, C.c_int, C.c_int64, _vp, _vp, _vp]),
+    "idp_create_batch": (C.c_int, [C.POINTER(_vp), C.POINTER(idp_params), C.c_int, _i64p,
+                                   C.POINTER(_dp), _i64p, C.POINTER(_i64p), C.POINTER(_u8p),
+                                   _vp]),
+    "idp_batch_info": (C.c_int, [_vp, C.POINTER(C.c_int), _i64p]),
+    "idp_batch_steps": (C.c_int, [_vp, _vp, C.c_int, _dp, _dp, C.POINTER(idp_schedule)]),
+    "idp_batch_max_dt": (C.c_int, [_vp, _vp, _dp]),
+    "idp_batch_tune": (C.c_int, [_vp, _vp, C.c_int, C.POINTER(idp_schedule), _dp,
+                                 C.POINTER(C.c_int)]),
     "idp_strerror": (C.c_char_p, [C.c_int]),
     "idp_destroy": (None, [_vp]),
 }

@@ -204,4 +204,101 @@ int build_graph(HostGraph &g, int dim, int64_t n, int64_t ncells,
     }
 }
 
+static int concat(const std::vector<HostGraph> &parts, HostGraph &g, BatchLayout &lay)
+{
+    const size_t K = parts.size();
+    const HostGraph &p0 = parts[0];
+    g = HostGraph();
+    g.dim = p0.dim;
+    g.nv = p0.nv;
+    for (auto *v : {&lay.node, &lay.cell, &lay.nnz, &lay.slice, &lay.sell, &lay.pair})
+        v->assign(K + 1, 0);
+    for (size_t k = 0; k < K; ++k) {
+        const HostGraph &h = parts[k];
+        lay.node[k + 1] = lay.node[k] + h.n;
+        lay.cell[k + 1] = lay.cell[k] + h.ncells;
+        lay.nnz[k + 1] = lay.nnz[k] + h.nnz;
+        lay.slice[k + 1] = lay.slice[k] + h.nslices;
+        lay.sell[k + 1] = lay.sell[k] + h.sell_size;
+        lay.pair[k + 1] = lay.pair[k] + h.npairs;
+        if (h.max_len > g.max_len) g.max_len = h.max_len;
+    }
+    // positions and node ids stay 32-bit on the device
+    if (lay.sell[K] >= (int64_t(1) << 31) || lay.node[K] >= (int64_t(1) << 31)) return IDP_EINVAL;
+    g.n = lay.node[K];
+    g.ncells = lay.cell[K];
+    g.nnz = lay.nnz[K];
+    g.nslices = lay.slice[K];
+    g.sell_size = lay.sell[K];
+    g.npairs = lay.pair[K];
+    g.row_ptr.resize(g.n + 1);
+    g.col.resize(g.nnz);
+    g.tpos.resize(g.nnz);
+    g.nc_ptr.resize(g.n + 1);
+    g.nc_list.resize(size_t(g.ncells) * g.nv);
+    const int64_t nr = g.nslices * kSellC;
+    g.perm.resize(nr);
+    g.row_len.resize(nr);
+    g.diag_k.resize(nr);
+    g.slice_w.resize(g.nslices);
+    g.slice_off.resize(g.nslices);
+    g.sell_of_csr.resize(g.nnz);
+    g.scol.resize(g.sell_size);
+    g.stpos.resize(g.sell_size);
+    g.pair_e.resize(g.npairs);
+    g.pair_t.resize(g.npairs);
+    g.pair_i.resize(g.npairs);
+    g.pair_j.resize(g.npairs);
+    lay.inst_slice.resize(g.nslices);
+    for (size_t k = 0; k < K; ++k) {
+        const HostGraph &h = parts[k];
+        const int64_t no = lay.node[k], co = lay.cell[k], zo = lay.nnz[k];
+        const int64_t so = lay.slice[k], eo = lay.sell[k], po = lay.pair[k];
+        for (int64_t i = 0; i < h.n; ++i) {
+            g.row_ptr[no + i] = zo + h.row_ptr[i];
+            g.nc_ptr[no + i] = co * g.nv + h.nc_ptr[i];
+        }
+        for (int64_t q = 0; q < h.nnz; ++q) {
+            g.col[zo + q] = int32_t(no + h.col[q]);
+            g.tpos[zo + q] = zo + h.tpos[q];
+            g.sell_of_csr[zo + q] = eo + h.sell_of_csr[q];
+        }
+        for (int64_t q = 0; q < h.ncells * h.nv; ++q)
+            g.nc_list[co * g.nv + q] = int32_t(co + h.nc_list[q]);
+        for (int64_t r = 0; r < h.nslices * kSellC; ++r) {
+            g.perm[so * kSellC + r] = h.perm[r] >= 0 ? int32_t(no + h.perm[r]) : -1;
+            g.row_len[so * kSellC + r] = h.row_len[r];
+            g.diag_k[so * kSellC + r] = h.diag_k[r];
+        }
+        for (int64_t t = 0; t < h.nslices; ++t) {
+            g.slice_w[so + t] = h.slice_w[t];
+            g.slice_off[so + t] = eo + h.slice_off[t];
+            lay.inst_slice[so + t] = int32_t(k);
+        }
+        for (int64_t e = 0; e < h.sell_size; ++e) {
+            g.scol[eo + e] = int32_t(no + h.scol[e]);
+            g.stpos[eo + e] = int32_t(eo + h.stpos[e]);
+        }
+        for (int64_t q = 0; q < h.npairs; ++q) {
+            g.pair_e[po + q] = int32_t(eo + h.pair_e[q]);
+            g.pair_t[po + q] = int32_t(eo + h.pair_t[q]);
+            g.pair_i[po + q] = int32_t(no + h.pair_i[q]);
+            g.pair_j[po + q] = int32_t(no + h.pair_j[q]);
+        }
+    }
+    g.row_ptr[g.n] = g.nnz;
+    g.nc_ptr[g.n] = g.ncells * g.nv;
+    return IDP_OK;
+}
+
+int concat_graphs(const std::vector<HostGraph> &parts, HostGraph &g, BatchLayout &lay)
+{
+    if (parts.empty()) return IDP_EINVAL;
+    try {
+        return concat(parts, g, lay);
+    } catch (const std::bad_alloc &) {
+        return IDP_ENOMEM;
+    }
+}
+
 }  // namespace idp

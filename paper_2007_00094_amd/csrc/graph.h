@@ -56,4 +56,18 @@ struct HostGraph {
 int build_graph(HostGraph &g, int dim, int64_t n, int64_t ncells,
                 const int64_t *cells);
 
+// Where each instance of a concatenated batch lives (k = 0..ninst, the
+// last entry is the total): nodes, cells, CSR entries, slices, SELL
+// entries, pairs.
+struct BatchLayout {
+    std::vector<int64_t> node, cell, nnz, slice, sell, pair;
+    std::vector<int32_t> inst_slice;   // [nslices] instance of each slice
+};
+
+// Concatenates independent graphs into one: instance k's ids, positions
+// and slices are shifted past those of instances 0..k-1, so a slice or a
+// pair never mixes instances and every row keeps its columns and order.
+// Returns 0 or IDP_ENOMEM.
+int concat_graphs(const std::vector<HostGraph> &parts, HostGraph &g, BatchLayout &lay);
+
 }  // namespace idp

@@ -17,23 +17,33 @@ namespace {
 
 enum KernelId {
     K_BEGIN, K_NODE, K_DPAIR, K_DIAG, K_TAU, K_LOW, K_LIM1P, K_PASS1A, K_LIM2P, K_PASS2,
-    K_COUNT
+    K_PERSIST, K_COUNT
 };
 const char *kKernelNames[K_COUNT] = {"begin", "node_pack", "pair_viscosity", "row_diagonal",
                                      "tau", "row_low_order", "pair_limiter1", "row_pass1",
-                                     "pair_limiter2", "row_pass2"};
+                                     "pair_limiter2", "row_pass2", "batch_persistent"};
 
 struct Pending {
     int id;
     hipEvent_t a, b;
 };
 
-struct Scalars {        // device-side scalars, copied back in one transfer
-    unsigned long long taumin;
-    double tau;
-    double bound;
-    int status;
-    int pad;
+// Device block of scalars, copied back in one transfer: the status word,
+// then per instance min tau_i (bits), tau and the bound.
+struct Scalars {
+    int status = 0;
+    std::vector<unsigned long long> taumin;
+    std::vector<double> tau, bound;
+};
+constexpr size_t kScalHead = 16;
+inline size_t scal_bytes(int ninst) { return kScalHead + size_t(ninst) * 24; }
+
+// Work tables of one persistent schedule (tile size) of a batch.
+struct PersistTables {
+    int tile = 0;
+    idp::BatchArgs B{};
+    int32_t *item_inst = nullptr;
+    int64_t *item_first = nullptr, *pre = nullptr;
 };
 
 }  // namespace
@@ -51,8 +61,21 @@ struct idp_ctx {
     std::vector<int64_t> sell_of_csr;
     int64_t sell_size = 0;
     idp::StageArgs P{};
-    Scalars *scal = nullptr;
+    char *scal = nullptr;           // device block, see Scalars
     double *U1 = nullptr;
+    // batches
+    int ninst = 1;
+    idp::BatchLayout lay;           // instance offsets (single mesh: one instance)
+    double *dt_dev = nullptr;       // [ninst] per-instance dt of a batch call
+    double *dt_rec = nullptr;       // [dt_rec_cap] tau of every step and instance
+    int64_t dt_rec_cap = 0;
+    int64_t *unit_end = nullptr;    // [ninst][3] node, pair, slice ends
+    unsigned long long *taumin2 = nullptr;
+    unsigned int *done = nullptr;
+    unsigned long long *head = nullptr;
+    std::vector<PersistTables> tables;
+    idp_schedule tuned{IDP_SCHED_LAUNCHES, 0};
+    double *U_tune = nullptr;
     // timing
     bool timing = false;
     std::vector<Pending> pending;
@@ -133,16 +156,28 @@ int sync(idp_ctx *c)
 
 int read_scalars(idp_ctx *c, Scalars *h)
 {
-    if (hipMemcpyAsync(h, c->scal, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream) !=
+    const int n = c->ninst;
+    std::vector<char> buf(scal_bytes(n));
+    if (hipMemcpyAsync(buf.data(), c->scal, buf.size(), hipMemcpyDeviceToHost, c->stream) !=
         hipSuccess)
         return IDP_EHIP;
-    return sync(c);
+    const int rc = sync(c);
+    if (rc != IDP_OK) return rc;
+    std::memcpy(&h->status, buf.data(), sizeof(int));
+    h->taumin.resize(n);
+    h->tau.resize(n);
+    h->bound.resize(n);
+    std::memcpy(h->taumin.data(), buf.data() + kScalHead, size_t(n) * 8);
+    std::memcpy(h->tau.data(), buf.data() + kScalHead + size_t(n) * 8, size_t(n) * 8);
+    std::memcpy(h->bound.data(), buf.data() + kScalHead + size_t(n) * 16, size_t(n) * 8);
+    return IDP_OK;
 }
 
 int status_code(int st)
 {
     if (st & idp::kErrState) return IDP_ESTATE;
     if (st & idp::kErrDt) return IDP_EDT;
+    if (st & idp::kErrWait) return IDP_EWAIT;
     if (st & idp::kWarnCfl) return IDP_WARN_CFL;
     return IDP_OK;
 }
@@ -198,32 +233,97 @@ void idp_destroy(idp_ctx *c)
     delete c;
 }
 
-int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
-               const double *coords, int64_t n_cells, const int64_t *cells,
-               const uint8_t *dirichlet, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+struct MeshIn {
+    int64_t n_nodes, n_cells;
+    const double *coords;
+    const int64_t *cells;
+    const uint8_t *dirichlet;
+};
+
+int check_params(const idp_params &p)
 {
-    if (!out || !prm || !coords || !cells) return IDP_EINVAL;
-    *out = nullptr;
-    const idp_params p = *prm;
     if ((p.dim != 2 && p.dim != 3) || !(p.gamma > 1.0) || !(p.cfl > 0.0) ||
         !(p.cfl <= 1.0) || (p.limiter_passes != 1 && p.limiter_passes != 2) ||
         p.newton_max_iter < 0 || p.newton_max_iter > 64 || !(p.newton_tol >= 0.0))
         return IDP_EINVAL;
     if (p.relax_bounds) return IDP_ENOTSUP;
+    return IDP_OK;
+}
+
+// One context for one mesh or a batch of meshes (concatenated graph).
+int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &meshes,
+                void *hip_stream)
+{
+    const int K = int(meshes.size());
     idp_ctx *c = new (std::nothrow) idp_ctx;
     if (!c) return IDP_ENOMEM;
     c->prm = p;
+    c->ninst = K;
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return IDP_EHIP; }
+    const int dim = p.dim;
+    const int nv = 1 << dim;
 
     idp::HostGraph g;
-    int rc = idp::build_graph(g, p.dim, n_nodes, n_cells, cells);
+    // host mesh arrays of the whole context (concatenated for a batch)
+    std::vector<double> coords_all;
+    std::vector<int64_t> cells_all;
+    std::vector<uint8_t> hold_all;
+    const double *coords = meshes[0].coords;
+    const int64_t *cells = meshes[0].cells;
+    const uint8_t *dirichlet = meshes[0].dirichlet;
+    int64_t n_cells = meshes[0].n_cells;
+    int rc = IDP_OK;
+    try {
+        if (K == 1) {
+            rc = idp::build_graph(g, dim, meshes[0].n_nodes, n_cells, cells);
+            auto &L = c->lay;
+            L.node = {0, g.n};
+            L.cell = {0, g.ncells};
+            L.nnz = {0, g.nnz};
+            L.slice = {0, g.nslices};
+            L.sell = {0, g.sell_size};
+            L.pair = {0, g.npairs};
+        } else {
+            std::vector<idp::HostGraph> parts(K);
+            for (int k = 0; k < K && rc == IDP_OK; ++k)
+                rc = idp::build_graph(parts[k], dim, meshes[k].n_nodes, meshes[k].n_cells,
+                                      meshes[k].cells);
+            if (rc == IDP_OK) rc = idp::concat_graphs(parts, g, c->lay);
+            if (rc == IDP_OK) {
+                const auto &L = c->lay;
+                coords_all.resize(size_t(L.node[K]) * dim);
+                cells_all.resize(size_t(L.cell[K]) * nv);
+                bool any_hold = false;
+                for (int k = 0; k < K; ++k) any_hold = any_hold || meshes[k].dirichlet;
+                if (any_hold) hold_all.assign(size_t(L.node[K]), 0);
+                for (int k = 0; k < K; ++k) {
+                    const MeshIn &m = meshes[k];
+                    std::memcpy(coords_all.data() + L.node[k] * dim, m.coords,
+                                size_t(m.n_nodes) * dim * 8);
+                    for (int64_t t = 0; t < m.n_cells * nv; ++t)
+                        cells_all[L.cell[k] * nv + t] = m.cells[t] + L.node[k];
+                    if (m.dirichlet)
+                        std::memcpy(hold_all.data() + L.node[k], m.dirichlet, size_t(m.n_nodes));
+                }
+                coords = coords_all.data();
+                cells = cells_all.data();
+                dirichlet = any_hold ? hold_all.data() : nullptr;
+                n_cells = L.cell[K];
+            }
+        }
+    } catch (const std::bad_alloc &) {
+        rc = IDP_ENOMEM;
+    }
     if (rc != IDP_OK) { delete c; return rc; }
     c->n = g.n;
     c->nnz = g.nnz;
     c->sell_size = g.sell_size;
     const int64_t nrows = g.nslices * idp::kSlice;
-    const int dim = p.dim;
     idp::StageArgs &P = c->P;
     P.dim = dim;
     P.n = g.n;
@@ -236,6 +336,7 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     P.tol = p.newton_tol;
     P.newton_max = p.newton_max_iter;
     P.passes = p.limiter_passes;
+    P.ninst = K;
 
     int32_t *perm, *row_len, *diag_k, *scol, *stpos;
     int32_t *pe, *pt, *pi, *pj;
@@ -276,11 +377,18 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     TRY(dalloc(c, &P.alpha, g.n));
     TRY(dalloc(c, &P.taui, g.n));
     TRY(dalloc(c, &c->U1, g.n * (dim + 2)));
-    TRY(dalloc(c, &c->scal, 1));
+    TRY(dalloc(c, &c->scal, scal_bytes(K)));
     uint8_t *hold = nullptr;
     if (dirichlet) {
         TRY(dalloc(c, &hold, g.n));
         HIPTRY(hipMemcpyAsync(hold, dirichlet, g.n, hipMemcpyHostToDevice, c->stream));
+    }
+    if (K > 1) {
+        int32_t *inst = nullptr;
+        TRY(dalloc(c, &inst, g.nslices));
+        HIPTRY(hipMemcpyAsync(inst, c->lay.inst_slice.data(), g.nslices * 4,
+                              hipMemcpyHostToDevice, c->stream));
+        P.inst_slice = inst;
     }
     P.hold = hold;
     P.perm = perm;
@@ -295,10 +403,10 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     P.pair_t = pt;
     P.pair_i = pi;
     P.pair_j = pj;
-    P.taumin = &c->scal->taumin;
-    P.tau = &c->scal->tau;
-    P.bound = &c->scal->bound;
-    P.status = &c->scal->status;
+    P.status = reinterpret_cast<int *>(c->scal);
+    P.taumin = reinterpret_cast<unsigned long long *>(c->scal + kScalHead);
+    P.tau = reinterpret_cast<double *>(c->scal + kScalHead + size_t(K) * 8);
+    P.bound = reinterpret_cast<double *>(c->scal + kScalHead + size_t(K) * 16);
     HIPTRY(hipMemcpyAsync(perm, g.perm.data(), nrows * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemcpyAsync(row_len, g.row_len.data(), nrows * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemcpyAsync(diag_k, g.diag_k.data(), nrows * 4, hipMemcpyHostToDevice, c->stream));
@@ -309,11 +417,10 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     HIPTRY(hipMemcpyAsync(pt, g.pair_t.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemcpyAsync(pi, g.pair_i.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemcpyAsync(pj, g.pair_j.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
-    HIPTRY(hipMemsetAsync(c->scal, 0, sizeof(Scalars), c->stream));
+    HIPTRY(hipMemsetAsync(c->scal, 0, scal_bytes(K), c->stream));
 
     // matrices on the device (temporary mesh arrays)
     {
-        const int nv = 1 << dim;
         std::vector<int32_t> cells32;
         try {
             cells32.resize(size_t(n_cells) * nv);
@@ -322,7 +429,7 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
             return IDP_ENOMEM;
         }
         for (int64_t t = 0; t < n_cells * nv; ++t) cells32[t] = int32_t(cells[t]);
-        double *dco = nullptr, *dummy = nullptr;
+        double *dco = nullptr;
         int32_t *dcells = nullptr, *dnl = nullptr;
         int64_t *dncp = nullptr;
         int *derr = nullptr;
@@ -331,7 +438,6 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
                   hipMalloc(&dncp, g.nc_ptr.size() * 8) == hipSuccess &&
                   hipMalloc(&dnl, g.nc_list.size() * 4) == hipSuccess &&
                   hipMalloc(&derr, sizeof(int)) == hipSuccess;
-        (void)dummy;
         int herr = 0;
         if (ok) {
             ok = hipMemcpyAsync(dco, coords, size_t(g.n) * dim * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
@@ -365,9 +471,50 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     return IDP_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
+               const double *coords, int64_t n_cells, const int64_t *cells,
+               const uint8_t *dirichlet, void *hip_stream)
+{
+    if (!out || !prm || !coords || !cells) return IDP_EINVAL;
+    *out = nullptr;
+    const int rc = check_params(*prm);
+    if (rc != IDP_OK) return rc;
+    return create_impl(out, *prm, {MeshIn{n_nodes, n_cells, coords, cells, dirichlet}},
+                       hip_stream);
+}
+
+int idp_create_batch(idp_ctx **out, const idp_params *prm, int n_inst,
+                     const int64_t *n_nodes, const double *const *coords,
+                     const int64_t *n_cells, const int64_t *const *cells,
+                     const uint8_t *const *dirichlet, void *hip_stream)
+{
+    if (!out || !prm || n_inst < 1 || !n_nodes || !coords || !n_cells || !cells)
+        return IDP_EINVAL;
+    *out = nullptr;
+    const int rc = check_params(*prm);
+    if (rc != IDP_OK) return rc;
+    std::vector<MeshIn> meshes;
+    try {
+        meshes.resize(n_inst);
+    } catch (const std::bad_alloc &) {
+        return IDP_ENOMEM;
+    }
+    for (int k = 0; k < n_inst; ++k) {
+        if (!coords[k] || !cells[k] || n_nodes[k] < 1 || n_cells[k] < 1) return IDP_EINVAL;
+        meshes[k] = MeshIn{n_nodes[k], n_cells[k], coords[k], cells[k],
+                           dirichlet ? dirichlet[k] : nullptr};
+    }
+    return create_impl(out, *prm, meshes, hip_stream);
+}
+
 int idp_step(idp_ctx *c, double *U, double dt, double *dt_used)
 {
     if (!c || !U || !std::isfinite(dt)) return IDP_EINVAL;
+    if (c->ninst != 1) return IDP_ENOTSUP;
     const bool async = (c->prm.flags & IDP_FLAG_ASYNC) != 0;
     double *U1 = c->U1;
     // stage 1: U1 = E(U^n), tau selected (or checked) from the stage-1 bound
@@ -382,7 +529,7 @@ int idp_step(idp_ctx *c, double *U, double dt, double *dt_used)
     int rc = read_scalars(c, &h);
     if (rc != IDP_OK) return rc;
     rc = status_code(h.status);
-    if (rc >= 0 && dt_used) *dt_used = h.tau;
+    if (rc >= 0 && dt_used) *dt_used = h.tau[0];
     return rc;
 }
 
@@ -390,6 +537,7 @@ int idp_euler_stage(idp_ctx *c, const double *U, double tau, double *Uout)
 {
     if (!c || !U || !Uout || !(tau > 0.0) || !std::isfinite(tau) || U == Uout)
         return IDP_EINVAL;
+    if (c->ninst != 1) return IDP_ENOTSUP;
     stage(c, U, U, Uout, 0, 2, tau, 1, 1);
     Scalars h{};
     int rc = read_scalars(c, &h);
@@ -397,9 +545,13 @@ int idp_euler_stage(idp_ctx *c, const double *U, double tau, double *Uout)
     return status_code(h.status);
 }
 
-int idp_max_dt(idp_ctx *c, const double *U, double *dt_out)
+}  // extern "C"
+
+namespace {
+
+// cfl * min_i m_i/(-2 d_ii) of every instance (host dt_out [ninst])
+int max_dt_all(idp_ctx *c, const double *U, double *dt_out)
 {
-    if (!c || !U || !dt_out) return IDP_EINVAL;
     const idp::StageArgs &P = c->P;
     timed(c, K_BEGIN, [&] { idp::launch_begin(P, c->stream, 1); });
     timed(c, K_NODE, [&] { idp::launch_node(P, c->stream, U, 1); });
@@ -409,10 +561,29 @@ int idp_max_dt(idp_ctx *c, const double *U, double *dt_out)
     int rc = read_scalars(c, &h);
     if (rc != IDP_OK) return rc;
     if (h.status & idp::kErrState) return IDP_ESTATE;
-    double bound;
-    std::memcpy(&bound, &h.taumin, sizeof(double));
-    *dt_out = c->prm.cfl * bound;
+    for (int k = 0; k < c->ninst; ++k) {
+        double bound;
+        std::memcpy(&bound, &h.taumin[k], sizeof(double));
+        dt_out[k] = c->prm.cfl * bound;
+    }
     return IDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int idp_max_dt(idp_ctx *c, const double *U, double *dt_out)
+{
+    if (!c || !U || !dt_out) return IDP_EINVAL;
+    if (c->ninst != 1) return IDP_ENOTSUP;
+    return max_dt_all(c, U, dt_out);
+}
+
+int idp_batch_max_dt(idp_ctx *c, const double *U, double *dt_out)
+{
+    if (!c || !U || !dt_out) return IDP_EINVAL;
+    return max_dt_all(c, U, dt_out);
 }
 
 int idp_get_status(idp_ctx *c)
@@ -421,7 +592,7 @@ int idp_get_status(idp_ctx *c)
     Scalars h{};
     int rc = read_scalars(c, &h);
     if (rc != IDP_OK) return rc;
-    if (hipMemsetAsync(&c->scal->status, 0, sizeof(int), c->stream) != hipSuccess) return IDP_EHIP;
+    if (hipMemsetAsync(c->P.status, 0, sizeof(int), c->stream) != hipSuccess) return IDP_EHIP;
     rc = sync(c);
     if (rc != IDP_OK) return rc;
     return status_code(h.status);
@@ -546,6 +717,230 @@ int idp_device_math(idp_ctx *c, int kind, int64_t n, const double *x, const doub
     return sync(c);
 }
 
+int idp_batch_info(const idp_ctx *c, int *n_inst, int64_t *node_offsets)
+{
+    if (!c) return IDP_EINVAL;
+    if (n_inst) *n_inst = c->ninst;
+    if (node_offsets)
+        for (int k = 0; k <= c->ninst; ++k) node_offsets[k] = c->lay.node[k];
+    return IDP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Work-item tables of the persistent schedule with `tile` tiles per item.
+int persist_tables(idp_ctx *c, int tile, PersistTables **out)
+{
+    for (auto &t : c->tables)
+        if (t.tile == tile) { *out = &t; return IDP_OK; }
+    const int K = c->ninst;
+    const auto &L = c->lay;
+    int e = IDP_OK;
+    if (!c->done) {
+        if ((e = dalloc(c, &c->done, K)) != IDP_OK) return e;
+        if ((e = dalloc(c, &c->head, 1)) != IDP_OK) return e;
+        if ((e = dalloc(c, &c->taumin2, 2 * size_t(K))) != IDP_OK) return e;
+        if ((e = dalloc(c, &c->unit_end, 3 * size_t(K))) != IDP_OK) return e;
+        std::vector<int64_t> ue(3 * size_t(K));
+        for (int k = 0; k < K; ++k) {
+            ue[3 * k + 0] = L.node[k + 1];
+            ue[3 * k + 1] = L.pair[k + 1];
+            ue[3 * k + 2] = L.slice[k + 1];
+        }
+        if (hipMemcpy(c->unit_end, ue.data(), ue.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return IDP_EHIP;
+    }
+    // sweep kinds: 0 nodes, 1 pairs, 2 slices; the unit of work of one
+    // wavefront: 64 nodes, 64 pairs, 1 slice
+    const int kind[idp::kSweeps] = {0, 1, 2, 2, 1, 2, 1, 2};
+    const int64_t unit[3] = {idp::kSlice, idp::kSlice, 1};
+    constexpr int S1 = idp::kSweeps + 1;
+    std::vector<int64_t> items(size_t(K) * idp::kSweeps), pre(size_t(K) * S1);
+    idp::BatchArgs B{};
+    B.tile = tile;
+    for (int s = 0; s < idp::kSweeps; ++s) {
+        B.sweep_off[s + 1] = B.sweep_off[s];
+        for (int k = 0; k < K; ++k) {
+            const int64_t *range = kind[s] == 0 ? L.node.data() : kind[s] == 1 ? L.pair.data()
+                                                                              : L.slice.data();
+            int64_t n = cdiv(cdiv(range[k + 1] - range[k], unit[kind[s]]), tile);
+            if (s == 6 && c->prm.limiter_passes < 2) n = 0;
+            items[size_t(k) * idp::kSweeps + s] = n;
+            B.sweep_off[s + 1] += n;
+        }
+    }
+    for (int k = 0; k < K; ++k) {
+        int64_t acc = 0;
+        for (int s = 0; s < idp::kSweeps; ++s) {
+            pre[size_t(k) * S1 + s] = acc + (s >= 3 ? 1 : 0);   // + the tau update
+            acc += items[size_t(k) * idp::kSweeps + s];
+        }
+        pre[size_t(k) * S1 + idp::kSweeps] = acc + 1;
+    }
+    B.items_per_stage = B.sweep_off[idp::kSweeps];
+    std::vector<int32_t> inst(B.items_per_stage);
+    std::vector<int64_t> first(B.items_per_stage);
+    int64_t q = 0;
+    for (int s = 0; s < idp::kSweeps; ++s)
+        for (int k = 0; k < K; ++k) {
+            const int64_t *range = kind[s] == 0 ? L.node.data() : kind[s] == 1 ? L.pair.data()
+                                                                              : L.slice.data();
+            for (int64_t it = 0; it < items[size_t(k) * idp::kSweeps + s]; ++it, ++q) {
+                inst[q] = k;
+                first[q] = range[k] + it * tile * unit[kind[s]];
+            }
+        }
+    PersistTables T;
+    T.tile = tile;
+    if ((e = dalloc(c, &T.item_inst, inst.size())) != IDP_OK) return e;
+    if ((e = dalloc(c, &T.item_first, first.size())) != IDP_OK) return e;
+    if ((e = dalloc(c, &T.pre, pre.size())) != IDP_OK) return e;
+    if (hipMemcpy(T.item_inst, inst.data(), inst.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(T.item_first, first.data(), first.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(T.pre, pre.data(), pre.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return IDP_EHIP;
+    B.item_inst = T.item_inst;
+    B.item_first = T.item_first;
+    B.pre = T.pre;
+    B.unit_end = c->unit_end;
+    B.taumin2 = c->taumin2;
+    B.done = c->done;
+    B.head = c->head;
+    T.B = B;
+    c->tables.push_back(T);
+    *out = &c->tables.back();
+    return IDP_OK;
+}
+
+int batch_steps(idp_ctx *c, double *U, int n_steps, const double *dt, double *dt_used,
+                const idp_schedule &sc)
+{
+    const int K = c->ninst;
+    idp::StageArgs &P = c->P;
+    int e = IDP_OK;
+    if (dt) {
+        for (int k = 0; k < K; ++k)
+            if (!(dt[k] > 0.0) || !std::isfinite(dt[k])) return IDP_EINVAL;
+        if (!c->dt_dev && (e = dalloc(c, &c->dt_dev, K)) != IDP_OK) return e;
+        if (hipMemcpyAsync(c->dt_dev, dt, size_t(K) * 8, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess)
+            return IDP_EHIP;
+    }
+    const int64_t need = int64_t(n_steps) * K;
+    if (c->dt_rec_cap < need) {
+        if ((e = dalloc(c, &c->dt_rec, need)) != IDP_OK) return e;
+        c->dt_rec_cap = need;
+    }
+    P.dt_inst = dt ? c->dt_dev : nullptr;
+    if (sc.kind == IDP_SCHED_LAUNCHES) {
+        for (int st = 0; st < n_steps; ++st) {
+            stage(c, U, U, c->U1, 1, 1, 0.0, 1, st == 0 ? 1 : 0);
+            (void)hipMemcpyAsync(c->dt_rec + int64_t(st) * K, P.tau, size_t(K) * 8,
+                                 hipMemcpyDeviceToDevice, c->stream);
+            stage(c, c->U1, U, c->U1, 2, 0, 0.0, 0, 0);
+            stage(c, c->U1, U, U, 3, 0, 0.0, 0, 0);
+        }
+    } else {
+        PersistTables *T = nullptr;
+        if ((e = persist_tables(c, sc.tile, &T)) != IDP_OK) { P.dt_inst = nullptr; return e; }
+        idp::BatchArgs B = T->B;
+        B.nsteps = n_steps;
+        B.check = 1;
+        B.total_items = B.items_per_stage * 3 * n_steps;
+        B.U = U;
+        B.U1 = c->U1;
+        B.dt_rec = c->dt_rec;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess) { P.dt_inst = nullptr; return IDP_EHIP; }
+        const int grid = idp::persistent_blocks_per_cu(P.dim) * cus;
+        idp::launch_batch_init(P, B, c->stream, 1);
+        timed(c, K_PERSIST, [&] { idp::launch_persistent(P, B, c->stream, grid); });
+    }
+    P.dt_inst = nullptr;
+    if (hipGetLastError() != hipSuccess) return IDP_EHIP;
+    Scalars h{};
+    int rc = read_scalars(c, &h);
+    if (rc != IDP_OK) return rc;
+    rc = status_code(h.status);
+    if (rc >= 0 && dt_used) {
+        if (hipMemcpy(dt_used, c->dt_rec, size_t(need) * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return IDP_EHIP;
+    }
+    return rc;
+}
+
+bool valid_schedule(const idp_schedule &s)
+{
+    if (s.kind == IDP_SCHED_LAUNCHES) return true;
+    return s.kind == IDP_SCHED_PERSISTENT && s.tile >= 1 && s.tile <= 1024;
+}
+
+}  // namespace
+
+extern "C" {
+
+int idp_batch_steps(idp_ctx *c, double *U, int n_steps, const double *dt, double *dt_used,
+                    const idp_schedule *sched)
+{
+    if (!c || !U || n_steps < 0) return IDP_EINVAL;
+    const idp_schedule sc = sched ? *sched : c->tuned;
+    if (!valid_schedule(sc)) return IDP_EINVAL;
+    if (n_steps == 0) return IDP_OK;
+    return batch_steps(c, U, n_steps, dt, dt_used, sc);
+}
+
+int idp_batch_tune(idp_ctx *c, const double *U, int n_steps, idp_schedule *best,
+                   double *ms_out, int *n_candidates)
+{
+    if (!c || !U || n_steps < 1) return IDP_EINVAL;
+    const idp_schedule cand[] = {{IDP_SCHED_LAUNCHES, 0},    {IDP_SCHED_PERSISTENT, 4},
+                                 {IDP_SCHED_PERSISTENT, 16},  {IDP_SCHED_PERSISTENT, 32},
+                                 {IDP_SCHED_PERSISTENT, 64},  {IDP_SCHED_PERSISTENT, 128},
+                                 {IDP_SCHED_PERSISTENT, 256}};
+    const int nc = int(sizeof(cand) / sizeof(cand[0]));
+    const size_t bytes = size_t(c->n) * (c->prm.dim + 2) * 8;
+    int e = IDP_OK;
+    if (!c->U_tune && (e = dalloc(c, &c->U_tune, size_t(c->n) * (c->prm.dim + 2))) != IDP_OK)
+        return e;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        return IDP_EHIP;
+    }
+    int bi = -1;
+    double bms = 0.0;
+    for (int q = 0; q < nc; ++q) {
+        double ms = -1.0;   // failed candidate
+        int rc = hipMemcpyAsync(c->U_tune, U, bytes, hipMemcpyDeviceToDevice, c->stream) ==
+                         hipSuccess ? batch_steps(c, c->U_tune, 1, nullptr, nullptr, cand[q])
+                                    : IDP_EHIP;                             // warm-up
+        if (rc >= 0 &&
+            hipMemcpyAsync(c->U_tune, U, bytes, hipMemcpyDeviceToDevice, c->stream) == hipSuccess &&
+            hipEventRecord(a, c->stream) == hipSuccess) {
+            rc = batch_steps(c, c->U_tune, n_steps, nullptr, nullptr, cand[q]);
+            float f = 0.f;
+            if (rc >= 0 && hipEventRecord(b, c->stream) == hipSuccess &&
+                hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&f, a, b) == hipSuccess)
+                ms = f;
+        }
+        (void)hipGetLastError();
+        if (ms_out) ms_out[q] = ms;
+        if (ms >= 0.0 && (bi < 0 || ms < bms)) { bi = q; bms = ms; }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (n_candidates) *n_candidates = nc;
+    if (bi < 0) return IDP_EHIP;
+    c->tuned = cand[bi];
+    if (best) *best = cand[bi];
+    return IDP_OK;
+}
+
 const char *idp_strerror(int code)
 {
     switch (code) {
@@ -558,6 +953,7 @@ const char *idp_strerror(int code)
     case IDP_ESTATE: return "input state not admissible (rho <= 0, internal energy <= 0 or NaN)";
     case IDP_EDT: return "dt exceeds the stage-1 bound min_i m_i/(-2 d_ii)";
     case IDP_ENOTSUP: return "option not supported";
+    case IDP_EWAIT: return "a persistent batch launch gave up waiting on a dependency";
     default: return "unknown error";
     }
 }

@@ -11,6 +11,11 @@
 //   k_pass1a  step 5   per row: U_i = U^L_i + sum lambda_i s_ij P_ij
 //   k_lim2p   step 5   per pair: candidates of pass 2 on (1 - s_ij) P_ij
 //   k_pass2   step 6   per row: final pass, SSP-RK3 combination, hold
+// Each sweep is a device function over a range of nodes, pairs or slices:
+// the kernels above launch one sweep over a whole context, and
+// k_persistent runs every sweep of many steps of a batch of independent
+// meshes in one launch, from a queue of work items with per-instance
+// dependency counts (no grid-wide barrier).
 // A row sweep gives one wavefront lane one stencil row (a SELL slice holds
 // 64 rows) and sums its columns in ascending order, sequentially, like the
 // CPU oracle, so every row reduction has one writer and a fixed order.  A
@@ -197,38 +202,48 @@ __global__ void __launch_bounds__(kBlock) k_pair_mass(StageArgs P)
 // ------------------------------------------------------------ helpers
 __global__ void k_begin(StageArgs P, int clear_status)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (clear_status) *P.status = 0;
-        *P.taumin = 0x7FF0000000000000ull;  // +inf
-    }
+    if (blockIdx.x != 0) return;
+    if (threadIdx.x == 0 && clear_status) *P.status = 0;
+    for (int k = threadIdx.x; k < P.ninst; k += blockDim.x)
+        P.taumin[k] = 0x7FF0000000000000ull;  // +inf
 }
 
-// mode 1 (stage 1 of a step): tau = dt if given (error if dt exceeds the
-// bound) else cfl * bound; mode 2: tau = dt, warn if it exceeds the bound;
-// mode 0 (stages 2, 3): warn if the held tau exceeds this stage's bound.
-__global__ void k_tau(StageArgs P, double dt_in, int mode)
+// Per instance k.  mode 1 (stage 1 of a step): tau = dt if given (error if
+// dt exceeds the bound) else cfl * bound; mode 2: tau = dt, warn if it
+// exceeds the bound; mode 0 (stages 2, 3): warn if the held tau exceeds
+// this stage's bound.
+__device__ __forceinline__ void select_tau(const StageArgs &P, int k, double bound,
+                                           double dt_in, int mode)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double bound = __longlong_as_double((long long)*P.taumin);
-    *P.bound = bound;
+    P.bound[k] = bound;
     if (mode == 1) {
         if (dt_in > 0.0 && dt_in > bound) atomicOr(P.status, kErrDt);
-        *P.tau = dt_in > 0.0 ? dt_in : P.cfl * bound;
+        P.tau[k] = dt_in > 0.0 ? dt_in : P.cfl * bound;
     } else if (mode == 2) {
-        *P.tau = dt_in;
+        P.tau[k] = dt_in;
         if (dt_in > bound) atomicOr(P.status, kWarnCfl);
     } else {
-        if (*P.tau > bound) atomicOr(P.status, kWarnCfl);
+        if (P.tau[k] > bound) atomicOr(P.status, kWarnCfl);
     }
 }
 
-// ------------------------------------------------------------- k_node
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_node(StageArgs P, const double *__restrict__ U,
-                                                 int check)
+__global__ void k_tau(StageArgs P, double dt_in, int mode)
 {
-    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= P.n) return;
+    if (blockIdx.x != 0) return;
+    for (int k = threadIdx.x; k < P.ninst; k += blockDim.x) {
+        const double bound = __longlong_as_double((long long)P.taumin[k]);
+        select_tau(P, k, bound, P.dt_inst ? P.dt_inst[k] : dt_in, mode);
+    }
+}
+
+// ----------------------------------------------------------- node pass
+// Step 0: p, c, eta/rho, v = m/rho, phi of nodes i in [i0, i0 + 256) below
+// iend; with check, flags inadmissible input.
+template <int D>
+__device__ __forceinline__ void node_sweep(const StageArgs &P, int64_t i, int64_t iend,
+                                           const double *__restrict__ U, int check)
+{
+    if (i >= iend) return;
     if (failed(P)) return;
     constexpr int NC = D + 2;
     double u[NC];
@@ -288,6 +303,7 @@ __device__ __forceinline__ void load_a(const double *__restrict__ A, NodeA<D> &o
 // per-wavefront LDS tile.  All loads are issued before the first is used.
 // Every lane of the wavefront must call it (node < 0: nothing wanted).
 constexpr int kLdsRow = kSlice + 1;   // double2 per chunk row (+1: bank skew)
+constexpr int kMaxChunks = 7;         // largest record gathered (pack B with coefficient)
 
 template <int NCH>
 __device__ __forceinline__ void gather(const double *__restrict__ base, int stride, int node,
@@ -321,17 +337,12 @@ __device__ __forceinline__ void gather(const double *__restrict__ base, int stri
     __builtin_amdgcn_wave_barrier();
 }
 
-// LDS tile of the calling wavefront (NCH chunk rows)
-#define WAVE_TILE(NCH)                                                       \
-    __shared__ double2 lds_[kBlock / kSlice][(NCH) * kLdsRow];               \
-    double2 *const lw = lds_[threadIdx.x / kSlice];
-
-// Row sweeps with gathers: every lane stays to the end of the slice's
-// longest row; lanes past the node count take node 0 and write nothing.
-#define WAVE_ROW_SETUP(P)                                                    \
-    const int64_t s_ = logical_block(P.per) * (kBlock / kSlice) +            \
-                       threadIdx.x / kSlice;                                 \
-    if (s_ >= P.nslices) return;                                             \
+// Row sweeps: one wavefront per slice s (below send); every lane stays to
+// the end of the slice's longest row; lanes past the node count take node
+// 0 and write nothing.  inst_ is the slice's instance.
+#define WAVE_ROW_SETUP(P, S, SEND)                                           \
+    const int64_t s_ = (S);                                                  \
+    if (s_ >= (SEND)) return;                                                \
     const int lane_ = threadIdx.x % kSlice;                                  \
     const int64_t r_ = s_ * kSlice + lane_;                                  \
     const int iraw_ = P.perm[r_];                                            \
@@ -339,17 +350,19 @@ __device__ __forceinline__ void gather(const double *__restrict__ base, int stri
     const int i = valid_ ? iraw_ : 0;                                        \
     const int L = valid_ ? P.row_len[r_] : 0;                                \
     const int64_t off_ = P.slice_off[s_] + lane_;                            \
+    const int inst_ = P.inst_slice ? P.inst_slice[s_] : 0;                   \
     int Lmax_ = L;                                                           \
     for (int o_ = kSlice / 2; o_ > 0; o_ /= 2) {                             \
         const int v_ = __shfl_xor(Lmax_, o_);                                \
         Lmax_ = v_ > Lmax_ ? v_ : Lmax_;                                     \
     }
 
-// Pair sweeps: lanes past the pair count take pair 0 and write nothing.
-#define WAVE_PAIR_SETUP(P)                                                   \
-    const int64_t p_ = logical_block(P.pper) * kBlock + threadIdx.x;         \
-    if (p_ - threadIdx.x % kSlice >= P.npairs) return;                       \
-    const bool valid_ = p_ < P.npairs;                                       \
+// Pair sweeps: one lane per pair p (below pend); lanes past the end take
+// pair 0 and write nothing; a wavefront with no pair leaves.
+#define WAVE_PAIR_SETUP(P, PIDX, PEND)                                       \
+    const int64_t p_ = (PIDX);                                               \
+    if (p_ - threadIdx.x % kSlice >= (PEND)) return;                         \
+    const bool valid_ = p_ < (PEND);                                         \
     const int64_t pq_ = valid_ ? p_ : 0;                                     \
     const int64_t e = P.pair_e[pq_];                                         \
     const int64_t t = P.pair_t[pq_];                                         \
@@ -378,17 +391,17 @@ __device__ __forceinline__ void load_c(const StageArgs &P, int64_t e, double *c)
     if (D == 3) c[D - 1] = P.c2[e];
 }
 
-// ------------------------------------------------------------ k_dpair
+// ------------------------------------------------------- pair viscosity
 // Step 1, once per unordered pair {i, j}: d_ij = d_ji = max of
 // lambda~(n_ij, U_i, U_j)|c_ij| and lambda~(n_ji, U_j, U_i)|c_ji|.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
+__device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, int64_t pend,
+                                            double2 *lw)
 {
-    WAVE_PAIR_SETUP(P)
+    WAVE_PAIR_SETUP(P, pidx, pend)
     if (failed(P)) return;
     constexpr int NC = D + 2;
     constexpr int NCH = (NC + 3) / 2;   // U, p, c
-    WAVE_TILE(NCH)
     double c[D], ct[D];   // c_ij, and c_ji stored at the position of c_ij
     load_c<D>(P, e, c);
     ct[0] = P.ct0[e];
@@ -427,17 +440,19 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
     P.dp[p_] = dd;
 }
 
-// ------------------------------------------------------------- k_diag
-// Step 2: d_ii = -sum_{j != i} d_ij (columns ascending), tau_i, min tau_i;
-// indicator alpha_i (Section 3.8) over all j in I(i).
+// --------------------------------------------------------- row diagonal
+// Step 2: d_ii = -sum_{j != i} d_ij (columns ascending), tau_i, the
+// instance's min tau_i (into taumin[instance]); indicator alpha_i
+// (Section 3.8) over all j in I(i).
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
+__device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int64_t send,
+                                           int with_alpha, unsigned long long *taumin,
+                                           double2 *lw)
 {
-    WAVE_ROW_SETUP(P)
+    WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
     constexpr int NC = D + 2;
     constexpr int NCH = (NC + 4 + D) / 2;   // U, p, c, eta/rho, v, phi
-    WAVE_TILE(NCH)
     const double g = P.gamma;
     NodeA<D> Ai;
     load_a<D>(P.packA + int64_t(i) * kPack, Ai);
@@ -479,7 +494,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
     P.d[ENTRY(P.diag_k[r_])] = dii;
     const double ti = P.mi[i] / (-2.0 * dii);
     P.taui[i] = ti;
-    atomicMin(P.taumin, (unsigned long long)__double_as_longlong(ti));
+    atomicMin(taumin + inst_, (unsigned long long)__double_as_longlong(ti));
     if (with_alpha) {
         double etap[NC];
         harten_entropy_derivative<D>(Ai.U, g, etap);
@@ -496,19 +511,19 @@ __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
     }
 }
 
-// -------------------------------------------------------------- k_low
+// ------------------------------------------------------ row low order
 // Step 3.  Its per-entry arithmetic (two fluxes, a division) hides the
 // latency of plain per-lane record loads better than a cooperative gather.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
+__device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int64_t send)
 {
-    WAVE_ROW_SETUP(P)
+    WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
     constexpr int NC = D + 2;
     NodeA<D> Ai;
     load_a<D>(P.packA + int64_t(i) * kPack, Ai);
     const double alpha_i = P.alpha[i];
-    const double tau = *P.tau;
+    const double tau = P.tau[inst_];
     double Fi[NC][D];
     flux<D>(Ai.U, Ai.v, Ai.p, Fi);
     double R[NC], Lw[NC];
@@ -628,19 +643,20 @@ template <int D> struct Chunks {
     static constexpr int rowB = (NC + 4) / 2;         // U^L, bounds
     static constexpr int upass = (NC + 1) / 2;        // pass-1 state
 };
+static_assert(Chunks<3>::packB <= kMaxChunks && Chunks<2>::packB <= kMaxChunks, "LDS tile");
 
-// ------------------------------------------------------------ k_lim1p
+// ------------------------------------------------------ pair limiter 1
 // Step 4, once per unordered pair: l_ij from (U^L_i, P_ij, bounds_i) and
 // l_ji from (U^L_j, P_ji, bounds_j), each evaluated exactly as its own row
 // would; s_ij = s_ji = min(l_ij, l_ji) stored at (i,j) and (j,i).
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_lim1p(StageArgs P)
+__device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int64_t pend,
+                                           double2 *lw)
 {
-    WAVE_PAIR_SETUP(P)
+    WAVE_PAIR_SETUP(P, pidx, pend)
     if (failed(P)) return;
     constexpr int NC = D + 2;
     using CH = Chunks<D>;
-    WAVE_TILE(CH::packB)
     const double dL = P.dp[pq_], m = P.mp[pq_];
     NodeB<D> Bi, Bj;
     double rec[2 * CH::packB], Wi[2 * CH::rowB], Wj[2 * CH::rowB];
@@ -666,23 +682,23 @@ __global__ void __launch_bounds__(kBlock) k_lim1p(StageArgs P)
     P.l1p[p_] = sv;
 }
 
-// ----------------------------------------------------------- k_pass1a
+// -------------------------------------------------------- row pass 1
 // Step 5, first half: U_i = U^L_i + sum_{j != i} lambda_i s_ij P_ij.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_pass1a(StageArgs P)
+__device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, int64_t send,
+                                            double2 *lw)
 {
-    WAVE_ROW_SETUP(P)
+    WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
     constexpr int NC = D + 2;
     using CH = Chunks<D>;
-    WAVE_TILE(CH::packBrow)
     NodeB<D> Bi;
     load_b<D>(P.packB + int64_t(i) * kPack, Bi);
     const double *W = P.rowB + int64_t(i) * kRowB;
     double V[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) V[r] = W[r];
-    const double tau = *P.tau;
+    const double tau = P.tau[inst_];
     const double lam = P.lam[i];
     const double coef = tau / (lam * Bi.m);
     int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
@@ -709,17 +725,17 @@ __global__ void __launch_bounds__(kBlock) k_pass1a(StageArgs P)
     for (int r = 0; r < NC; ++r) Up[r] = V[r];
 }
 
-// ------------------------------------------------------------ k_lim2p
+// ------------------------------------------------------ pair limiter 2
 // Step 5, second half, once per unordered pair: candidates of pass 2 on the
 // rescaled directions (1 - s_ij) P_ij from the pass-1 states.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
+__device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int64_t pend,
+                                           double2 *lw)
 {
-    WAVE_PAIR_SETUP(P)
+    WAVE_PAIR_SETUP(P, pidx, pend)
     if (failed(P)) return;
     constexpr int NC = D + 2;
     using CH = Chunks<D>;
-    WAVE_TILE(CH::packB)
     const double dL = P.dp[pq_], m = P.mp[pq_];
     const double l = P.l1p[pq_];
     NodeB<D> Bi, Bj;
@@ -748,19 +764,19 @@ __global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
     P.l2[t] = sv;
 }
 
-// ------------------------------------------------------------ k_pass2
+// -------------------------------------------------------- row pass 2
 // Step 6: U_i += sum_{j != i} lambda_i s2_ij (1 - s1_ij) P_ij, then
 // mode 0: out = E(U); 1: out = E (stage 1); 2: out = U0 + 1/4 (E - U0);
 // 3: out = U0 + 2/3 (E - U0); modes 1-3 keep held nodes at U0.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0, double *out,
-                                                  int mode)
+__device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, int64_t send,
+                                            const double *U0, double *out, int mode,
+                                            double2 *lw)
 {
-    WAVE_ROW_SETUP(P)
+    WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
     constexpr int NC = D + 2;
     using CH = Chunks<D>;
-    WAVE_TILE(CH::packBrow)
     NodeB<D> Bi;
     load_b<D>(P.packB + int64_t(i) * kPack, Bi);
     double V[NC];
@@ -768,7 +784,7 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
 #pragma unroll
     for (int r = 0; r < NC; ++r) V[r] = Up[r];
     if (P.passes >= 2) {
-        const double tau = *P.tau;
+        const double tau = P.tau[inst_];
         const double lam = P.lam[i];
         const double coef = tau / (lam * Bi.m);
         int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
@@ -819,6 +835,188 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
     for (int r = 0; r < NC; ++r) o[r] = w[r];
 }
 
+// ------------------------------------------------- one launch per sweep
+// Row sweeps: wavefront w of logical block b takes slice 4 b + w.
+#define ROW_SLICE(P) (logical_block(P.per) * (kBlock / kSlice) + threadIdx.x / kSlice)
+#define PAIR_INDEX(P) (logical_block(P.pper) * kBlock + threadIdx.x)
+#define WAVE_LDS(NCH)                                                        \
+    __shared__ double2 lds_[kBlock / kSlice][(NCH) * kLdsRow];               \
+    double2 *const lw = lds_[threadIdx.x / kSlice];
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_node(StageArgs P, const double *__restrict__ U,
+                                                 int check)
+{
+    node_sweep<D>(P, int64_t(blockIdx.x) * kBlock + threadIdx.x, P.n, U, check);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
+{
+    WAVE_LDS((D + 5) / 2)
+    dpair_sweep<D>(P, PAIR_INDEX(P), P.npairs, lw);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
+{
+    WAVE_LDS((D + 6 + D) / 2)
+    diag_sweep<D>(P, ROW_SLICE(P), P.nslices, with_alpha, P.taumin, lw);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
+{
+    low_sweep<D>(P, ROW_SLICE(P), P.nslices);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_lim1p(StageArgs P)
+{
+    WAVE_LDS(Chunks<D>::packB)
+    lim1_sweep<D>(P, PAIR_INDEX(P), P.npairs, lw);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_pass1a(StageArgs P)
+{
+    WAVE_LDS(Chunks<D>::packBrow)
+    pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, lw);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
+{
+    WAVE_LDS(Chunks<D>::packB)
+    lim2_sweep<D>(P, PAIR_INDEX(P), P.npairs, lw);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0, double *out,
+                                                  int mode)
+{
+    WAVE_LDS(Chunks<D>::packBrow)
+    pass2_sweep<D>(P, ROW_SLICE(P), P.nslices, U0, out, mode, lw);
+}
+
+// ------------------------------------------------ persistent batch launch
+// Every wavefront is an independent worker that pops work items from one
+// queue in (stage, sweep, instance) order.  An item of sweep s of instance
+// k waits until every item of the earlier sweeps of that instance's stage
+// (and the instance's tau update) has completed; items only ever wait on
+// items earlier in the queue, which running workers hold, so the queue
+// always drains, whatever the number of resident wavefronts.  The last
+// diagonal item of an instance to complete also selects the instance's tau
+// (the kernel-launch path's k_tau).  A wait that outlives kWaitPolls polls
+// sets kErrWait and gives up; every later item then skips its work, so
+// every wavefront reaches the end.  All control flow of the worker loop is
+// wavefront-uniform (values through readfirstlane, atomics issued by every
+// lane with the increment on lane 0 only): there is no block barrier and
+// no lane-divergent region around the queue, so the compiler cannot split
+// the loop between lanes.
+constexpr unsigned kWaitPolls = 1u << 22;
+constexpr unsigned long long kPosInf = 0x7FF0000000000000ull;
+
+__device__ __forceinline__ uint32_t uniform32(uint32_t v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint64_t u = uint64_t(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(u >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ unsigned load_done(unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_batch_init(StageArgs P, BatchArgs B, int clear_status)
+{
+    if (blockIdx.x != 0) return;
+    if (threadIdx.x == 0) {
+        *B.head = 0;
+        if (clear_status) *P.status = 0;
+    }
+    for (int k = threadIdx.x; k < P.ninst; k += blockDim.x) {
+        B.done[k] = 0;
+        B.taumin2[k] = kPosInf;
+        B.taumin2[P.ninst + k] = kPosInf;
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_persistent(StageArgs P, BatchArgs B)
+{
+    __shared__ double2 lds_[kBlock / kSlice][kMaxChunks * kLdsRow];
+    double2 *const lw = lds_[threadIdx.x / kSlice];
+    const int lane = threadIdx.x % kSlice;
+    const unsigned one = lane == 0 ? 1u : 0u;   // per-wavefront increments
+    for (;;) {
+        const int64_t q = uniform64(int64_t(atomicAdd(B.head, (unsigned long long)one)));
+        if (q >= B.total_items) return;
+        const int64_t sg = q / B.items_per_stage;   // stage index of the whole run
+        const int64_t r = q - sg * B.items_per_stage;
+        int s = 0;
+        while (s + 1 < kSweeps && B.sweep_off[s + 1] <= r) ++s;
+        const int k = int(uniform32(uint32_t(B.item_inst[r])));
+        const int64_t first = uniform64(B.item_first[r]);
+        const int64_t *pre = B.pre + int64_t(k) * (kSweeps + 1);
+        const unsigned base = uniform32(unsigned(sg * pre[kSweeps]));
+        const unsigned need = base + uniform32(unsigned(pre[s]));
+        for (unsigned polls = 0;;) {
+            if (uniform32(load_done(B.done + k)) >= need) break;
+            if (++polls > kWaitPolls) {
+                atomicOr(P.status, kErrWait);
+                break;
+            }
+            if ((polls & 1023u) == 0 &&
+                (uniform32(__hip_atomic_load(P.status, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)) & kErrWait))
+                break;
+            __builtin_amdgcn_s_sleep(8);
+        }
+        __threadfence();   // acquire: the stores of the items waited for
+        const int stage = int(sg % 3);
+        const int64_t *end = B.unit_end + int64_t(k) * 3;   // nodes, pairs, slices
+        const int64_t e0 = uniform64(end[0]), e1 = uniform64(end[1]), e2 = uniform64(end[2]);
+        for (int u = 0; u < B.tile; ++u) {
+            const int64_t lin = first + int64_t(u) * kSlice + lane;   // node, pair
+            const int64_t sl = first + u;                               // slice
+            switch (s) {
+            case 0: node_sweep<D>(P, lin, e0, stage == 0 ? B.U : B.U1,
+                                  stage == 0 ? B.check : 0); break;
+            case 1: dpair_sweep<D>(P, lin, e1, lw); break;
+            case 2: diag_sweep<D>(P, sl, e2, 1, B.taumin2 + (sg & 1) * P.ninst, lw); break;
+            case 3: low_sweep<D>(P, sl, e2); break;
+            case 4: lim1_sweep<D>(P, lin, e1, lw); break;
+            case 5: pass1_sweep<D>(P, sl, e2, lw); break;
+            case 6: lim2_sweep<D>(P, lin, e1, lw); break;
+            default: pass2_sweep<D>(P, sl, e2, B.U, stage == 2 ? B.U : B.U1, stage + 1, lw);
+            }
+        }
+        __threadfence();   // release: this item's stores before its completion count
+        const unsigned old = uniform32(atomicAdd(B.done + k, one));
+        if (s == 2 && old + 1 == base + unsigned(pre[3]) - 1) {
+            // every diagonal item of the instance is in: select its tau (every
+            // lane writes the same values)
+            __threadfence();
+            const unsigned long long bits = __hip_atomic_load(
+                B.taumin2 + (sg & 1) * P.ninst + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const double bound = __longlong_as_double((long long)uniform64(int64_t(bits)));
+            select_tau(P, k, bound, P.dt_inst ? P.dt_inst[k] : 0.0, stage == 0 ? 1 : 0);
+            if (stage == 0) B.dt_rec[(sg / 3) * P.ninst + k] = P.tau[k];
+            B.taumin2[((sg + 1) & 1) * P.ninst + k] = kPosInf;   // next stage's slot
+            __threadfence();
+            (void)atomicAdd(B.done + k, one);
+        }
+    }
+}
+
 // ------------------------------------------------------- device math
 __global__ void k_math(int kind, int64_t n, const double *x, const double *y, double *out)
 {
@@ -855,12 +1053,12 @@ void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
 
 void launch_begin(const StageArgs &P, hipStream_t st, int clear_status)
 {
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, P, clear_status);
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBlock), 0, st, P, clear_status);
 }
 
 void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode)
 {
-    hipLaunchKernelGGL(k_tau, dim3(1), dim3(64), 0, st, P, dt_in, mode);
+    hipLaunchKernelGGL(k_tau, dim3(1), dim3(kBlock), 0, st, P, dt_in, mode);
 }
 
 void launch_node(const StageArgs &P, hipStream_t st, const double *U, int check)
@@ -893,6 +1091,29 @@ void launch_lim2p(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_lim2p, grid_p
 void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out, int mode)
 {
     LAUNCH_D(k_pass2, grid_rows(P), P, U0, out, mode);
+}
+
+void launch_batch_init(const StageArgs &P, const BatchArgs &B, hipStream_t st, int clear_status)
+{
+    hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(kBlock), 0, st, P, B, clear_status);
+}
+
+void launch_persistent(const StageArgs &P, const BatchArgs &B, hipStream_t st, int grid)
+{
+    LAUNCH_D(k_persistent, grid, P, B);
+}
+
+int persistent_blocks_per_cu(int dim)
+{
+    int nb = 0;
+    hipError_t e = dim == 2
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<2>, kBlock, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<3>, kBlock, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return nb > 0 ? nb : 1;
 }
 
 void launch_math(hipStream_t st, int kind, int64_t n, const double *x, const double *y,

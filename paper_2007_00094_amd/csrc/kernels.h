@@ -22,7 +22,8 @@ constexpr int kRowU = 8;      // doubles per node: state after pass 1
 constexpr int kErrState = 1;
 constexpr int kErrDt = 2;
 constexpr int kWarnCfl = 4;
-constexpr int kErrMask = kErrState | kErrDt;
+constexpr int kErrWait = 8;     // a persistent launch gave up waiting on a dependency
+constexpr int kErrMask = kErrState | kErrDt | kErrWait;
 
 // Everything a kernel needs, passed by value.
 struct StageArgs {
@@ -52,15 +53,47 @@ struct StageArgs {
     double *d;                  // [sell] d_ij, diagonal d_ii
     double *l1, *l2;            // [sell] min(l_ij, l_ji) of pass 1, 2
     double *packA, *alpha, *packB, *rowB, *upass, *taui;
-    unsigned long long *taumin; // bits of min_i m_i/(-2 d_ii)
-    double *tau, *bound;
+    // instances: a batch of independent meshes shares one context; their
+    // slices, pairs and nodes are contiguous and never mixed
+    int ninst;
+    const int32_t *inst_slice;  // [nslices] instance of each slice (null: one)
+    unsigned long long *taumin; // [ninst] bits of min_i m_i/(-2 d_ii)
+    double *tau, *bound;        // [ninst]
+    const double *dt_inst;      // [ninst] per-instance dt of a batch call, or null
     int *status;
+};
+
+// One persistent launch over a batch: a queue of work items, each a few
+// consecutive wavefront units (64 nodes, 64 pairs or 1 slice) of one sweep
+// of one instance, in (stage, sweep, instance) order; an item starts once
+// every item of the previous sweep of its instance has completed.
+constexpr int kSweeps = 8;      // node, dpair, diag, low, lim1p, pass1a, lim2p, pass2
+struct BatchArgs {
+    int nsteps;
+    int tile;                   // wavefront units per work item
+    int check;                  // admissibility check of stage-1 inputs
+    int64_t items_per_stage;
+    int64_t total_items;
+    int64_t sweep_off[kSweeps + 1];   // item offsets of the sweeps inside a stage
+    const int32_t *item_inst;   // [items_per_stage] instance of each item
+    const int64_t *item_first;  // [items_per_stage] first node/pair/slice of each item
+    const int64_t *pre;         // [ninst][kSweeps + 1] completions required before each
+                                // sweep inside a stage; [kSweeps]: completions per stage
+    const int64_t *unit_end;    // [ninst][3] end of the instance's nodes, pairs, slices
+    unsigned long long *taumin2;  // [2][ninst] (stages alternate)
+    unsigned int *done;         // [ninst] completed items (and tau updates)
+    unsigned long long *head;   // next item
+    double *U, *U1;             // state and the stage scratch, concatenated
+    double *dt_rec;             // [nsteps][ninst] tau of every step
 };
 
 void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
                      const int32_t *cells, const int64_t *nc_ptr,
                      const int32_t *nc_list, const double gx[3], int *err);
 void launch_begin(const StageArgs &P, hipStream_t st, int clear_status);
+void launch_batch_init(const StageArgs &P, const BatchArgs &B, hipStream_t st, int clear_status);
+void launch_persistent(const StageArgs &P, const BatchArgs &B, hipStream_t st, int grid);
+int persistent_blocks_per_cu(int dim);
 void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode);
 void launch_node(const StageArgs &P, hipStream_t st, const double *U, int check);
 void launch_dpair(const StageArgs &P, hipStream_t st);

@@ -260,6 +260,22 @@ def workload(name: str, n: int | None = None, order: str | None = None):
     raise ValueError(f"unknown workload {name!r}")
 
 
+def batch_workload(count: int = 64, smin: int = 33, smax: int = 513, seed0: int = 100,
+                   order: str = "morton"):
+    """Independent 2D four-quadrant problems of uneven sizes: instance k
+    draws its side s_k log-uniformly in [smin, smax] from seed seed0 + k,
+    and uses the same seed for its jitter and its four states.  Returns a
+    list of (mesh, U0)."""
+    out = []
+    for k in range(count):
+        seed = seed0 + k
+        rng = np.random.default_rng(seed)
+        side = int(round(math.exp(rng.uniform(math.log(smin), math.log(smax)))))
+        m = q1_grid(side, 2, 0.2, seed=seed, order=order)
+        out.append((m, ic_four_quadrant(m.coords, random_quadrant_states(seed))))
+    return out
+
+
 # --------------------------------------------------------------- patches
 
 class PatchExtractor:

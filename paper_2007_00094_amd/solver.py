@@ -1,4 +1,5 @@
-"""Python face of the library: a Solver over one Q1 mesh.
+"""Python face of the library: a Solver over one Q1 mesh, a BatchSolver
+over many independent meshes.
 
 State tensors are torch.float64 on the current HIP device, [n_nodes, dim+2]
 contiguous, in the caller's node order; calls are ordered on the torch
@@ -154,3 +155,111 @@ class Solver:
             self._h, int(kind), int(x.numel()), C.c_void_p(x.data_ptr()), yp,
             C.c_void_p(out.data_ptr())))
         return out
+
+
+class BatchSolver:
+    """Many independent Q1 meshes advanced together, each with its own tau.
+
+    The state is one contiguous float64 device tensor [N, dim+2]; instance k
+    owns rows offsets[k]:offsets[k+1] (its own node order).  Results are
+    bit-identical to a Solver per instance.
+    """
+
+    def __init__(self, meshes, *, dirichlet=None, gamma=1.4, cfl=0.5, passes=2,
+                 newton_max=2, newton_tol=1e-10, stream=None):
+        torch = _require_torch_gpu()
+        meshes = list(meshes)
+        if not meshes:
+            raise ValueError("empty batch")
+        self.dim = int(meshes[0].dim)
+        if any(int(m.dim) != self.dim for m in meshes):
+            raise ValueError("every instance must have the same dimension")
+        self.nc = self.dim + 2
+        self.count = len(meshes)
+        L = capi.lib()
+        p = capi.idp_params()
+        capi.check("idp_default_params", L.idp_default_params(C.byref(p), self.dim))
+        p.gamma, p.cfl = float(gamma), float(cfl)
+        p.limiter_passes, p.newton_max_iter = int(passes), int(newton_max)
+        p.newton_tol = float(newton_tol)
+        self.params = p
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        K = self.count
+        self._keep = []
+        co = (capi._dp * K)()
+        ce = (capi._i64p * K)()
+        hd = (capi._u8p * K)()
+        nn = (C.c_int64 * K)()
+        ncell = (C.c_int64 * K)()
+        for k, m in enumerate(meshes):
+            x = np.ascontiguousarray(m.coords, dtype=np.float64)
+            c = np.ascontiguousarray(m.cells, dtype=np.int64)
+            d = m.boundary if dirichlet is None else dirichlet[k]
+            d = np.ascontiguousarray(d, dtype=np.uint8) if d is not None else None
+            self._keep += [x, c, d]
+            co[k] = x.ctypes.data_as(capi._dp)
+            ce[k] = c.ctypes.data_as(capi._i64p)
+            hd[k] = d.ctypes.data_as(capi._u8p) if d is not None else None
+            nn[k] = x.shape[0]
+            ncell[k] = c.shape[0]
+        h = C.c_void_p()
+        rc = L.idp_create_batch(C.byref(h), C.byref(p), K, nn, co, ncell, ce, hd,
+                                C.c_void_p(self._stream.cuda_stream))
+        self._keep = None
+        capi.check("idp_create_batch", rc)
+        self._h = h
+        off = np.empty(K + 1, np.int64)
+        capi.check("idp_batch_info", L.idp_batch_info(h, None, off.ctypes.data_as(capi._i64p)))
+        self.offsets = off
+        self.n = int(off[-1])
+        nz, nb = C.c_int64(), C.c_size_t()
+        capi.check("idp_info", L.idp_info(h, None, C.byref(nz), C.byref(nb)))
+        self.nnz = int(nz.value)
+        self.device_bytes = int(nb.value)
+
+    close = Solver.close
+    __del__ = Solver.__del__
+    _u = Solver._u
+    set_timing = Solver.set_timing
+    kernel_times = Solver.kernel_times
+
+    @staticmethod
+    def schedule(kind, tile=0):
+        """kind: "launches" or "persistent"."""
+        k = {"launches": capi.IDP_SCHED_LAUNCHES, "persistent": capi.IDP_SCHED_PERSISTENT}[kind]
+        return capi.idp_schedule(k, int(tile))
+
+    def steps(self, U, n_steps: int, dt=None, schedule=None):
+        """n_steps SSP-RK3 steps of every instance in place.  dt: None (each
+        instance's CFL tau at every step) or one tau per instance.  Returns
+        (tau [n_steps, count], status)."""
+        K = self.count
+        used = np.zeros((max(int(n_steps), 0), K))
+        dta = None
+        if dt is not None:
+            dta = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (K,)))
+        rc = capi.lib().idp_batch_steps(
+            self._h, self._u(U), int(n_steps),
+            dta.ctypes.data_as(capi._dp) if dta is not None else None,
+            used.ctypes.data_as(capi._dp),
+            C.byref(schedule) if schedule is not None else None)
+        capi.check("idp_batch_steps", rc)
+        return used, rc
+
+    def max_dt(self, U) -> np.ndarray:
+        out = np.empty(self.count)
+        capi.check("idp_batch_max_dt", capi.lib().idp_batch_max_dt(
+            self._h, self._u(U), out.ctypes.data_as(capi._dp)))
+        return out
+
+    def tune(self, U, n_steps: int = 2):
+        """Time every candidate schedule on a scratch copy of U; the fastest
+        becomes the default.  Returns (best schedule, {name: ms})."""
+        best = capi.idp_schedule()
+        ms = np.zeros(16)
+        nc = C.c_int()
+        capi.check("idp_batch_tune", capi.lib().idp_batch_tune(
+            self._h, self._u(U), int(n_steps), C.byref(best), ms.ctypes.data_as(capi._dp),
+            C.byref(nc)))
+        names = ["launches"] + [f"persistent_tile{t}" for t in (4, 16, 32, 64, 128, 256)]
+        return best, {names[i]: float(ms[i]) for i in range(nc.value)}

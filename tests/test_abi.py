@@ -58,3 +58,27 @@ def test_create_rejects_bad_params_before_any_device_call(field, value, code):
     assert L.idp_create(None, C.byref(p), 4, xy, 1, cells, None, None) == capi.IDP_EINVAL
     assert L.idp_step(None, None, 0.0, None) == capi.IDP_EINVAL
     assert L.idp_max_dt(None, None, None) == capi.IDP_EINVAL
+
+
+def test_create_batch_rejects_bad_arguments_before_any_device_call():
+    L = capi.lib()
+    p = capi.idp_params()
+    L.idp_default_params(C.byref(p), 2)
+    h = C.c_void_p()
+    xy = (C.c_double * 8)()
+    cells = (C.c_int64 * 4)(0, 1, 2, 3)
+    co = (capi._dp * 1)(C.cast(xy, capi._dp))
+    ce = (capi._i64p * 1)(C.cast(cells, capi._i64p))
+    nn = (C.c_int64 * 1)(4)
+    nc = (C.c_int64 * 1)(1)
+    assert L.idp_create_batch(C.byref(h), C.byref(p), 0, nn, co, nc, ce, None, None) == capi.IDP_EINVAL
+    assert L.idp_create_batch(None, C.byref(p), 1, nn, co, nc, ce, None, None) == capi.IDP_EINVAL
+    assert L.idp_create_batch(C.byref(h), C.byref(p), 1, None, co, nc, ce, None, None) == capi.IDP_EINVAL
+    bad = (C.c_int64 * 1)(0)
+    assert L.idp_create_batch(C.byref(h), C.byref(p), 1, bad, co, nc, ce, None, None) == capi.IDP_EINVAL
+    p.cfl = 2.0
+    assert L.idp_create_batch(C.byref(h), C.byref(p), 1, nn, co, nc, ce, None, None) == capi.IDP_EINVAL
+    assert L.idp_batch_steps(None, None, 1, None, None, None) == capi.IDP_EINVAL
+    assert L.idp_batch_tune(None, None, 1, None, None, None) == capi.IDP_EINVAL
+    assert L.idp_batch_max_dt(None, None, None) == capi.IDP_EINVAL
+    assert L.idp_batch_info(None, None, None) == capi.IDP_EINVAL
