@@ -226,6 +226,18 @@ def ic_smooth_blobs(coords: np.ndarray, seed: int = 2,
                      np.ones_like(rho), gamma)
 
 
+def ic_isothermal_blobs(coords: np.ndarray, seed: int = 2,
+                        gamma: float = GAMMA) -> np.ndarray:
+    """rho = 1 + 0.1 * (eight seeded Gaussians in [0.2,0.8]^d), p = rho
+    (background pressure 1, uniform temperature), u = 0.  The blobs release
+    acoustic waves; with a uniform pressure the state would be steady, and
+    with p = rho^gamma the specific entropy would be uniform, which puts
+    every limiter decision on the entropy bound itself."""
+    dim = coords.shape[1]
+    rho = 1.0 + 0.1 * gaussian_blobs(coords, seed, lo=0.2, hi=0.8)
+    return conserved(rho, np.zeros((coords.shape[0], dim)), rho.copy(), gamma)
+
+
 def ic_uniform(n_nodes: int, dim: int, rho=1.0, vel=None, p=1.0,
                gamma: float = GAMMA) -> np.ndarray:
     v = np.zeros((n_nodes, dim)) if vel is None else np.tile(
@@ -242,6 +254,7 @@ def workload(name: str, n: int | None = None, order: str | None = None):
     sphere_3d        : 3D 65^3 jittered, random order, spherical shock tube
     mach3_3d         : 3D 257^3 jittered, Morton order, Mach 3 + blobs
     smooth_3d        : 3D 65^3 jittered, smooth Gaussian density, at rest
+    adjoint_3d       : 3D 65^3 jittered, isothermal Gaussian blobs, at rest
     """
     if name == "four_quadrant_2d":
         m = q1_grid(n or 33, 2, 0.2, seed=0, order=order or "lex")
@@ -257,6 +270,9 @@ def workload(name: str, n: int | None = None, order: str | None = None):
     if name == "smooth_3d":
         m = q1_grid(n or 65, 3, 0.2, seed=0, order=order or "lex")
         return m, ic_smooth_blobs(m.coords, seed=2)
+    if name == "adjoint_3d":
+        m = q1_grid(n or 65, 3, 0.2, seed=0, order=order or "morton")
+        return m, ic_isothermal_blobs(m.coords, seed=2)
     raise ValueError(f"unknown workload {name!r}")
 
 
