@@ -24,7 +24,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 KERNEL_SOURCES = ["paper_2007_00094_amd/csrc/idp_kernels.hip",
                   "paper_2007_00094_amd/csrc/idp_device.h",
-                  "paper_2007_00094_amd/csrc/kernels.h"]
+                  "paper_2007_00094_amd/csrc/kernels.h",
+                  "paper_2007_00094_amd/csrc/sweep_common.h"]
 COUNTERS = os.path.join(ROOT, "profiles", "counters_mach3_257_morton.md")
 FP64_VECTOR_PEAK = 78.6e12   # MI355X FP64 vector, flop/s
 

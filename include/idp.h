@@ -220,6 +220,57 @@ int idp_batch_max_dt(idp_ctx *ctx, const double *U_dev, double *dt_out);
 int idp_batch_tune(idp_ctx *ctx, const double *U_dev, int n_steps, idp_schedule *best,
                    double *ms_out, int *n_candidates);
 
+/* ------------------------------------------------------------ adjoint
+ * Reverse mode of the scheme with a fixed time step (the tau of every stage
+ * given), for one mesh (IDP_ENOTSUP on a batch context or with
+ * newton_max_iter > 8).  Every max, min, clamp and branch of the forward is
+ * differentiated on the branch the forward took (at an exact tie, the
+ * branch its comparison picks); the limiter's Newton iterations (Alg. 2/3)
+ * are differentiated as unrolled.  Cotangent arrays are device [n][nc],
+ * like states.  All calls synchronise; they return IDP_OK, IDP_WARN_CFL
+ * (some tau exceeded a stage's bound), IDP_ESTATE, IDP_EINVAL, IDP_ENOMEM
+ * or IDP_EHIP.                                                           */
+
+/* Ubar = (dE/dU)^T Ebar for the forward-Euler update E with step tau
+ * (Alg. 1; idp_euler_stage's map).  U_dev, Ebar_dev, Ubar_dev distinct.  */
+int idp_euler_stage_vjp(idp_ctx *ctx, const double *U_dev, double tau,
+                        const double *Ebar_dev, double *Ubar_dev);
+
+/* Ubar = (dS/dU)^T Ubar_next for one SSP-RK3 step S (eq. ssprk3, held
+ * nodes included) from U_dev with step dt > 0.  Arrays distinct.        */
+int idp_step_vjp(idp_ctx *ctx, const double *U_dev, double dt,
+                 const double *Ubar_next_dev, double *Ubar_dev);
+
+/* n_steps SSP-RK3 steps in place on U_dev with the steps dt[s] (host
+ * [n_steps], each > 0), keeping the state before steps 0, every,
+ * 2 every, ... in device memory owned by the context (checkpoints).     */
+int idp_forward_checkpoints(idp_ctx *ctx, double *U_dev, int n_steps,
+                            const double *dt, int every);
+
+/* Ubar0 = (d U_final / d U_0)^T Ubar_final for the steps of the last
+ * idp_forward_checkpoints call (same n_steps, dt, every): each segment of
+ * `every` steps is recomputed from its checkpoint, then stepped backwards
+ * with idp_step_vjp.  IDP_EINVAL if the arguments differ from that call. */
+int idp_adjoint_checkpoints(idp_ctx *ctx, int n_steps, const double *dt, int every,
+                            const double *Ubar_final_dev, double *Ubar0_dev);
+
+/* Host copy of a total cotangent of the last stage VJP run (for tests):
+ *  IDP_ADJ_UL     U^L_i's [n][nc]      IDP_ADJ_R      R_i's [n][nc]
+ *  IDP_ADJ_BOUNDS (rho_min, rho_max, phi_min)'s [n][3]
+ *  IDP_ADJ_ALPHA  alpha_i's [n]
+ *  IDP_ADJ_D      d_ij's [nnz] in CSR order, at the entry (i, j) with
+ *                 i < j of each pair (the symmetric entry and the
+ *                 diagonal hold 0)
+ *  IDP_ADJ_P      P_ij's [nnz][nc] in CSR order (diagonal: 0).
+ * Synchronises.                                                          */
+#define IDP_ADJ_UL 0
+#define IDP_ADJ_R 1
+#define IDP_ADJ_BOUNDS 2
+#define IDP_ADJ_ALPHA 3
+#define IDP_ADJ_D 4
+#define IDP_ADJ_P 5
+int idp_debug_adjoint(idp_ctx *ctx, int what, double *host_out);
+
 /* Text of a return code.                                                 */
 const char *idp_strerror(int code);
 

@@ -192,8 +192,10 @@ class Reference:
         return tL
 
     # ------------------------------------------------------------- stage
-    def stage(self, U, tau):
-        """E(U): one limited forward-Euler update with step tau (Alg. 1)."""
+    def stage(self, U, tau, keep=None):
+        """E(U): one limited forward-Euler update with step tau (Alg. 1).
+        keep (a dict, optional) receives the intermediates (U^L, R, the
+        bounds, alpha, d per off-diagonal entry), gradients retained."""
         D, n, g = self.dim, self.n, self.g
         I, J, Io, Jo, To = self.I, self.J, self.Io, self.Jo, self.To
         A = self.node(U)
@@ -229,12 +231,20 @@ class Reference:
         rmin = rho.scatter_reduce(0, Io, rbar, "amin", include_self=True)
         rmax = rho.scatter_reduce(0, Io, rbar, "amax", include_self=True)
         phimin = A["phi"].scatter_reduce(0, Io, A["phi"][Jo], "amin", include_self=True)
+        if keep is not None:
+            for k, v in (("UL", UL), ("R", R), ("rmin", rmin), ("rmax", rmax),
+                         ("phimin", phimin), ("alpha", alpha), ("d", d)):
+                v.retain_grad()
+                keep[k] = v
         # step 4: directions (eq. def-p) and the first pass
         coef = tau / (self.lam[Io] * self.mi[Io])
         bij = -self.mo / self.mi[Jo]
         bji = -self.mo / self.mi[Io]
         P = coef[:, None] * (bij[:, None] * R[Jo] - bji[:, None] * R[Io] + (dH - d)[:, None] * dU)
         lamo = self.lam[Io][:, None]
+        if keep is not None:
+            P.retain_grad()
+            keep["P"] = P
         l1 = self.limiter(UL[Io], P, rmin[Io], rmax[Io], phimin[Io])
         s1 = torch.where(l1 < l1[To], l1, l1[To])
         Up = UL + torch.zeros(n, self.nc, dtype=_T).index_add(0, Io, lamo * s1[:, None] * P)

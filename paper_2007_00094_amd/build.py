@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
     o = os.path.join(OUT_DIR, "graph.o")
     _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "graph.cpp"), "-o", o], verbose)
     objs.append(o)
-    for src in ("idp_kernels.hip", "idp_capi.hip"):
+    for src in ("idp_kernels.hip", "idp_adjoint.hip", "idp_capi.hip"):
         o = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

@@ -77,6 +77,11 @@ SIGNATURES = {
     "idp_batch_max_dt": (C.c_int, [_vp, _vp, _dp]),
     "idp_batch_tune": (C.c_int, [_vp, _vp, C.c_int, C.POINTER(idp_schedule), _dp,
                                  C.POINTER(C.c_int)]),
+    "idp_euler_stage_vjp": (C.c_int, [_vp, _vp, C.c_double, _vp, _vp]),
+    "idp_step_vjp": (C.c_int, [_vp, _vp, C.c_double, _vp, _vp]),
+    "idp_forward_checkpoints": (C.c_int, [_vp, _vp, C.c_int, _dp, C.c_int]),
+    "idp_adjoint_checkpoints": (C.c_int, [_vp, C.c_int, _dp, C.c_int, _vp, _vp]),
+    "idp_debug_adjoint": (C.c_int, [_vp, C.c_int, _dp]),
     "idp_strerror": (C.c_char_p, [C.c_int]),
     "idp_destroy": (None, [_vp]),
 }

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/idp.h"
+#include "adjoint.h"
 #include "graph.h"
 #include "kernels.h"
 
@@ -76,6 +77,15 @@ struct idp_ctx {
     std::vector<PersistTables> tables;
     idp_schedule tuned{IDP_SCHED_LAUNCHES, 0};
     double *U_tune = nullptr;
+    // adjoint
+    idp::AdjArgs A{};
+    bool adj_ready = false;
+    double *Estage = nullptr, *U2 = nullptr, *Eb = nullptr, *acc = nullptr;
+    double *bar[3] = {nullptr, nullptr, nullptr};
+    double *ckpt = nullptr;          // [slots][n][nc]
+    int64_t ckpt_slots = 0;
+    int ck_steps = -1, ck_every = 0;
+    std::vector<double> ck_dt;
     // timing
     bool timing = false;
     std::vector<Pending> pending;
@@ -715,6 +725,232 @@ int idp_device_math(idp_ctx *c, int kind, int64_t n, const double *x, const doub
     if (n == 0) return IDP_OK;
     idp::launch_math(c->stream, kind, n, x, y, out);
     return sync(c);
+}
+
+}  // extern "C"
+
+namespace {
+
+int adj_setup(idp_ctx *c)
+{
+    if (c->adj_ready) return IDP_OK;
+    const int nc = c->prm.dim + 2;
+    const int64_t n = c->n, S = c->sell_size, np = c->P.npairs;
+    idp::AdjArgs &A = c->A;
+    double *Eb = nullptr;
+    int e = IDP_OK;
+#define ADJ_ALLOC(ptr, count) if ((e = dalloc(c, &(ptr), (count))) != IDP_OK) return e
+    ADJ_ALLOC(A.Upb, n * nc);
+    ADJ_ALLOC(A.bndb, n * 3);
+    ADJ_ALLOC(A.Ub3, n * nc);
+    ADJ_ALLOC(A.Ub2, n * nc);
+    ADJ_ALLOC(A.alb, n);
+    ADJ_ALLOC(A.sb1, S);
+    ADJ_ALLOC(A.sb2, S);
+    ADJ_ALLOC(A.Pb, S * nc);
+    ADJ_ALLOC(A.cnode, S * (nc + 3));
+    ADJ_ALLOC(A.cR, S * nc);
+    ADJ_ALLOC(A.cU, S * nc);
+    ADJ_ALLOC(A.cal, S);
+    ADJ_ALLOC(A.dbp, np);
+    ADJ_ALLOC(A.cUj, S * nc);
+    ADJ_ALLOC(A.cUj2, S * nc);
+    ADJ_ALLOC(A.calj, S);
+    ADJ_ALLOC(A.db3, S);
+    ADJ_ALLOC(A.ULt, n * nc);
+    ADJ_ALLOC(A.Rt, n * nc);
+    ADJ_ALLOC(A.bndt, n * 3);
+    ADJ_ALLOC(A.alt, n);
+    ADJ_ALLOC(c->Estage, n * nc);
+    ADJ_ALLOC(c->U2, n * nc);
+    ADJ_ALLOC(Eb, n * nc);
+    ADJ_ALLOC(c->acc, n * nc);
+    for (int k = 0; k < 3; ++k) ADJ_ALLOC(c->bar[k], n * nc);
+#undef ADJ_ALLOC
+    c->Eb = Eb;
+    c->adj_ready = true;
+    return IDP_OK;
+}
+
+int adj_check(idp_ctx *c)
+{
+    if (c->ninst != 1 || c->prm.newton_max_iter > 8) return IDP_ENOTSUP;
+    return adj_setup(c);
+}
+
+// Recompute the stage at U (its intermediates), then run it backwards.
+void stage_vjp(idp_ctx *c, const double *U, double tau, const double *Eb, double *Ub, int clear)
+{
+    stage(c, U, U, c->Estage, 0, 2, tau, 1, clear);
+    idp::AdjArgs A = c->A;
+    A.tau = tau;
+    A.Eb = Eb;
+    A.Ub = Ub;
+    idp::launch_stage_vjp(c->P, A, c->stream);
+}
+
+// One SSP-RK3 step backwards (stages recomputed from U).
+void step_vjp(idp_ctx *c, const double *U, double dt, const double *Ubn, double *Ub, int clear)
+{
+    const int nc = c->prm.dim + 2;
+    const int64_t n = c->n;
+    const uint8_t *hold = c->P.hold;
+    stage(c, U, U, c->U1, 1, 2, dt, 1, clear);          // U1
+    stage(c, c->U1, U, c->U2, 2, 2, dt, 0, 0);          // U2
+    // stage 3: U^{n+1} = U + 2/3 (E(U2) - U)
+    idp::launch_adj_ssp(c->stream, n, nc, hold, Ubn, 2.0 / 3.0, c->Eb, c->acc, 1);
+    stage_vjp(c, c->U2, dt, c->Eb, c->bar[1], 0);
+    // stage 2: U2 = U + 1/4 (E(U1) - U)
+    idp::launch_adj_ssp(c->stream, n, nc, hold, c->bar[1], 0.25, c->Eb, c->acc, 0);
+    stage_vjp(c, c->U1, dt, c->Eb, c->bar[2], 0);
+    // stage 1: U1 = E(U)
+    idp::launch_adj_ssp(c->stream, n, nc, hold, c->bar[2], 1.0, c->Eb, c->acc, 0);
+    stage_vjp(c, U, dt, c->Eb, c->bar[1], 0);
+    idp::launch_adj_add(c->stream, n * nc, c->bar[1], c->acc);
+    (void)hipMemcpyAsync(Ub, c->acc, size_t(n) * nc * 8, hipMemcpyDeviceToDevice, c->stream);
+}
+
+int finish(idp_ctx *c)
+{
+    if (hipGetLastError() != hipSuccess) return IDP_EHIP;
+    Scalars h{};
+    const int rc = read_scalars(c, &h);
+    if (rc != IDP_OK) return rc;
+    return status_code(h.status);
+}
+
+}  // namespace
+
+extern "C" {
+
+int idp_euler_stage_vjp(idp_ctx *c, const double *U, double tau, const double *Ebar,
+                        double *Ubar)
+{
+    if (!c || !U || !Ebar || !Ubar || !(tau > 0.0) || !std::isfinite(tau) || U == Ubar ||
+        Ebar == Ubar)
+        return IDP_EINVAL;
+    int rc = adj_check(c);
+    if (rc != IDP_OK) return rc;
+    stage_vjp(c, U, tau, Ebar, Ubar, 1);
+    return finish(c);
+}
+
+int idp_step_vjp(idp_ctx *c, const double *U, double dt, const double *Ubar_next, double *Ubar)
+{
+    if (!c || !U || !Ubar_next || !Ubar || !(dt > 0.0) || !std::isfinite(dt) || U == Ubar)
+        return IDP_EINVAL;
+    int rc = adj_check(c);
+    if (rc != IDP_OK) return rc;
+    step_vjp(c, U, dt, Ubar_next, Ubar, 1);
+    return finish(c);
+}
+
+int idp_debug_adjoint(idp_ctx *c, int what, double *out)
+{
+    if (!c || !out) return IDP_EINVAL;
+    if (!c->adj_ready) return IDP_EINVAL;
+    const int nc = c->prm.dim + 2;
+    switch (what) {
+    case IDP_ADJ_UL: return node_to_host(c, c->A.ULt, nc, 0, nc, out);
+    case IDP_ADJ_R: return node_to_host(c, c->A.Rt, nc, 0, nc, out);
+    case IDP_ADJ_BOUNDS: return node_to_host(c, c->A.bndt, 3, 0, 3, out);
+    case IDP_ADJ_ALPHA: return node_to_host(c, c->A.alt, 1, 0, 1, out);
+    case IDP_ADJ_P: {
+        std::vector<double> all(size_t(c->sell_size) * nc);
+        if (hipMemcpy(all.data(), c->A.Pb, all.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return IDP_EHIP;
+        for (int64_t q = 0; q < c->nnz; ++q)
+            for (int r = 0; r < nc; ++r) out[q * nc + r] = all[c->sell_of_csr[q] * nc + r];
+        return IDP_OK;
+    }
+    case IDP_ADJ_D: {
+        const int64_t np = c->P.npairs;
+        std::vector<double> dp(np);
+        std::vector<int32_t> pe(np);
+        if (hipMemcpy(dp.data(), c->A.dbp, np * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(pe.data(), c->P.pair_e, np * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return IDP_EHIP;
+        // CSR position of each pair's (i, j) entry, value at (i,j); 0 elsewhere
+        std::vector<int64_t> csr_of_sell(size_t(c->sell_size), -1);
+        for (int64_t q = 0; q < c->nnz; ++q) csr_of_sell[c->sell_of_csr[q]] = q;
+        for (int64_t q = 0; q < c->nnz; ++q) out[q] = 0.0;
+        for (int64_t k = 0; k < np; ++k) out[csr_of_sell[pe[k]]] = dp[k];
+        return IDP_OK;
+    }
+    default: return IDP_EINVAL;
+    }
+}
+
+int idp_forward_checkpoints(idp_ctx *c, double *U, int n_steps, const double *dt, int every)
+{
+    if (!c || !U || !dt || n_steps < 1 || every < 1) return IDP_EINVAL;
+    for (int s = 0; s < n_steps; ++s)
+        if (!(dt[s] > 0.0) || !std::isfinite(dt[s])) return IDP_EINVAL;
+    int rc = adj_check(c);
+    if (rc != IDP_OK) return rc;
+    const int nc = c->prm.dim + 2;
+    const size_t state = size_t(c->n) * nc;
+    const int64_t slots = (n_steps + every - 1) / every + every;   // checkpoints + a segment
+    if (c->ckpt_slots < slots) {
+        if ((rc = dalloc(c, &c->ckpt, slots * state)) != IDP_OK) return rc;
+        c->ckpt_slots = slots;
+    }
+    c->ck_steps = -1;
+    for (int s = 0; s < n_steps; ++s) {
+        if (s % every == 0)
+            (void)hipMemcpyAsync(c->ckpt + (s / every) * state, U, state * 8,
+                                 hipMemcpyDeviceToDevice, c->stream);
+        stage(c, U, U, c->U1, 1, 1, dt[s], 1, s == 0 ? 1 : 0);
+        stage(c, c->U1, U, c->U1, 2, 0, 0.0, 0, 0);
+        stage(c, c->U1, U, U, 3, 0, 0.0, 0, 0);
+    }
+    rc = finish(c);
+    if (rc >= 0) {
+        c->ck_steps = n_steps;
+        c->ck_every = every;
+        c->ck_dt.assign(dt, dt + n_steps);
+    }
+    return rc;
+}
+
+int idp_adjoint_checkpoints(idp_ctx *c, int n_steps, const double *dt, int every,
+                            const double *Ubar_final, double *Ubar0)
+{
+    if (!c || !dt || !Ubar_final || !Ubar0 || n_steps < 1 || every < 1) return IDP_EINVAL;
+    if (n_steps != c->ck_steps || every != c->ck_every) return IDP_EINVAL;
+    for (int s = 0; s < n_steps; ++s)
+        if (dt[s] != c->ck_dt[s]) return IDP_EINVAL;
+    const int nc = c->prm.dim + 2;
+    const size_t state = size_t(c->n) * nc;
+    const int nck = (n_steps + every - 1) / every;
+    double *seg = c->ckpt + int64_t(nck) * state;      // `every` states of one segment
+    // the running cotangent alternates between Ubar0 and bar[0]
+    double *cur = c->bar[0], *nxt = Ubar0;
+    (void)hipMemcpyAsync(cur, Ubar_final, state * 8, hipMemcpyDeviceToDevice, c->stream);
+    int first = 1;
+    for (int k = nck - 1; k >= 0; --k) {
+        const int s0 = k * every, s1 = s0 + every < n_steps ? s0 + every : n_steps;
+        (void)hipMemcpyAsync(seg, c->ckpt + int64_t(k) * state, state * 8,
+                             hipMemcpyDeviceToDevice, c->stream);
+        for (int s = s0; s + 1 < s1; ++s) {
+            double *from = seg + int64_t(s - s0) * state, *to = from + state;
+            (void)hipMemcpyAsync(to, from, state * 8, hipMemcpyDeviceToDevice, c->stream);
+            stage(c, to, to, c->U1, 1, 1, dt[s], 1, first);
+            stage(c, c->U1, to, c->U1, 2, 0, 0.0, 0, 0);
+            stage(c, c->U1, to, to, 3, 0, 0.0, 0, 0);
+            first = 0;
+        }
+        for (int s = s1 - 1; s >= s0; --s) {
+            step_vjp(c, seg + int64_t(s - s0) * state, dt[s], cur, nxt, first);
+            first = 0;
+            double *tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+        }
+    }
+    if (cur != Ubar0)
+        (void)hipMemcpyAsync(Ubar0, cur, state * 8, hipMemcpyDeviceToDevice, c->stream);
+    return finish(c);
 }
 
 int idp_batch_info(const idp_ctx *c, int *n_inst, int64_t *node_offsets)

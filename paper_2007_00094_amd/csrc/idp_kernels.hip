@@ -32,32 +32,9 @@
 
 #include "idp_device.h"
 #include "kernels.h"
+#include "sweep_common.h"
 
 namespace idp {
-
-__device__ __forceinline__ int64_t logical_block(int per)
-{
-    const int b = blockIdx.x;
-    return int64_t(b % kXcd) * per + b / kXcd;
-}
-
-#define ROW_SETUP(P)                                                         \
-    const int64_t s_ = logical_block(P.per) * (kBlock / kSlice) +            \
-                       threadIdx.x / kSlice;                                 \
-    if (s_ >= P.nslices) return;                                             \
-    const int lane_ = threadIdx.x % kSlice;                                  \
-    const int64_t r_ = s_ * kSlice + lane_;                                  \
-    const int i = P.perm[r_];                                                \
-    if (i < 0) return;                                                       \
-    const int L = P.row_len[r_];                                             \
-    const int64_t off_ = P.slice_off[s_] + lane_;
-
-#define ENTRY(k) (off_ + int64_t(k) * kSlice)
-
-__device__ __forceinline__ bool failed(const StageArgs &P)
-{
-    return (*P.status & kErrMask) != 0;
-}
 
 // ------------------------------------------------------------ matrices
 // Eq. matrices by 3-point Gauss quadrature per direction on each cell;
@@ -272,125 +249,6 @@ __device__ __forceinline__ void node_sweep(const StageArgs &P, int64_t i, int64_
     }
 }
 
-template <int D>
-struct NodeA {
-    double U[D + 2];
-    double p, c, er, v[D], phi;
-};
-
-template <int D>
-__device__ __forceinline__ void load_a(const double *__restrict__ A, NodeA<D> &o)
-{
-    constexpr int NC = D + 2;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) o.U[k] = A[k];
-    o.p = A[NC];
-    o.c = A[NC + 1];
-    o.er = A[NC + 2];
-#pragma unroll
-    for (int k = 0; k < D; ++k) o.v[k] = A[NC + 3 + k];
-    o.phi = A[NC + 3 + D];
-}
-
-// ------------------------------------------------- cooperative gathers
-// A lane that fetches a neighbour's record with its own 16-byte loads
-// touches a different cache line per lane, so every load instruction costs
-// the L1 address path 64 line lookups, and a 104-byte record costs seven
-// instructions.  Instead the 64 lanes of a wavefront fetch the records of
-// all its lanes together: lane l loads chunk l % LPR of the record wanted
-// by lane it * (64 / LPR) + l / LPR, so one instruction covers 64 / LPR
-// records (one line each), and the chunks reach their owners through a
-// per-wavefront LDS tile.  All loads are issued before the first is used.
-// Every lane of the wavefront must call it (node < 0: nothing wanted).
-constexpr int kLdsRow = kSlice + 1;   // double2 per chunk row (+1: bank skew)
-constexpr int kMaxChunks = 7;         // largest record gathered (pack B with coefficient)
-
-template <int NCH>
-__device__ __forceinline__ void gather(const double *__restrict__ base, int stride, int node,
-                                       double2 *lds, double *out)
-{
-    static_assert(NCH >= 1 && NCH <= 8, "record of 1 to 8 chunks");
-    constexpr int LPR = NCH > 4 ? 8 : (NCH > 2 ? 4 : (NCH > 1 ? 2 : 1));
-    constexpr int RPI = kSlice / LPR;
-    const int lane = threadIdx.x % kSlice;
-    const int c = lane % LPR;
-    const int cc = c < NCH ? c : NCH - 1;   // spare lanes repeat the last chunk
-    int nd[LPR];
-#pragma unroll
-    for (int it = 0; it < LPR; ++it) {
-        const int v = __shfl(node, it * RPI + lane / LPR);
-        nd[it] = v < 0 ? 0 : v;
-    }
-    double2 val[LPR];
-#pragma unroll
-    for (int it = 0; it < LPR; ++it)
-        val[it] = *reinterpret_cast<const double2 *>(base + int64_t(nd[it]) * stride + 2 * cc);
-#pragma unroll
-    for (int it = 0; it < LPR; ++it) lds[cc * kLdsRow + it * RPI + lane / LPR] = val[it];
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int k = 0; k < NCH; ++k) {
-        const double2 v = lds[k * kLdsRow + lane];
-        out[2 * k] = v.x;
-        out[2 * k + 1] = v.y;
-    }
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Row sweeps: one wavefront per slice s (below send); every lane stays to
-// the end of the slice's longest row; lanes past the node count take node
-// 0 and write nothing.  inst_ is the slice's instance.
-#define WAVE_ROW_SETUP(P, S, SEND)                                           \
-    const int64_t s_ = (S);                                                  \
-    if (s_ >= (SEND)) return;                                                \
-    const int lane_ = threadIdx.x % kSlice;                                  \
-    const int64_t r_ = s_ * kSlice + lane_;                                  \
-    const int iraw_ = P.perm[r_];                                            \
-    const bool valid_ = iraw_ >= 0;                                          \
-    const int i = valid_ ? iraw_ : 0;                                        \
-    const int L = valid_ ? P.row_len[r_] : 0;                                \
-    const int64_t off_ = P.slice_off[s_] + lane_;                            \
-    const int inst_ = P.inst_slice ? P.inst_slice[s_] : 0;                   \
-    int Lmax_ = L;                                                           \
-    for (int o_ = kSlice / 2; o_ > 0; o_ /= 2) {                             \
-        const int v_ = __shfl_xor(Lmax_, o_);                                \
-        Lmax_ = v_ > Lmax_ ? v_ : Lmax_;                                     \
-    }
-
-// Pair sweeps: one lane per pair p (below pend); lanes past the end take
-// pair 0 and write nothing; a wavefront with no pair leaves.
-#define WAVE_PAIR_SETUP(P, PIDX, PEND)                                       \
-    const int64_t p_ = (PIDX);                                               \
-    if (p_ - threadIdx.x % kSlice >= (PEND)) return;                         \
-    const bool valid_ = p_ < (PEND);                                         \
-    const int64_t pq_ = valid_ ? p_ : 0;                                     \
-    const int64_t e = P.pair_e[pq_];                                         \
-    const int64_t t = P.pair_t[pq_];                                         \
-    const int i = P.pair_i[pq_];                                             \
-    const int j = P.pair_j[pq_];
-
-template <int D>
-__device__ __forceinline__ void unpack_a(const double *o, NodeA<D> &A)
-{
-    constexpr int NC = D + 2;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) A.U[k] = o[k];
-    A.p = o[NC];
-    A.c = o[NC + 1];
-    A.er = o[NC + 2];
-#pragma unroll
-    for (int k = 0; k < D; ++k) A.v[k] = o[NC + 3 + k];
-    A.phi = o[NC + 3 + D];
-}
-
-template <int D>
-__device__ __forceinline__ void load_c(const StageArgs &P, int64_t e, double *c)
-{
-    c[0] = P.c0[e];
-    c[1] = P.c1[e];
-    if (D == 3) c[D - 1] = P.c2[e];
-}
-
 // ------------------------------------------------------- pair viscosity
 // Step 1, once per unordered pair {i, j}: d_ij = d_ji = max of
 // lambda~(n_ij, U_i, U_j)|c_ij| and lambda~(n_ji, U_j, U_i)|c_ji|.
@@ -575,75 +433,6 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
     W[NC + 1] = rho_max;
     W[NC + 2] = phi_min;
 }
-
-template <int D>
-struct NodeB {
-    double U[D + 2], R[D + 2], alpha, m, coef;
-};
-
-template <int D>
-__device__ __forceinline__ void load_b(const double *__restrict__ B, NodeB<D> &o)
-{
-    constexpr int NC = D + 2;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        o.U[k] = B[k];
-        o.R[k] = B[NC + k];
-    }
-    o.alpha = B[2 * NC];
-    o.m = B[2 * NC + 1];
-    o.coef = B[kPackCoef];
-}
-
-// pack B record as gathered: U, R, alpha, m (and the coefficient if
-// WITH_COEF, i.e. if the gather reached slot kPackCoef)
-template <int D, bool WITH_COEF>
-__device__ __forceinline__ void unpack_b(const double *o, NodeB<D> &B)
-{
-    constexpr int NC = D + 2;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        B.U[k] = o[k];
-        B.R[k] = o[NC + k];
-    }
-    B.alpha = o[2 * NC];
-    B.m = o[2 * NC + 1];
-    B.coef = WITH_COEF ? o[kPackCoef] : 0.0;
-}
-
-// eq. def-p: P_ij = tau/(lambda_i m_i) (b_ij R_j - b_ji R_i + (d^H - d^L)(U_j - U_i)),
-// b_ij = -m_ij/m_j, b_ji = -m_ij/m_i (j != i)
-template <int D>
-__device__ __forceinline__ void direction(const NodeB<D> &Bi, const NodeB<D> &Bj,
-                                          double coef, double dL, double mij,
-                                          double *Pd)
-{
-    const double dH = dL * (Bi.alpha + Bj.alpha) / 2.0;
-    const double bij = -mij / Bj.m;
-    const double bji = -mij / Bi.m;
-#pragma unroll
-    for (int r = 0; r < D + 2; ++r)
-        Pd[r] = coef * (bij * Bj.R[r] - bji * Bi.R[r] + (dH - dL) * (Bj.U[r] - Bi.U[r]));
-}
-
-// Candidate of row i on the line U + t P_ij under the bounds of row i.
-template <int D>
-__device__ __forceinline__ double row_limiter(const double *Urow, const double *W,
-                                              const double *Pd, const StageArgs &P)
-{
-    constexpr int NC = D + 2;
-    return limiter<D>(Urow, Pd, W[NC], W[NC + 1], W[NC + 2], P.gamma, P.newton_max, P.tol);
-}
-
-// record sizes in 16-byte chunks
-template <int D> struct Chunks {
-    static constexpr int NC = D + 2;
-    static constexpr int packB = kPackCoef / 2 + 1;   // U, R, alpha, m, coefficient
-    static constexpr int packBrow = NC + 1;           // U, R, alpha, m
-    static constexpr int rowB = (NC + 4) / 2;         // U^L, bounds
-    static constexpr int upass = (NC + 1) / 2;        // pass-1 state
-};
-static_assert(Chunks<3>::packB <= kMaxChunks && Chunks<2>::packB <= kMaxChunks, "LDS tile");
 
 // ------------------------------------------------------ pair limiter 1
 // Step 4, once per unordered pair: l_ij from (U^L_i, P_ij, bounds_i) and

@@ -238,6 +238,29 @@ def ic_isothermal_blobs(coords: np.ndarray, seed: int = 2,
     return conserved(rho, np.zeros((coords.shape[0], dim)), rho.copy(), gamma)
 
 
+def smooth_field(coords: np.ndarray, seed: int, terms: int = 3) -> np.ndarray:
+    """A smooth seeded field of unit size: sum of `terms` products of sines
+    with random wave numbers 1-2 and phases (no flat region)."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros(coords.shape[0])
+    for _ in range(terms):
+        w = rng.uniform(1.0, 2.0, size=coords.shape[1]) * 2.0 * np.pi
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=coords.shape[1])
+        out += np.prod(np.sin(coords * w + ph), axis=1) / terms
+    return out
+
+
+def ic_generic_smooth(coords: np.ndarray, seed: int = 5, gamma: float = GAMMA) -> np.ndarray:
+    """rho = 1 + 0.3 f1, p = 1 + 0.3 f2, u = 0.3 (f3, f4, f5) with smooth
+    seeded fields f_k: a smooth state with no uniform region, so that no
+    bound of Section 3.9 is tight by construction."""
+    dim = coords.shape[1]
+    rho = 1.0 + 0.3 * smooth_field(coords, seed)
+    p = 1.0 + 0.3 * smooth_field(coords, seed + 1)
+    vel = np.stack([0.3 * smooth_field(coords, seed + 2 + k) for k in range(dim)], axis=1)
+    return conserved(rho, vel, p, gamma)
+
+
 def ic_uniform(n_nodes: int, dim: int, rho=1.0, vel=None, p=1.0,
                gamma: float = GAMMA) -> np.ndarray:
     v = np.zeros((n_nodes, dim)) if vel is None else np.tile(

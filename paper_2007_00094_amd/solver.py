@@ -106,6 +106,39 @@ class Solver:
     def status(self) -> int:
         return capi.check("idp_get_status", capi.lib().idp_get_status(self._h))
 
+    # ----------------------------------------------------------- adjoint
+    def euler_stage_vjp(self, U, tau: float, Ebar):
+        """(dE/dU)^T Ebar for the forward-Euler update with step tau."""
+        torch = _require_torch_gpu()
+        out = torch.empty_like(U)
+        capi.check("idp_euler_stage_vjp", capi.lib().idp_euler_stage_vjp(
+            self._h, self._u(U), float(tau), self._u(Ebar), self._u(out)))
+        return out
+
+    def step_vjp(self, U, dt: float, Ubar_next):
+        """(dS/dU)^T Ubar_next for one SSP-RK3 step from U with step dt."""
+        torch = _require_torch_gpu()
+        out = torch.empty_like(U)
+        capi.check("idp_step_vjp", capi.lib().idp_step_vjp(
+            self._h, self._u(U), float(dt), self._u(Ubar_next), self._u(out)))
+        return out
+
+    def forward_checkpoints(self, U, dts, every: int):
+        """len(dts) steps in place with the given steps, checkpoints kept."""
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        return capi.check("idp_forward_checkpoints", capi.lib().idp_forward_checkpoints(
+            self._h, self._u(U), len(d), d.ctypes.data_as(capi._dp), int(every)))
+
+    def adjoint_checkpoints(self, dts, every: int, Ubar_final):
+        """Cotangent of the initial state of the last forward_checkpoints run."""
+        torch = _require_torch_gpu()
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        out = torch.empty_like(Ubar_final)
+        capi.check("idp_adjoint_checkpoints", capi.lib().idp_adjoint_checkpoints(
+            self._h, len(d), d.ctypes.data_as(capi._dp), int(every), self._u(Ubar_final),
+            self._u(out)))
+        return out
+
     # ----------------------------------------------------------- exports
     def matrices(self):
         n, z, d = self.n, self.nnz, self.dim
