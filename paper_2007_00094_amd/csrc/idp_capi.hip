@@ -18,11 +18,12 @@ namespace {
 
 enum KernelId {
     K_BEGIN, K_NODE, K_DPAIR, K_DIAG, K_TAU, K_LOW, K_LIM1P, K_PASS1A, K_LIM2P, K_PASS2,
-    K_PERSIST, K_COUNT
+    K_PERSIST, K_VJP, K_COUNT
 };
 const char *kKernelNames[K_COUNT] = {"begin", "node_pack", "pair_viscosity", "row_diagonal",
                                      "tau", "row_low_order", "pair_limiter1", "row_pass1",
-                                     "pair_limiter2", "row_pass2", "batch_persistent"};
+                                     "pair_limiter2", "row_pass2", "batch_persistent",
+                                     "stage_vjp"};
 
 struct Pending {
     int id;
@@ -786,7 +787,7 @@ void stage_vjp(idp_ctx *c, const double *U, double tau, const double *Eb, double
     A.tau = tau;
     A.Eb = Eb;
     A.Ub = Ub;
-    idp::launch_stage_vjp(c->P, A, c->stream);
+    timed(c, K_VJP, [&] { idp::launch_stage_vjp(c->P, A, c->stream); });
 }
 
 // One SSP-RK3 step backwards (stages recomputed from U).

@@ -113,7 +113,10 @@ __device__ __forceinline__ void gather(const double *__restrict__ base, int stri
     const int i = valid_ ? iraw_ : 0;                                        \
     const int L = valid_ ? P.row_len[r_] : 0;                                \
     const int64_t off_ = P.slice_off[s_] + lane_;                            \
-    const int inst_ = P.inst_slice ? P.inst_slice[s_] : 0;                   \
+    /* the slice's instance, wavefront-uniform: keeps atomics on its tau */  \
+    /* combined per wavefront                                            */  \
+    const int inst_ = __builtin_amdgcn_readfirstlane(                        \
+        P.inst_slice ? P.inst_slice[s_] : 0);                                \
     int Lmax_ = L;                                                           \
     for (int o_ = kSlice / 2; o_ > 0; o_ /= 2) {                             \
         const int v_ = __shfl_xor(Lmax_, o_);                                \
