@@ -8,32 +8,47 @@
 
 namespace idp {
 
-// Work arrays of one stage's vector-Jacobian product (device).
-// Per node: [n][nc] unless noted; per stencil entry (SELL order): [sell][nc]
-// unless noted.  Written by one kernel each, read by later ones.
+// Record strides (doubles) of the adjoint's work arrays.  Records read by
+// cooperative gathers have even strides (16-byte chunks).
+constexpr int kEbS = 8;    // node: stage-output cotangent (nc), padded
+constexpr int kUpS = 8;    // node: pass-1 state's cotangent (nc), bounds' (3)
+constexpr int kC2S = 8;    // entry: pass-2 limiter's state (nc) and bounds (3) cotangents
+constexpr int kC1S = 16;   // entry: pass-1 limiter's U^L (nc) and bounds (3) cotangents
+                           // [0, 8); direction cotangent Z (nc) [8, 13); alpha's
+                           // share [13]; d^H - d^L [14]
+constexpr int kC5S = 6;    // entry: state cotangent (nc) from the graph viscosity
+constexpr int kQS = 6;     // pair: cotangent of the pass-2 direction (nc)
+constexpr int kNS = 16;    // node: Lw's (nc) [0, 5), R's (nc) [5, 10), bounds' [10, 13)
+                           // cotangents, alpha [13], the neighbours that set the
+                           // bounds [14, 16)
+constexpr int kIS = 8;     // node: the indicator's a and b (nc) cotangents [0, 6),
+                           // eta/rho [6]
+
+// Work arrays of one stage's vector-Jacobian product (device).  The
+// per-entry buffer C holds, in turn, the pass-2 limiter records (kC2S), the
+// pass-1 limiter and direction records (kC1S) and the graph-viscosity
+// records (kC5S): each is dead before the next is written.
 struct AdjArgs {
     double tau;
-    const double *Eb;   // cotangent of the stage output E(U)
-    double *Ub;         // result: cotangent of U
-    double *Upb;        // pass-1 state's (= U^L's) cotangent
-    double *bndb;       // [n][3] bounds' cotangent from pass 2
-    double *Ub3, *Ub2;  // own parts of U's cotangent (low order, indicator)
-    double *alb;        // [n] alpha's own cotangent (low order)
-    double *sb1, *sb2;  // [sell] s1, s2 cotangents, one row's share
-    double *Pb;         // P_ij's cotangent
-    double *cnode;      // [sell][nc + 3] limiter contributions to the row's
-                        // state (U^L or pass-1) and bounds
-    double *cR, *cU;    // R's and U's cotangent contributions to the row's node
-    double *cal;        // [sell] alpha's contribution to the row's node
-    double *dbp;        // [npairs] d_ij's cotangent from the directions
-    double *cUj, *cUj2; // contributions to the column node j (low order, indicator)
-    double *calj, *db3; // [sell] alpha_j's and d_ij's contributions (low order)
+    const double *Ebp;  // [n][kEbS] cotangent of the stage output E(U)
+    double *Ub;         // [n][nc] result: cotangent of U
+    double *Upb;        // [n][kUpS]
+    double *Nrec;       // [n][kNS]
+    double *Irec;       // [n][kIS]
+    double *Up4, *Up6;  // [n][nc] parts of U's cotangent (low order; indicator and
+                        // the neighbours' low order)
+    double *alb;        // [n] alpha's cotangent from the directions and its own R
+    double *C;          // [sell][kC1S]
+    double *db4;        // [sell] d_ij's cotangent from row i's low-order update
+    double *Qb;         // [npairs][kQS]
+    double *dLb;        // [npairs] d_ij's cotangent: the directions', then the total
     // totals kept for inspection: U^L's, R's, bounds', alpha's cotangents
-    // (d_ij's total is left in dbp)
     double *ULt, *Rt, *bndt, *alt;
 };
 
 void launch_stage_vjp(const StageArgs &P, const AdjArgs &A, hipStream_t st);
+// Eb [n][kEbS] of a user array [n][nc]
+void launch_adj_pad(hipStream_t st, int64_t n, int nc, const double *in, double *out);
 void launch_adj_ssp(hipStream_t st, int64_t n, int nc, const uint8_t *hold, const double *outb,
                     double theta, double *Eb, double *U0b, int first);
 void launch_adj_add(hipStream_t st, int64_t n, const double *x, double *y);

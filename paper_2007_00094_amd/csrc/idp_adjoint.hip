@@ -419,424 +419,411 @@ __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, do
     }
 }
 
-// direction P_ij (eq. def-p) backwards for P's cotangent Pbar; adds R and
-// U cotangents of both rows, alpha cotangents and returns dL's.
-template <int D>
-__device__ __forceinline__ double direction_vjp(const NodeB<D> &Bi, const NodeB<D> &Bj,
-                                                double coef, double dL, double mij,
-                                                const double *Pbar, double *Rbi, double *Rbj,
-                                                double *Ubi, double *Ubj, double &albi,
-                                                double &albj)
-{
-    const double dH = dL * (Bi.alpha + Bj.alpha) / 2.0;
-    const double bij = -mij / Bj.m;
-    const double bji = -mij / Bi.m;
-    const double k = dH - dL;
-    double kb = 0.0;
-#pragma unroll
-    for (int r = 0; r < D + 2; ++r) {
-        const double w = coef * Pbar[r];
-        Rbj[r] += bij * w;
-        Rbi[r] -= bji * w;
-        Ubj[r] += k * w;
-        Ubi[r] -= k * w;
-        kb += w * (Bj.U[r] - Bi.U[r]);
-    }
-    albi += kb * dL / 2.0;
-    albj += kb * dL / 2.0;
-    return kb * ((Bi.alpha + Bj.alpha) / 2.0 - 1.0);
-}
-
 // ------------------------------------------------------------- kernels
-#define ADJ_PAIR_SETUP(P)                                                    \
-    const int64_t p_ = int64_t(blockIdx.x) * kBlock + threadIdx.x;           \
-    if (p_ >= P.npairs) return;                                              \
-    const int64_t e = P.pair_e[p_];                                          \
-    const int64_t t = P.pair_t[p_];                                          \
-    const int i = P.pair_i[p_];                                              \
-    const int j = P.pair_j[p_];
+// Every sweep is a wavefront sweep (rows: one slice per wavefront; pairs:
+// one pair per lane) whose node records come through cooperative gathers,
+// and whose per-entry records leave through cooperative scatters.
 
-template <int D> constexpr int kNodeSlot = D + 5;   // nc + 3 bounds per entry
-
-// pass 2 backwards (row): Up's cotangent = Eb; s2, s1 and P cotangents per entry
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_adj_pass2(StageArgs P, AdjArgs A)
+// Bits of the neighbour ids in a node record: slot 14 holds (min, max),
+// slot 15 the phi_min neighbour; -1: the node itself.
+__device__ __forceinline__ double pack_ids(int a, int b)
 {
-    ROW_SETUP(P)
-    constexpr int NC = D + 2;
-    NodeB<D> Bi;
-    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
-    double Eb[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) {
-        Eb[r] = A.Eb[int64_t(i) * NC + r];
-        A.Upb[int64_t(i) * NC + r] = Eb[r];
-    }
-    const double lam = P.lam[i];
-    const double coef = A.tau / (lam * Bi.m);
-    for (int k = 0; k < L; ++k) {
-        const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        double *Pb = A.Pb + e * NC;
-        if (j == i || P.passes < 2) {
-            A.sb1[e] = 0.0;
-            A.sb2[e] = 0.0;
-#pragma unroll
-            for (int r = 0; r < NC; ++r) Pb[r] = 0.0;
-            continue;
-        }
-        const double s1 = P.l1[e], s2 = P.l2[e];
-        NodeB<D> Bj;
-        load_b<D>(P.packB + int64_t(j) * kPack, Bj);
-        double Pd[NC];
-        direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
-        double EP = 0.0;
-#pragma unroll
-        for (int r = 0; r < NC; ++r) EP += Eb[r] * Pd[r];
-        A.sb2[e] = lam * (1.0 - s1) * EP;
-        A.sb1[e] = -lam * s2 * EP;
-#pragma unroll
-        for (int r = 0; r < NC; ++r) Pb[r] = lam * s2 * (1.0 - s1) * Eb[r];
-    }
+    return __longlong_as_double((long long)((unsigned long long)(unsigned)a |
+                                            ((unsigned long long)(unsigned)b << 32)));
+}
+__device__ __forceinline__ int id_lo(double v)
+{
+    return int((unsigned)((unsigned long long)__double_as_longlong(v) & 0xffffffffull));
+}
+__device__ __forceinline__ int id_hi(double v)
+{
+    return int((unsigned)((unsigned long long)__double_as_longlong(v) >> 32));
 }
 
-// limiter pass 2 backwards (pair): the active candidate of min(l_ij, l_ji)
+// pass 2 and its limiter backwards (pair).  E_i = U_i' + sum_j lambda_i
+// s2_ij (1 - s1_ij) P_ij gives s2's cotangent; the candidate that set
+// s2 = min(l_ij, l_ji) is run backwards (Alg. 2/3 on the line U_a' + t
+// (1 - s1) P_a): its state and bounds cotangents go to the entry of its row
+// (zeros to the other), the direction's cotangent to the pair.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_lim2(StageArgs P, AdjArgs A)
 {
-    ADJ_PAIR_SETUP(P)
-    constexpr int NC = D + 2, NS = kNodeSlot<D>;
+    WAVE_LDS(Chunks<D>::packB)
+    WAVE_PAIR_SETUP(P, PAIR_INDEX(P), P.npairs)
+    constexpr int NC = D + 2, NU = (NC + 1) / 2;
+    using CH = Chunks<D>;
     NodeB<D> Bi, Bj;
-    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
-    load_b<D>(P.packB + int64_t(j) * kPack, Bj);
-    const double *Wi = P.rowB + int64_t(i) * kRowB, *Wj = P.rowB + int64_t(j) * kRowB;
-    const double *Ui = P.upass + int64_t(i) * kRowU, *Uj = P.upass + int64_t(j) * kRowU;
-    const double dL = P.dp[p_], m = P.mp[p_], s1 = P.l1p[p_];
-    double Pij[NC], Pji[NC], Qij[NC], Qji[NC];
+    double rec[2 * CH::packB], Wi[2 * CH::rowB], Wj[2 * CH::rowB];
+    double Ui[2 * NU], Uj[2 * NU], Ei[2 * NU], Ej[2 * NU];
+    gather<CH::packB>(P.packB, kPack, i, lw, rec);
+    unpack_b<D, true>(rec, Bi);
+    gather<CH::packB>(P.packB, kPack, j, lw, rec);
+    unpack_b<D, true>(rec, Bj);
+    gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
+    gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
+    gather<NU>(P.upass, kRowU, i, lw, Ui);
+    gather<NU>(P.upass, kRowU, j, lw, Uj);
+    gather<NU>(A.Ebp, kEbS, i, lw, Ei);
+    gather<NU>(A.Ebp, kEbS, j, lw, Ej);
+    const double dL = P.dp[pq_], m = P.mp[pq_], s1 = P.l1p[pq_];
+    const bool iside = P.side2[pq_] != 0;
+    double Pij[NC], Pji[NC];
     direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
     direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) { Qij[r] = (1.0 - s1) * Pij[r]; Qji[r] = (1.0 - s1) * Pji[r]; }
-    double Uc[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) Uc[r] = Ui[r];
-    const double lij = row_limiter<D>(Uc, Wi, Qij, P);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) Uc[r] = Uj[r];
-    const double lji = row_limiter<D>(Uc, Wj, Qji, P);
-    const double sb = A.sb2[e] + A.sb2[t];
-    double *ce = A.cnode + e * NS, *ct = A.cnode + t * NS;
-#pragma unroll
-    for (int r = 0; r < NS; ++r) { ce[r] = 0.0; ct[r] = 0.0; }
-    const bool iside = lij < lji;
-    const double *Ua = iside ? Ui : Uj;
-    const double *Wa = iside ? Wi : Wj;
-    const double *Qa = iside ? Qij : Qji;
-    const double *Pa = iside ? Pij : Pji;
-    double *ca = iside ? ce : ct;
-    const int64_t ea = iside ? e : t;
-    double Ub[NC], Qb[NC], bb[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int r = 0; r < NC; ++r) { Ub[r] = 0.0; Qb[r] = 0.0; Uc[r] = Ua[r]; }
-    limiter_vjp<D>(Uc, Qa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb, Ub,
-                   Qb, bb);
-    double QP = 0.0;
-    double *Pb = A.Pb + ea * NC;
+    double EPi = 0.0, EPj = 0.0;
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
-        ca[r] = Ub[r];
-        Pb[r] += (1.0 - s1) * Qb[r];
-        QP += Qb[r] * Pa[r];
+        EPi += Ei[r] * Pij[r];
+        EPj += Ej[r] * Pji[r];
     }
-    ca[NC] = bb[0];
-    ca[NC + 1] = bb[1];
-    ca[NC + 2] = bb[2];
-    A.sb1[ea] -= QP;
+    const double sb = (1.0 - s1) * (P.lam[i] * EPi + P.lam[j] * EPj);
+    double Ub[NC], Qb[NC], bb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < NC; ++r) { Ub[r] = 0.0; Qb[r] = 0.0; }
+    if (valid_ && sb != 0.0) {
+        const double *Ua = iside ? Ui : Uj;
+        const double *Wa = iside ? Wi : Wj;
+        double Qa[NC], Uc[NC];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            Qa[r] = (1.0 - s1) * (iside ? Pij[r] : Pji[r]);
+            Uc[r] = Ua[r];
+        }
+        limiter_vjp<D>(Uc, Qa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
+                       Ub, Qb, bb);
+    }
+    double ra[kC2S], rz[kC2S], rq[kQS];
+#pragma unroll
+    for (int r = 0; r < kC2S; ++r) rz[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < kC2S; ++r) ra[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) ra[r] = Ub[r];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) ra[NC + q] = bb[q];
+#pragma unroll
+    for (int r = 0; r < kQS; ++r) rq[r] = r < NC ? Qb[r] : 0.0;
+    scatter<kC2S / 2>(A.C, kC2S, valid_ ? int(e) : -1, lw, iside ? ra : rz);
+    scatter<kC2S / 2>(A.C, kC2S, valid_ ? int(t) : -1, lw, iside ? rz : ra);
+    scatter<kQS / 2>(A.Qb, kQS, valid_ ? int(p_) : -1, lw, rq);
 }
 
-// pass 1 backwards (row): Up's total cotangent (= U^L's), bounds' so far
+// pass 1 backwards (row): U_i' = E_i's cotangent plus the pass-2 limiter's
+// records of the row; the bounds' cotangents so far.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_pass1(StageArgs P, AdjArgs A)
 {
-    ROW_SETUP(P)
-    constexpr int NC = D + 2, NS = kNodeSlot<D>;
-    double Upb[NC], bnd[3] = {0.0, 0.0, 0.0};
+    WAVE_LDS(kC2S / 2)
+    WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
+    (void)inst_;   // one instance: adjoints run on single meshes
+    constexpr int NC = D + 2;
+    const int dk = valid_ ? P.diag_k[r_] : -1;
+    double u[NC], bnd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < NC; ++r) Upb[r] = A.Upb[int64_t(i) * NC + r];
+    for (int r = 0; r < NC; ++r) u[r] = A.Ebp[int64_t(i) * kEbS + r];
     if (P.passes >= 2) {
-        for (int k = 0; k < L; ++k) {
+        for (int k = 0; k < Lmax_; ++k) {
             const int64_t e = ENTRY(k);
-            if (P.scol[e] == i) continue;
-            const double *c = A.cnode + e * NS;
+            const bool act = k < L && k != dk;
+            double rec[kC2S];
+            gather<kC2S / 2>(A.C, kC2S, act ? int(e) : -1, lw, rec);
+            if (!act) continue;
 #pragma unroll
-            for (int r = 0; r < NC; ++r) Upb[r] += c[r];
-            bnd[0] += c[NC];
-            bnd[1] += c[NC + 1];
-            bnd[2] += c[NC + 2];
+            for (int r = 0; r < NC; ++r) u[r] += rec[r];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) bnd[q] += rec[NC + q];
         }
     }
+    if (!valid_) return;
+    double *o = A.Upb + int64_t(i) * kUpS;
 #pragma unroll
-    for (int r = 0; r < NC; ++r) A.Upb[int64_t(i) * NC + r] = Upb[r];
-    A.bndb[int64_t(i) * 3 + 0] = bnd[0];
-    A.bndb[int64_t(i) * 3 + 1] = bnd[1];
-    A.bndb[int64_t(i) * 3 + 2] = bnd[2];
-    NodeB<D> Bi;
-    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
-    const double lam = P.lam[i];
-    const double coef = A.tau / (lam * Bi.m);
-    for (int k = 0; k < L; ++k) {
-        const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        if (j == i) continue;
-        NodeB<D> Bj;
-        load_b<D>(P.packB + int64_t(j) * kPack, Bj);
-        double Pd[NC];
-        direction<D>(Bi, Bj, coef, P.d[e], P.mij[e], Pd);
-        const double s1 = P.l1[e];
-        double UP = 0.0;
-        double *Pb = A.Pb + e * NC;
+    for (int r = 0; r < NC; ++r) o[r] = u[r];
 #pragma unroll
-        for (int r = 0; r < NC; ++r) {
-            UP += Upb[r] * Pd[r];
-            Pb[r] += lam * s1 * Upb[r];
-        }
-        A.sb1[e] += lam * UP;
-    }
+    for (int q = 0; q < 3; ++q) o[NC + q] = bnd[q];
 }
 
-// limiter pass 1 and the directions backwards (pair)
+// the directions P_ij, P_ji (eq. def-p) and the pass-1 limiter backwards
+// (pair).  P_ij's cotangent gathers pass 2 (lambda_i s2 (1 - s1) Eb_i), the
+// pass-2 limiter ((1 - s1) Q if row i set s2) and pass 1 (lambda_i s1 U_i'
+// bar); s1's cotangent likewise.  The candidate that set s1 is run
+// backwards.  Both directions then reduce to Z = coef_j Pb_ji - coef_i
+// Pb_ij: R_i gains b_ji Z, U_i gains (d^H - d^L) Z, R_j and U_j the same
+// with -Z and b_ij; alpha_i and alpha_j each gain -Z.(U_j - U_i) d^L/2.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_lim1(StageArgs P, AdjArgs A)
 {
-    ADJ_PAIR_SETUP(P)
-    constexpr int NC = D + 2, NS = kNodeSlot<D>;
+    WAVE_LDS(kC1S / 2)
+    WAVE_PAIR_SETUP(P, PAIR_INDEX(P), P.npairs)
+    constexpr int NC = D + 2, NU = (NC + 1) / 2;
+    using CH = Chunks<D>;
     NodeB<D> Bi, Bj;
-    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
-    load_b<D>(P.packB + int64_t(j) * kPack, Bj);
-    const double *Wi = P.rowB + int64_t(i) * kRowB, *Wj = P.rowB + int64_t(j) * kRowB;
-    const double dL = P.dp[p_], m = P.mp[p_];
-    double Pij[NC], Pji[NC], Uc[NC];
+    double rec[2 * CH::packB], Wi[2 * CH::rowB], Wj[2 * CH::rowB];
+    double Ei[2 * NU], Ej[2 * NU], Vi[2 * NU], Vj[2 * NU], Qr[kQS];
+    gather<CH::packB>(P.packB, kPack, i, lw, rec);
+    unpack_b<D, true>(rec, Bi);
+    gather<CH::packB>(P.packB, kPack, j, lw, rec);
+    unpack_b<D, true>(rec, Bj);
+    gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
+    gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
+    gather<NU>(A.Ebp, kEbS, i, lw, Ei);
+    gather<NU>(A.Ebp, kEbS, j, lw, Ej);
+    gather<NU>(A.Upb, kUpS, i, lw, Vi);
+    gather<NU>(A.Upb, kUpS, j, lw, Vj);
+    const bool two = P.passes >= 2;
+    if (two) {
+        gather<kQS / 2>(A.Qb, kQS, valid_ ? int(p_) : -1, lw, Qr);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kQS; ++r) Qr[r] = 0.0;
+    }
+    const double dL = P.dp[pq_], m = P.mp[pq_], s1 = P.l1p[pq_];
+    const double s2 = two ? P.l2[e] : 0.0;
+    const bool side1 = P.side1[pq_] != 0;
+    const bool side2 = two ? P.side2[pq_] != 0 : true;
+    const double li = P.lam[i], lj = P.lam[j];
+    double Pij[NC], Pji[NC];
     direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
     direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) Uc[r] = Wi[r];
-    const double lij = row_limiter<D>(Uc, Wi, Pij, P);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) Uc[r] = Wj[r];
-    const double lji = row_limiter<D>(Uc, Wj, Pji, P);
-    const double sb = A.sb1[e] + A.sb1[t];
-    double *ce = A.cnode + e * NS, *ct = A.cnode + t * NS;
-#pragma unroll
-    for (int r = 0; r < NS; ++r) { ce[r] = 0.0; ct[r] = 0.0; }
-    const bool iside = lij < lji;
-    const double *Wa = iside ? Wi : Wj;
-    const double *Pa = iside ? Pij : Pji;
-    double *ca = iside ? ce : ct;
-    double Ub[NC], Pab[NC], bb[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int r = 0; r < NC; ++r) { Ub[r] = 0.0; Pab[r] = 0.0; Uc[r] = Wa[r]; }
-    limiter_vjp<D>(Uc, Pa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb, Ub,
-                   Pab, bb);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) ca[r] = Ub[r];
-    ca[NC] = bb[0];
-    ca[NC + 1] = bb[1];
-    ca[NC + 2] = bb[2];
-    // total P cotangents of both directions
-    double Pbij[NC], Pbji[NC];
+    double EPi = 0.0, EPj = 0.0, VPi = 0.0, VPj = 0.0, QP = 0.0;
+    double Pbi[NC], Pbj[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
-        Pbij[r] = A.Pb[e * NC + r] + (iside ? Pab[r] : 0.0);
-        Pbji[r] = A.Pb[t * NC + r] + (iside ? 0.0 : Pab[r]);
-        A.Pb[e * NC + r] = Pbij[r];   // totals (kept for inspection)
-        A.Pb[t * NC + r] = Pbji[r];
+        EPi += Ei[r] * Pij[r];
+        EPj += Ej[r] * Pji[r];
+        VPi += Vi[r] * Pij[r];
+        VPj += Vj[r] * Pji[r];
+        QP += Qr[r] * (side2 ? Pij[r] : Pji[r]);
+        const double q = (1.0 - s1) * Qr[r];
+        Pbi[r] = li * s2 * (1.0 - s1) * Ei[r] + li * s1 * Vi[r] + (side2 ? q : 0.0);
+        Pbj[r] = lj * s2 * (1.0 - s1) * Ej[r] + lj * s1 * Vj[r] + (side2 ? 0.0 : q);
     }
-    double Rbi[NC], Rbj[NC], Ubi[NC], Ubj[NC];
+    const double sb = -s2 * (li * EPi + lj * EPj) - QP + li * VPi + lj * VPj;
+    double ULb[NC], Pab[NC], bb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < NC; ++r) { Rbi[r] = Rbj[r] = Ubi[r] = Ubj[r] = 0.0; }
-    double albi = 0.0, albj = 0.0;
-    double dLb = direction_vjp<D>(Bi, Bj, Bi.coef, dL, m, Pbij, Rbi, Rbj, Ubi, Ubj, albi, albj);
-    dLb += direction_vjp<D>(Bj, Bi, Bj.coef, dL, m, Pbji, Rbj, Rbi, Ubj, Ubi, albj, albi);
+    for (int r = 0; r < NC; ++r) { ULb[r] = 0.0; Pab[r] = 0.0; }
+    if (valid_ && sb != 0.0) {
+        const double *Wa = side1 ? Wi : Wj;
+        double Pa[NC], Uc[NC];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            Pa[r] = side1 ? Pij[r] : Pji[r];
+            Uc[r] = Wa[r];
+        }
+        limiter_vjp<D>(Uc, Pa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
+                       ULb, Pab, bb);
+    }
+    double Z[NC], kb = 0.0;
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
-        A.cR[e * NC + r] = Rbi[r];
-        A.cR[t * NC + r] = Rbj[r];
-        A.cU[e * NC + r] = Ubi[r];
-        A.cU[t * NC + r] = Ubj[r];
+        if (side1) Pbi[r] += Pab[r]; else Pbj[r] += Pab[r];
+        Z[r] = Bj.coef * Pbj[r] - Bi.coef * Pbi[r];
+        kb -= Z[r] * (Bj.U[r] - Bi.U[r]);
     }
-    A.cal[e] = albi;
-    A.cal[t] = albj;
-    A.dbp[p_] = dLb;
+    const double dH = dL * (Bi.alpha + Bj.alpha) / 2.0;
+    double re[kC1S], rt[kC1S];
+#pragma unroll
+    for (int r = 0; r < kC1S; ++r) { re[r] = 0.0; rt[r] = 0.0; }
+    double *ra = side1 ? re : rt;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) ra[r] = ULb[r];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) ra[NC + q] = bb[q];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) { re[8 + r] = Z[r]; rt[8 + r] = -Z[r]; }
+    re[13] = rt[13] = kb * dL / 2.0;
+    re[14] = rt[14] = dH - dL;
+    scatter<kC1S / 2>(A.C, kC1S, valid_ ? int(e) : -1, lw, re);
+    scatter<kC1S / 2>(A.C, kC1S, valid_ ? int(t) : -1, lw, rt);
+    if (valid_) A.dLb[p_] = kb * ((Bi.alpha + Bj.alpha) / 2.0 - 1.0);
 }
 
-// low-order update, bar states and bounds backwards (row)
+// low-order update, bar states and bounds backwards (row).  The row's
+// records give the totals of U^L_i's, the bounds', R_i's cotangents; then
+// Lw_i = sum_j (-(f_j - f_i).c_ij + d_ij (U_j - U_i)) and R_i (with d^H)
+// run backwards for what belongs to node i itself: U_i's own part, d_ij's
+// share of row i (db4, per entry), alpha_i's own share.  The neighbours'
+// shares are pulled by the neighbours from the node record.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_low(StageArgs P, AdjArgs A)
 {
-    ROW_SETUP(P)
-    constexpr int NC = D + 2, NS = kNodeSlot<D>;
+    WAVE_LDS(kC1S / 2)
+    WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
+    (void)inst_;   // one instance: adjoints run on single meshes
+    constexpr int NC = D + 2, NU = (NC + 1) / 2;
     const double g = P.gamma;
+    const int dk = valid_ ? P.diag_k[r_] : -1;
     NodeA<D> Ai;
     load_a<D>(P.packA + int64_t(i) * kPack, Ai);
-    const double alpha_i = P.alpha[i];
+    const double al_i = P.packA[int64_t(i) * kPack + kPackAlpha];
     const double mi = P.mi[i];
-    // cotangents of R_i, U^L_i and the bounds of row i
-    double Rb[NC], ULb[NC], bnd[3];
+    double ULb[NC], bnd[3], Rb[NC], Ud[NC], alb = 0.0;
 #pragma unroll
-    for (int r = 0; r < NC; ++r) { Rb[r] = 0.0; ULb[r] = A.Upb[int64_t(i) * NC + r]; }
+    for (int r = 0; r < NC; ++r) {
+        ULb[r] = A.Upb[int64_t(i) * kUpS + r];
+        Rb[r] = 0.0;
+        Ud[r] = 0.0;
+    }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) bnd[q] = A.bndb[int64_t(i) * 3 + q];
-    double Fi[NC][D];
-    flux<D>(Ai.U, Ai.v, Ai.p, Fi);
-    // forward pass over the row: the entries that set the bounds
-    double rho_min = Ai.U[0], rho_max = Ai.U[0], phi_min = Ai.phi;
-    int kmin = -1, kmax = -1, kphi = -1;
-    for (int k = 0; k < L; ++k) {
+    for (int q = 0; q < 3; ++q) bnd[q] = A.Upb[int64_t(i) * kUpS + NC + q];
+    for (int k = 0; k < Lmax_; ++k) {
         const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        if (j == i) continue;
-        const double *cn = A.cnode + e * NS;
-        const double *cr = A.cR + e * NC;
+        const bool act = k < L && k != dk;
+        double rec[kC1S];
+        gather<kC1S / 2>(A.C, kC1S, act ? int(e) : -1, lw, rec);
+        if (!act) continue;
+        const double b = -P.mij[e] / mi;
 #pragma unroll
-        for (int r = 0; r < NC; ++r) { ULb[r] += cn[r]; Rb[r] += cr[r]; }
-        bnd[0] += cn[NC];
-        bnd[1] += cn[NC + 1];
-        bnd[2] += cn[NC + 2];
-        NodeA<D> Aj;
-        load_a<D>(P.packA + int64_t(j) * kPack, Aj);
+        for (int r = 0; r < NC; ++r) {
+            ULb[r] += rec[r];
+            Rb[r] += b * rec[8 + r];
+            Ud[r] += rec[14] * rec[8 + r];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) bnd[q] += rec[NC + q];
+        alb += rec[13];
+    }
+    double Lwb[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) Lwb[r] = A.tau / mi * ULb[r];
+    const int ak = valid_ ? P.argk[i] : 0xFFFFFF;
+    const int kmin = ak & 255, kmax = (ak >> 8) & 255, kphi = (ak >> 16) & 255;
+    int idmin = -1, idmax = -1, idphi = -1;
+    double Uo[NC], Sc[D], Fb0[D];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) Uo[r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) { Sc[q] = 0.0; Fb0[q] = 0.0; }
+    int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+    for (int k = 0; k < Lmax_; ++k) {
+        const int64_t e = ENTRY(k);
+        const int j = jn;
+        if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
+        const bool act = k < L && k != dk;
+        double rec[2 * (NU + 1)];
+        gather_tail<NU + 1, kPackAlpha / 2>(P.packA, kPack, act ? j : -1, lw, rec);
+        if (!act) continue;
+        const double al_j = rec[2 * NU];
         double c[D];
         load_c<D>(P, e, c);
         const double dL = P.d[e];
-        double Fj[NC][D], fd[NC];
-        flux<D>(Aj.U, Aj.v, Aj.p, Fj);
-        flux_diff_dot<D>(Fi, Fj, c, fd);
-        double rbar = 0.5 * (Ai.U[0] + Aj.U[0]);
-        if (dL > 0.0) rbar -= fd[0] / (2.0 * dL);
-        if (rbar < rho_min) { rho_min = rbar; kmin = k; }
-        if (rbar > rho_max) { rho_max = rbar; kmax = k; }
-        if (Aj.phi < phi_min) { phi_min = Aj.phi; kphi = k; }
+        const double dH = dL * (al_i + al_j) / 2.0;
+        double dLb = 0.0, dHb = 0.0;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            const double dU = rec[r] - Ai.U[r];
+            dHb += Rb[r] * dU;
+            dLb += Lwb[r] * dU;
+            Uo[r] -= dL * Lwb[r] + dH * Rb[r];
+        }
+        dLb += dHb * (al_i + al_j) / 2.0;
+        alb += dHb * dL / 2.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) Sc[q] += c[q];
+        double rb = 0.0;
+        if (k == kmin) { rb += bnd[0]; idmin = j; }
+        if (k == kmax) { rb += bnd[1]; idmax = j; }
+        if (k == kphi) idphi = j;
+        if (rb != 0.0) {
+            Uo[0] += 0.5 * rb;
+            if (dL > 0.0) {
+                double fd0 = 0.0;
+#pragma unroll
+                for (int q = 0; q < D; ++q) fd0 += (rec[1 + q] - Ai.U[1 + q]) * c[q];
+#pragma unroll
+                for (int q = 0; q < D; ++q) Fb0[q] += rb / (2.0 * dL) * c[q];
+                dLb += rb * fd0 / (2.0 * dL * dL);
+            }
+        }
+        A.db4[e] = dLb;
     }
-    double Lwb[NC], Ubi[NC];
+    if (kmin == 255) Uo[0] += bnd[0];
+    if (kmax == 255) Uo[0] += bnd[1];
+    NodeCot<D> ci;
+    cot_zero<D>(ci);
+    if (kphi == 255) ci.phi = bnd[2];
+    double Fb[NC][D];
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+        for (int q = 0; q < D; ++q) Fb[r][q] = (Lwb[r] + Rb[r]) * Sc[q];
+#pragma unroll
+    for (int q = 0; q < D; ++q) Fb[0][q] += Fb0[q];
+    flux_vjp<D>(Ai.U, Ai.v, Ai.p, Fb, ci);
+    double Up[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) Up[r] = ULb[r] + Ud[r] + Uo[r];
+    node_vjp<D>(Ai.U, Ai.p, Ai.c, Ai.er, Ai.phi, g, ci, false, Up);
+    double nr[kNS];
+#pragma unroll
+    for (int r = 0; r < kNS; ++r) nr[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) { nr[r] = Lwb[r]; nr[5 + r] = Rb[r]; }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) nr[10 + q] = bnd[q];
+    nr[13] = al_i;
+    nr[14] = pack_ids(idmin, idmax);
+    nr[15] = pack_ids(idphi, -1);
+    scatter<kNS / 2>(A.Nrec, kNS, valid_ ? i : -1, lw, nr);
+    if (!valid_) return;
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
-        Lwb[r] = A.tau / mi * ULb[r];
-        Ubi[r] = ULb[r];
+        A.Up4[int64_t(i) * NC + r] = Up[r];
         A.ULt[int64_t(i) * NC + r] = ULb[r];
         A.Rt[int64_t(i) * NC + r] = Rb[r];
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) A.bndt[int64_t(i) * 3 + q] = bnd[q];
-    double Fbi[NC][D];
-#pragma unroll
-    for (int r = 0; r < NC; ++r)
-#pragma unroll
-        for (int q = 0; q < D; ++q) Fbi[r][q] = 0.0;
-    double albi = 0.0;
-    for (int k = 0; k < L; ++k) {
-        const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        double *cuj = A.cUj + e * NC;
-        if (j == i) {
-#pragma unroll
-            for (int r = 0; r < NC; ++r) cuj[r] = 0.0;
-            A.calj[e] = 0.0;
-            A.db3[e] = 0.0;
-            continue;
-        }
-        NodeA<D> Aj;
-        load_a<D>(P.packA + int64_t(j) * kPack, Aj);
-        const double alpha_j = P.packA[int64_t(j) * kPack + kPackAlpha];
-        double c[D];
-        load_c<D>(P, e, c);
-        const double dL = P.d[e];
-        const double dH = dL * (alpha_i + alpha_j) / 2.0;
-        double Fj[NC][D], fd[NC];
-        flux<D>(Aj.U, Aj.v, Aj.p, Fj);
-        flux_diff_dot<D>(Fi, Fj, c, fd);
-        double fdb[NC], Ujb[NC];
-        double dHb = 0.0, dLb = 0.0;
-#pragma unroll
-        for (int r = 0; r < NC; ++r) {
-            const double dU = Aj.U[r] - Ai.U[r];
-            fdb[r] = -Lwb[r] - Rb[r];
-            dHb += Rb[r] * dU;
-            dLb += Lwb[r] * dU;
-            Ujb[r] = dL * Lwb[r] + dH * Rb[r];
-            Ubi[r] -= Ujb[r];
-        }
-        dLb += dHb * (alpha_i + alpha_j) / 2.0;
-        albi += dHb * dL / 2.0;
-        const double albj = dHb * dL / 2.0;
-        double rb = 0.0;
-        if (k == kmin) rb += bnd[0];
-        if (k == kmax) rb += bnd[1];
-        if (rb != 0.0) {
-            Ubi[0] += 0.5 * rb;
-            Ujb[0] += 0.5 * rb;
-            if (dL > 0.0) {
-                fdb[0] -= rb / (2.0 * dL);
-                dLb += rb * fd[0] / (2.0 * dL * dL);
-            }
-        }
-        NodeCot<D> cj;
-        cot_zero<D>(cj);
-        if (k == kphi) cj.phi = bnd[2];
-        double Fbj[NC][D];
-#pragma unroll
-        for (int r = 0; r < NC; ++r)
-#pragma unroll
-            for (int q = 0; q < D; ++q) {
-                Fbj[r][q] = fdb[r] * c[q];
-                Fbi[r][q] -= fdb[r] * c[q];
-            }
-        flux_vjp<D>(Aj.U, Aj.v, Aj.p, Fbj, cj);
-        node_vjp<D>(Aj.U, Aj.p, Aj.c, Aj.er, Aj.phi, g, cj, false, Ujb);
-#pragma unroll
-        for (int r = 0; r < NC; ++r) cuj[r] = Ujb[r];
-        A.calj[e] = albj;
-        A.db3[e] = dLb;
-    }
-    if (kmin < 0) Ubi[0] += bnd[0];
-    if (kmax < 0) Ubi[0] += bnd[1];
-    NodeCot<D> ci;
-    cot_zero<D>(ci);
-    if (kphi < 0) ci.phi = bnd[2];
-    flux_vjp<D>(Ai.U, Ai.v, Ai.p, Fbi, ci);
-    node_vjp<D>(Ai.U, Ai.p, Ai.c, Ai.er, Ai.phi, g, ci, false, Ubi);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) A.Ub3[int64_t(i) * NC + r] = Ubi[r];
-    A.alb[i] = albi;
+    A.alb[i] = alb;
 }
 
-// indicator alpha_i backwards (row)
+// indicator alpha_i (Section 3.8) backwards, with what the neighbours' low
+// order owes node i (row).  alpha_i's total cotangent adds the neighbours'
+// R_j shares; the indicator's sums a_i and b_i are recomputed as the
+// forward does and run backwards.  U_i's part: the indicator's own terms
+// and, from each neighbour j's record, d_ij Lw_j + d^H R_j bar, the flux
+// terms through c_ji, and the bar-state and phi terms where node i set a
+// bound of row j.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_alpha(StageArgs P, AdjArgs A)
 {
-    ROW_SETUP(P)
+    WAVE_LDS(kNS / 2)
+    WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
+    (void)inst_;   // one instance: adjoints run on single meshes
     constexpr int NC = D + 2;
+    constexpr int NCH = (NC + 4 + D) / 2;   // U, p, c, eta/rho, v, phi
     const double g = P.gamma;
-    double alb = A.alb[i];
-    for (int k = 0; k < L; ++k) {
-        const int64_t e = ENTRY(k);
-        if (P.scol[e] == i) continue;
-        alb += A.cal[e] + A.calj[P.stpos[e]];
-    }
-    A.alt[i] = alb;
-    double Ubi[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) Ubi[r] = 0.0;
+    const int dk = valid_ ? P.diag_k[r_] : -1;
     NodeA<D> Ai;
     load_a<D>(P.packA + int64_t(i) * kPack, Ai);
+    const double al_i = P.packA[int64_t(i) * kPack + kPackAlpha];
     double Fi[NC][D];
     flux<D>(Ai.U, Ai.v, Ai.p, Fi);
-    double a = 0.0, b[NC];
+    double a = 0.0, b[NC], MC = 0.0, Sc[D], alb = valid_ ? A.alb[i] : 0.0;
+    double Fb[NC][D], Up[NC];
+    NodeCot<D> ci;
+    cot_zero<D>(ci);
 #pragma unroll
-    for (int r = 0; r < NC; ++r) b[r] = 0.0;
-    for (int k = 0; k < L; ++k) {
+    for (int r = 0; r < NC; ++r) {
+        b[r] = 0.0;
+        Up[r] = 0.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) Fb[r][q] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) Sc[q] = 0.0;
+    int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+    for (int k = 0; k < Lmax_; ++k) {
         const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
+        const int j = jn;
+        if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
+        const bool in = k < L;
+        const bool act = in && k != dk;
+        double ra[2 * NCH], rn[kNS];
+        gather<NCH>(P.packA, kPack, in ? j : -1, lw, ra);
+        gather<kNS / 2>(A.Nrec, kNS, act ? j : -1, lw, rn);
+        if (!in) continue;
         NodeA<D> Aj;
-        load_a<D>(P.packA + int64_t(j) * kPack, Aj);
+        unpack_a<D>(ra, Aj);
         double c[D];
         load_c<D>(P, e, c);
         double mc = 0.0;
@@ -848,7 +835,40 @@ __global__ void __launch_bounds__(kBlock) k_adj_alpha(StageArgs P, AdjArgs A)
         flux_diff_dot<D>(Fi, Fj, c, fd);
 #pragma unroll
         for (int r = 0; r < NC; ++r) b[r] += fd[r];
+        if (!act) continue;
+        MC += mc;
+#pragma unroll
+        for (int q = 0; q < D; ++q) Sc[q] += c[q];
+        // neighbour j's low order: Lw_j, R_j with d_ji = d_ij, c_ji
+        const double dL = P.d[e];
+        const double al_j = rn[13];
+        double ct[D];
+        ct[0] = P.ct0[e];
+        ct[1] = P.ct1[e];
+        if (D == 3) ct[D - 1] = P.ct2[e];
+        const double dH = dL * (al_j + al_i) / 2.0;
+        double rdu = 0.0;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            rdu += rn[5 + r] * (Ai.U[r] - Aj.U[r]);
+            Up[r] += dL * rn[r] + dH * rn[5 + r];
+#pragma unroll
+            for (int q = 0; q < D; ++q) Fb[r][q] -= (rn[r] + rn[5 + r]) * ct[q];
+        }
+        alb += rdu * dL / 2.0;
+        double rb = 0.0;
+        if (id_lo(rn[14]) == i) rb += rn[10];
+        if (id_hi(rn[14]) == i) rb += rn[11];
+        if (rb != 0.0) {
+            Up[0] += 0.5 * rb;
+            if (dL > 0.0) {
+#pragma unroll
+                for (int q = 0; q < D; ++q) Fb[0][q] -= rb / (2.0 * dL) * ct[q];
+            }
+        }
+        if (id_lo(rn[15]) == i) ci.phi += rn[12];
     }
+    // alpha_i = |X| / Dn with X = a - eta'(U_i).b + (eta/rho)_i b_rho
     double etap[NC];
     harten_entropy_derivative<D>(Ai.U, g, etap);
     double etab = 0.0;
@@ -859,8 +879,6 @@ __global__ void __launch_bounds__(kBlock) k_adj_alpha(StageArgs P, AdjArgs A)
     double Dn = fabs(a);
 #pragma unroll
     for (int r = 0; r < NC; ++r) Dn += fabs(etap[r] - (r == 0 ? Ai.er : 0.0)) * fabs(b[r]);
-    NodeCot<D> ci;
-    cot_zero<D>(ci);
     double ab = 0.0, bb[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) bb[r] = 0.0;
@@ -886,143 +904,158 @@ __global__ void __launch_bounds__(kBlock) k_adj_alpha(StageArgs P, AdjArgs A)
             bb[r] += Dnb * fabs(Y) * sgn(b[r]);
         }
     }
-    double Fbi[NC][D];
+    // the indicator's own terms: a_i through eta/rho_i, b_i through f(U_i)
+    ci.er -= ab * MC;
 #pragma unroll
     for (int r = 0; r < NC; ++r)
 #pragma unroll
-        for (int q = 0; q < D; ++q) Fbi[r][q] = 0.0;
-    for (int k = 0; k < L; ++k) {
-        const int64_t e = ENTRY(k);
-        const int j = P.scol[e];
-        double *cuj = A.cUj2 + e * NC;
-        double Ujb[NC];
+        for (int q = 0; q < D; ++q) Fb[r][q] -= bb[r] * Sc[q];
+    flux_vjp<D>(Ai.U, Ai.v, Ai.p, Fb, ci);
+    node_vjp<D>(Ai.U, Ai.p, Ai.c, Ai.er, Ai.phi, g, ci, true, Up);
+    double ir[kIS];
 #pragma unroll
-        for (int r = 0; r < NC; ++r) Ujb[r] = 0.0;
-        {
-            NodeA<D> Aj;
-            load_a<D>(P.packA + int64_t(j) * kPack, Aj);
-            double c[D];
-            load_c<D>(P, e, c);
-            double mc = 0.0;
+    for (int r = 0; r < kIS; ++r) ir[r] = 0.0;
+    ir[0] = ab;
 #pragma unroll
-            for (int q = 0; q < D; ++q) mc += Aj.U[1 + q] * c[q];
-            NodeCot<D> cj;
-            cot_zero<D>(cj);
-            cj.er = ab * mc;
-            ci.er -= ab * mc;
+    for (int r = 0; r < NC; ++r) ir[1 + r] = bb[r];
+    ir[6] = Ai.er;
+    scatter<kIS / 2>(A.Irec, kIS, valid_ ? i : -1, lw, ir);
+    if (!valid_) return;
 #pragma unroll
-            for (int q = 0; q < D; ++q) cj.U[1 + q] += ab * (Aj.er - Ai.er) * c[q];
-            double Fbj[NC][D];
-#pragma unroll
-            for (int r = 0; r < NC; ++r)
-#pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    Fbj[r][q] = bb[r] * c[q];
-                    Fbi[r][q] -= bb[r] * c[q];
-                }
-            flux_vjp<D>(Aj.U, Aj.v, Aj.p, Fbj, cj);
-            node_vjp<D>(Aj.U, Aj.p, Aj.c, Aj.er, Aj.phi, g, cj, false, Ujb);
-        }
-        if (j == i) {
-#pragma unroll
-            for (int r = 0; r < NC; ++r) { Ubi[r] += Ujb[r]; cuj[r] = 0.0; }
-        } else {
-#pragma unroll
-            for (int r = 0; r < NC; ++r) cuj[r] = Ujb[r];
-        }
-    }
-    flux_vjp<D>(Ai.U, Ai.v, Ai.p, Fbi, ci);
-    node_vjp<D>(Ai.U, Ai.p, Ai.c, Ai.er, Ai.phi, g, ci, true, Ubi);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) A.Ub2[int64_t(i) * NC + r] = Ubi[r];
+    for (int r = 0; r < NC; ++r) A.Up6[int64_t(i) * NC + r] = Up[r];
+    A.alt[i] = alb;
 }
 
-// graph viscosity backwards (pair): the active orientation of the max
+// graph viscosity backwards (pair): d_ij's total cotangent (the
+// directions', rows i's and j's low order) through the active orientation
+// of the max to both states.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_dpair(StageArgs P, AdjArgs A)
 {
-    ADJ_PAIR_SETUP(P)
     constexpr int NC = D + 2;
-    const double db = A.dbp[p_] + A.db3[e] + A.db3[t];
-    A.dbp[p_] = db;
-    if (db == 0.0) return;
-    NodeA<D> Ai, Aj;
-    load_a<D>(P.packA + int64_t(i) * kPack, Ai);
-    load_a<D>(P.packA + int64_t(j) * kPack, Aj);
-    double c[D], ct[D];
-    load_c<D>(P, e, c);
-    ct[0] = P.ct0[e];
-    ct[1] = P.ct1[e];
-    if (D == 3) ct[D - 1] = P.ct2[e];
-    double aij = 0.0, aji = 0.0;
+    constexpr int NCH = (NC + 3) / 2;   // U, p, c
+    WAVE_LDS(NCH)
+    WAVE_PAIR_SETUP(P, PAIR_INDEX(P), P.npairs)
+    double Ai[2 * NCH], Aj[2 * NCH];
+    gather<NCH>(P.packA, kPack, i, lw, Ai);
+    gather<NCH>(P.packA, kPack, j, lw, Aj);
+    const double db = A.dLb[pq_] + A.db4[e] + A.db4[t];
+    double Ubi[kC5S], Ubj[kC5S];
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-        aij += c[q] * c[q];
-        aji += ct[q] * ct[q];
-    }
-    aij = sqrt(aij);
-    aji = sqrt(aji);
-    double nij[D], nji[D], t1 = 0.0, t2 = 0.0;
-    if (aij > 0.0) {
-        const double inv = 1.0 / aij;
+    for (int r = 0; r < kC5S; ++r) { Ubi[r] = 0.0; Ubj[r] = 0.0; }
+    if (valid_ && db != 0.0) {
+        double c[D], ct[D];
+        load_c<D>(P, e, c);
+        ct[0] = P.ct0[e];
+        ct[1] = P.ct1[e];
+        if (D == 3) ct[D - 1] = P.ct2[e];
+        double aij = 0.0, aji = 0.0;
 #pragma unroll
-        for (int q = 0; q < D; ++q) nij[q] = c[q] * inv;
-        t1 = lambda_max<D>(nij, Ai.U, Ai.p, Ai.c, Aj.U, Aj.p, Aj.c, P.gas) * aij;
-    }
-    if (aji > 0.0) {
-        const double inv = 1.0 / aji;
+        for (int q = 0; q < D; ++q) {
+            aij += c[q] * c[q];
+            aji += ct[q] * ct[q];
+        }
+        aij = sqrt(aij);
+        aji = sqrt(aji);
+        const double pi = Ai[NC], ci_ = Ai[NC + 1], pj = Aj[NC], cj_ = Aj[NC + 1];
+        double nij[D], nji[D], t1 = 0.0, t2 = 0.0;
+        if (aij > 0.0) {
+            const double inv = 1.0 / aij;
 #pragma unroll
-        for (int q = 0; q < D; ++q) nji[q] = ct[q] * inv;
-        t2 = lambda_max<D>(nji, Aj.U, Aj.p, Aj.c, Ai.U, Ai.p, Ai.c, P.gas) * aji;
-    }
-    NodeCot<D> bi, bj;
-    cot_zero<D>(bi);
-    cot_zero<D>(bj);
-    if (t1 > t2) {
-        if (aij > 0.0)
-            lambda_vjp<D>(nij, Ai.U, Ai.p, Ai.c, Aj.U, Aj.p, Aj.c, P.gas, db * aij, bi, bj);
-    } else if (aji > 0.0) {
-        lambda_vjp<D>(nji, Aj.U, Aj.p, Aj.c, Ai.U, Ai.p, Ai.c, P.gas, db * aji, bj, bi);
-    }
-    double Ubi[NC], Ubj[NC];
+            for (int q = 0; q < D; ++q) nij[q] = c[q] * inv;
+            t1 = lambda_max<D>(nij, Ai, pi, ci_, Aj, pj, cj_, P.gas) * aij;
+        }
+        if (aji > 0.0) {
+            const double inv = 1.0 / aji;
 #pragma unroll
-    for (int r = 0; r < NC; ++r) { Ubi[r] = 0.0; Ubj[r] = 0.0; }
-    node_vjp<D>(Ai.U, Ai.p, Ai.c, Ai.er, Ai.phi, P.gamma, bi, false, Ubi);
-    node_vjp<D>(Aj.U, Aj.p, Aj.c, Aj.er, Aj.phi, P.gamma, bj, false, Ubj);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) {
-        A.cU[e * NC + r] += Ubi[r];
-        A.cU[t * NC + r] += Ubj[r];
+            for (int q = 0; q < D; ++q) nji[q] = ct[q] * inv;
+            t2 = lambda_max<D>(nji, Aj, pj, cj_, Ai, pi, ci_, P.gas) * aji;
+        }
+        NodeCot<D> bi, bj;
+        cot_zero<D>(bi);
+        cot_zero<D>(bj);
+        if (t1 > t2) {
+            if (aij > 0.0)
+                lambda_vjp<D>(nij, Ai, pi, ci_, Aj, pj, cj_, P.gas, db * aij, bi, bj);
+        } else if (aji > 0.0) {
+            lambda_vjp<D>(nji, Aj, pj, cj_, Ai, pi, ci_, P.gas, db * aji, bj, bi);
+        }
+        node_vjp<D>(Ai, pi, ci_, 0.0, 0.0, P.gamma, bi, false, Ubi);
+        node_vjp<D>(Aj, pj, cj_, 0.0, 0.0, P.gamma, bj, false, Ubj);
     }
+    scatter<kC5S / 2>(A.C, kC5S, valid_ ? int(e) : -1, lw, Ubi);
+    scatter<kC5S / 2>(A.C, kC5S, valid_ ? int(t) : -1, lw, Ubj);
+    if (valid_) A.dLb[p_] = db;
 }
 
-// the node's cotangent: its own parts and its entries' and transposed
-// entries' slots, in row order
+// the node's cotangent (row): its low-order and indicator parts, the graph
+// viscosity's entry records, and what the neighbours' indicators owe it
+// (a_j through eta/rho_i and m_i, b_j through f(U_i), both along c_ji).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_final(StageArgs P, AdjArgs A)
 {
-    ROW_SETUP(P)
+    WAVE_LDS(kIS / 2)
+    WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
+    (void)inst_;   // one instance: adjoints run on single meshes
     constexpr int NC = D + 2;
-    double Ub[NC];
+    const int dk = valid_ ? P.diag_k[r_] : -1;
+    NodeA<D> Ai;
+    load_a<D>(P.packA + int64_t(i) * kPack, Ai);
+    double U[NC], Fb[NC][D];
 #pragma unroll
-    for (int r = 0; r < NC; ++r)
-        Ub[r] = A.Ub3[int64_t(i) * NC + r] + A.Ub2[int64_t(i) * NC + r];
-    for (int k = 0; k < L; ++k) {
-        const int64_t e = ENTRY(k);
-        if (P.scol[e] == i) continue;
-        const int64_t t = P.stpos[e];
+    for (int r = 0; r < NC; ++r) {
+        U[r] = A.Up4[int64_t(i) * NC + r] + A.Up6[int64_t(i) * NC + r];
 #pragma unroll
-        for (int r = 0; r < NC; ++r)
-            Ub[r] += A.cU[e * NC + r] + A.cUj[t * NC + r] + A.cUj2[t * NC + r];
+        for (int q = 0; q < D; ++q) Fb[r][q] = 0.0;
     }
+    NodeCot<D> ci;
+    cot_zero<D>(ci);
+    int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+    for (int k = 0; k < Lmax_; ++k) {
+        const int64_t e = ENTRY(k);
+        const int j = jn;
+        if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
+        const bool act = k < L && k != dk;
+        double r5[kC5S], ri[kIS];
+        gather<kC5S / 2>(A.C, kC5S, act ? int(e) : -1, lw, r5);
+        gather<kIS / 2>(A.Irec, kIS, act ? j : -1, lw, ri);
+        if (!act) continue;
+        double ct[D];
+        ct[0] = P.ct0[e];
+        ct[1] = P.ct1[e];
+        if (D == 3) ct[D - 1] = P.ct2[e];
+        double mc = 0.0;
 #pragma unroll
-    for (int r = 0; r < NC; ++r) A.Ub[int64_t(i) * NC + r] = Ub[r];
+        for (int q = 0; q < D; ++q) mc += Ai.U[1 + q] * ct[q];
+        ci.er += ri[0] * mc;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            U[r] += r5[r];
+#pragma unroll
+            for (int q = 0; q < D; ++q) Fb[r][q] += ri[1 + r] * ct[q];
+        }
+#pragma unroll
+        for (int q = 0; q < D; ++q) U[1 + q] += ri[0] * (Ai.er - ri[6]) * ct[q];
+    }
+    flux_vjp<D>(Ai.U, Ai.v, Ai.p, Fb, ci);
+    node_vjp<D>(Ai.U, Ai.p, Ai.c, Ai.er, Ai.phi, P.gamma, ci, false, U);
+    if (!valid_) return;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) A.Ub[int64_t(i) * NC + r] = U[r];
+}
+
+// U's cotangent layout [n][nc] -> [n][kEbS]
+__global__ void k_adj_pad(int64_t n, int nc, const double *in, double *out)
+{
+    const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (q >= n * nc) return;
+    out[(q / nc) * kEbS + q % nc] = in[q];
 }
 
 // SSP-RK3 and the held nodes backwards, per node (stage k of a step):
 // out = hold ? U0 : U0 + theta (E - U0) with theta = 1 (stage 1: out = E),
-// 1/4, 2/3.  Eb = theta * outb off the held nodes; U0's cotangent gains
-// (1 - theta) outb (all of outb on a held node).
+// 1/4, 2/3.  Eb = theta * outb off the held nodes (layout [n][kEbS]); U0's
+// cotangent gains (1 - theta) outb (all of outb on a held node).
 __global__ void k_adj_ssp(int64_t n, int nc, const uint8_t *hold, const double *outb,
                           double theta, double *Eb, double *U0b, int first)
 {
@@ -1030,7 +1063,7 @@ __global__ void k_adj_ssp(int64_t n, int nc, const uint8_t *hold, const double *
     if (q >= n * nc) return;
     const bool h = hold && hold[q / nc];
     const double o = outb[q];
-    Eb[q] = h ? 0.0 : theta * o;
+    Eb[(q / nc) * kEbS + q % nc] = h ? 0.0 : theta * o;
     const double add = h ? o : (1.0 - theta) * o;
     U0b[q] = first ? add : U0b[q] + add;
 }
@@ -1042,9 +1075,9 @@ __global__ void k_adj_add(int64_t n, const double *x, double *y)
 }
 
 // ------------------------------------------------------------ launches
-// row kernels use the XCD renumbering of ROW_SETUP: per * 8 blocks
+// row and pair sweeps use the XCD renumbering: per * 8 and pper * 8 blocks
 static inline int rows_grid(const StageArgs &P) { return P.per * kXcd; }
-static inline int pairs_grid(const StageArgs &P) { return int((P.npairs + kBlock - 1) / kBlock); }
+static inline int pairs_grid(const StageArgs &P) { return P.pper * kXcd; }
 
 #define ADJ_LAUNCH(K, grid)                                                              \
     do {                                                                                 \
@@ -1058,7 +1091,6 @@ static inline int pairs_grid(const StageArgs &P) { return int((P.npairs + kBlock
 
 void launch_stage_vjp(const StageArgs &P, const AdjArgs &A, hipStream_t st)
 {
-    ADJ_LAUNCH(k_adj_pass2, rows_grid(P));
     if (P.passes >= 2) ADJ_LAUNCH(k_adj_lim2, pairs_grid(P));
     ADJ_LAUNCH(k_adj_pass1, rows_grid(P));
     ADJ_LAUNCH(k_adj_lim1, pairs_grid(P));
@@ -1068,18 +1100,24 @@ void launch_stage_vjp(const StageArgs &P, const AdjArgs &A, hipStream_t st)
     ADJ_LAUNCH(k_adj_final, rows_grid(P));
 }
 
+static inline int flat_grid(int64_t m) { return int((m + kBlock - 1) / kBlock); }
+
+void launch_adj_pad(hipStream_t st, int64_t n, int nc, const double *in, double *out)
+{
+    if (n > 0) hipLaunchKernelGGL(k_adj_pad, dim3(flat_grid(n * nc)), dim3(kBlock), 0, st, n, nc, in, out);
+}
+
 void launch_adj_ssp(hipStream_t st, int64_t n, int nc, const uint8_t *hold, const double *outb,
                     double theta, double *Eb, double *U0b, int first)
 {
-    const int64_t m = n * nc;
-    hipLaunchKernelGGL(k_adj_ssp, dim3(int((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, nc,
-                       hold, outb, theta, Eb, U0b, first);
+    if (n > 0)
+        hipLaunchKernelGGL(k_adj_ssp, dim3(flat_grid(n * nc)), dim3(kBlock), 0, st, n, nc, hold,
+                           outb, theta, Eb, U0b, first);
 }
 
 void launch_adj_add(hipStream_t st, int64_t n, const double *x, double *y)
 {
-    hipLaunchKernelGGL(k_adj_add, dim3(int((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, x,
-                       y);
+    if (n > 0) hipLaunchKernelGGL(k_adj_add, dim3(flat_grid(n)), dim3(kBlock), 0, st, n, x, y);
 }
 
 }  // namespace idp

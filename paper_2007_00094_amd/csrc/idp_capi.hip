@@ -1,6 +1,7 @@
 // C-ABI of the library: context, precompute, SSP-RK3 stepper, exports.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -81,12 +82,21 @@ struct idp_ctx {
     // adjoint
     idp::AdjArgs A{};
     bool adj_ready = false;
-    double *Estage = nullptr, *U2 = nullptr, *Eb = nullptr, *acc = nullptr;
+    double *Estage = nullptr, *U2 = nullptr, *Ebp = nullptr, *acc = nullptr;
     double *bar[3] = {nullptr, nullptr, nullptr};
+    uint8_t *side1 = nullptr, *side2 = nullptr;   // records of a recomputed stage
+    int32_t *argk = nullptr;
     double *ckpt = nullptr;          // [slots][n][nc]
     int64_t ckpt_slots = 0;
     int ck_steps = -1, ck_every = 0;
     std::vector<double> ck_dt;
+    // tape: the per-stage arrays of tape_steps steps (3 stage argument sets
+    // each), so that a segment recomputed once serves its whole backward
+    void *tape_mem = nullptr;
+    size_t tape_bytes = 0;
+    int tape_steps = 0;
+    std::vector<idp::StageArgs> tape;
+    bool tape_last = false;          // holds the last segment of the forward
     // timing
     bool timing = false;
     std::vector<Pending> pending;
@@ -196,10 +206,11 @@ int status_code(int st)
 // One forward-Euler stage on the context stream.
 //  in: stage input state; U0: step-initial state; out: destination;
 //  tau_mode: 1 select tau (stage 1), 0 check the held tau, 2 use dt_in.
-void stage(idp_ctx *c, const double *in, const double *U0, double *out, int mode,
-           int tau_mode, double dt_in, int check, int clear)
+//  P: the stage's arguments (the context's, or a set whose per-stage arrays
+//  live elsewhere, e.g. in the adjoint's tape).
+void stage_p(idp_ctx *c, const idp::StageArgs &P, const double *in, const double *U0,
+             double *out, int mode, int tau_mode, double dt_in, int check, int clear)
 {
-    const idp::StageArgs &P = c->P;
     hipStream_t st = c->stream;
     timed(c, K_BEGIN, [&] { idp::launch_begin(P, st, clear); });
     timed(c, K_NODE, [&] { idp::launch_node(P, st, in, check); });
@@ -211,6 +222,12 @@ void stage(idp_ctx *c, const double *in, const double *U0, double *out, int mode
     timed(c, K_PASS1A, [&] { idp::launch_pass1a(P, st); });
     if (P.passes >= 2) timed(c, K_LIM2P, [&] { idp::launch_lim2p(P, st); });
     timed(c, K_PASS2, [&] { idp::launch_pass2(P, st, U0, out, mode); });
+}
+
+void stage(idp_ctx *c, const double *in, const double *U0, double *out, int mode,
+           int tau_mode, double dt_in, int check, int clear)
+{
+    stage_p(c, c->P, in, U0, out, mode, tau_mode, dt_in, check, clear);
 }
 
 }  // namespace
@@ -241,6 +258,7 @@ void idp_destroy(idp_ctx *c)
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     for (void *q : c->allocs) (void)hipFree(q);
+    if (c->tape_mem) (void)hipFree(c->tape_mem);
     delete c;
 }
 
@@ -735,40 +753,37 @@ namespace {
 int adj_setup(idp_ctx *c)
 {
     if (c->adj_ready) return IDP_OK;
+    // the stage records keep row positions in 8 bits (255: none)
+    for (int64_t i = 0; i < c->n; ++i)
+        if (c->row_ptr[i + 1] - c->row_ptr[i] > 254) return IDP_ENOTSUP;
     const int nc = c->prm.dim + 2;
     const int64_t n = c->n, S = c->sell_size, np = c->P.npairs;
     idp::AdjArgs &A = c->A;
-    double *Eb = nullptr;
     int e = IDP_OK;
 #define ADJ_ALLOC(ptr, count) if ((e = dalloc(c, &(ptr), (count))) != IDP_OK) return e
-    ADJ_ALLOC(A.Upb, n * nc);
-    ADJ_ALLOC(A.bndb, n * 3);
-    ADJ_ALLOC(A.Ub3, n * nc);
-    ADJ_ALLOC(A.Ub2, n * nc);
+    ADJ_ALLOC(c->Ebp, n * idp::kEbS);
+    ADJ_ALLOC(A.Upb, n * idp::kUpS);
+    ADJ_ALLOC(A.Nrec, n * idp::kNS);
+    ADJ_ALLOC(A.Irec, n * idp::kIS);
+    ADJ_ALLOC(A.Up4, n * nc);
+    ADJ_ALLOC(A.Up6, n * nc);
     ADJ_ALLOC(A.alb, n);
-    ADJ_ALLOC(A.sb1, S);
-    ADJ_ALLOC(A.sb2, S);
-    ADJ_ALLOC(A.Pb, S * nc);
-    ADJ_ALLOC(A.cnode, S * (nc + 3));
-    ADJ_ALLOC(A.cR, S * nc);
-    ADJ_ALLOC(A.cU, S * nc);
-    ADJ_ALLOC(A.cal, S);
-    ADJ_ALLOC(A.dbp, np);
-    ADJ_ALLOC(A.cUj, S * nc);
-    ADJ_ALLOC(A.cUj2, S * nc);
-    ADJ_ALLOC(A.calj, S);
-    ADJ_ALLOC(A.db3, S);
+    ADJ_ALLOC(A.C, S * idp::kC1S);
+    ADJ_ALLOC(A.db4, S);
+    ADJ_ALLOC(A.Qb, np * idp::kQS);
+    ADJ_ALLOC(A.dLb, np);
     ADJ_ALLOC(A.ULt, n * nc);
     ADJ_ALLOC(A.Rt, n * nc);
     ADJ_ALLOC(A.bndt, n * 3);
     ADJ_ALLOC(A.alt, n);
     ADJ_ALLOC(c->Estage, n * nc);
     ADJ_ALLOC(c->U2, n * nc);
-    ADJ_ALLOC(Eb, n * nc);
     ADJ_ALLOC(c->acc, n * nc);
     for (int k = 0; k < 3; ++k) ADJ_ALLOC(c->bar[k], n * nc);
+    ADJ_ALLOC(c->side1, np);
+    ADJ_ALLOC(c->side2, np);
+    ADJ_ALLOC(c->argk, n);
 #undef ADJ_ALLOC
-    c->Eb = Eb;
     c->adj_ready = true;
     return IDP_OK;
 }
@@ -779,36 +794,153 @@ int adj_check(idp_ctx *c)
     return adj_setup(c);
 }
 
-// Recompute the stage at U (its intermediates), then run it backwards.
-void stage_vjp(idp_ctx *c, const double *U, double tau, const double *Eb, double *Ub, int clear)
+// The context's stage arguments with the adjoint's records switched on.
+idp::StageArgs rec_args(const idp_ctx *c)
 {
-    stage(c, U, U, c->Estage, 0, 2, tau, 1, clear);
-    idp::AdjArgs A = c->A;
-    A.tau = tau;
-    A.Eb = Eb;
-    A.Ub = Ub;
-    timed(c, K_VJP, [&] { idp::launch_stage_vjp(c->P, A, c->stream); });
+    idp::StageArgs P = c->P;
+    P.side1 = c->side1;
+    P.side2 = c->side2;
+    P.argk = c->argk;
+    return P;
 }
 
-// One SSP-RK3 step backwards (stages recomputed from U).
-void step_vjp(idp_ctx *c, const double *U, double dt, const double *Ubn, double *Ub, int clear)
+// ------------------------------------------------------------------ tape
+inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t tape_slot_bytes(const idp_ctx *c)
+{
+    const size_t S = size_t(c->sell_size), np = size_t(c->P.npairs), n = size_t(c->n);
+    return 3 * al256(S * 8) + 2 * al256(np * 8) + 2 * al256(n * idp::kPack * 8) +
+           al256(n * idp::kRowB * 8) + al256(n * idp::kRowU * 8) + al256(n * 8) +
+           2 * al256(np) + al256(n * 4);
+}
+
+// Room for `steps` steps (fewer if device memory is short: the largest
+// count that leaves 1/16 of the free memory, and at least 1 GiB, free).
+int tape_reserve(idp_ctx *c, int steps)
+{
+    if (c->tape_steps >= steps) return IDP_OK;
+    if (c->tape_mem) {
+        (void)hipFree(c->tape_mem);
+        c->tape_mem = nullptr;
+        c->tape_bytes = 0;
+        c->tape_steps = 0;
+        c->tape.clear();
+        c->tape_last = false;
+    }
+    const size_t slot = tape_slot_bytes(c);
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return IDP_EHIP;
+    }
+    const size_t keep = std::max<size_t>(size_t(1) << 30, fr / 16);
+    const int64_t fit = fr > keep ? int64_t((fr - keep) / (3 * slot)) : 0;
+    int want = int(std::min<int64_t>(steps, fit));
+    void *mem = nullptr;
+    while (want > 0) {
+        if (hipMalloc(&mem, size_t(want) * 3 * slot) == hipSuccess) break;
+        (void)hipGetLastError();
+        mem = nullptr;
+        want /= 2;
+    }
+    if (!mem) return IDP_OK;           // no tape: the backward recomputes per stage
+    c->tape_mem = mem;
+    c->tape_bytes = size_t(want) * 3 * slot;
+    c->tape_steps = want;
+    c->tape.assign(size_t(want) * 3, c->P);
+    const size_t S = size_t(c->sell_size), np = size_t(c->P.npairs), n = size_t(c->n);
+    for (size_t k = 0; k < c->tape.size(); ++k) {
+        char *q = static_cast<char *>(mem) + k * slot;
+        auto take = [&](size_t b) { char *r = q; q += al256(b); return r; };
+        idp::StageArgs &P = c->tape[k];
+        P.d = reinterpret_cast<double *>(take(S * 8));
+        P.l1 = reinterpret_cast<double *>(take(S * 8));
+        P.l2 = reinterpret_cast<double *>(take(S * 8));
+        P.dp = reinterpret_cast<double *>(take(np * 8));
+        P.l1p = reinterpret_cast<double *>(take(np * 8));
+        P.packA = reinterpret_cast<double *>(take(n * idp::kPack * 8));
+        P.packB = reinterpret_cast<double *>(take(n * idp::kPack * 8));
+        P.rowB = reinterpret_cast<double *>(take(n * idp::kRowB * 8));
+        P.upass = reinterpret_cast<double *>(take(n * idp::kRowU * 8));
+        P.alpha = reinterpret_cast<double *>(take(n * 8));
+        P.side1 = reinterpret_cast<uint8_t *>(take(np));
+        P.side2 = reinterpret_cast<uint8_t *>(take(np));
+        P.argk = reinterpret_cast<int32_t *>(take(n * 4));
+    }
+    return IDP_OK;
+}
+
+// One SSP-RK3 step in place on U whose three stages keep their arrays in
+// tape step `slot` (the same arithmetic as idp_step with a given dt).
+void tape_step(idp_ctx *c, int slot, double *U, double dt, int clear)
+{
+    const idp::StageArgs *T = c->tape.data() + 3 * slot;
+    stage_p(c, T[0], U, U, c->U1, 1, 1, dt, 1, clear);
+    stage_p(c, T[1], c->U1, U, c->U1, 2, 0, 0.0, 0, 0);
+    stage_p(c, T[2], c->U1, U, U, 3, 0, 0.0, 0, 0);
+}
+
+// ------------------------------------------------------------- backward
+// The stage VJP on the intermediates held by P.
+void run_vjp(idp_ctx *c, const idp::StageArgs &P, double tau, const double *Ebp, double *Ub)
+{
+    idp::AdjArgs A = c->A;
+    A.tau = tau;
+    A.Ebp = Ebp;
+    A.Ub = Ub;
+    timed(c, K_VJP, [&] { idp::launch_stage_vjp(P, A, c->stream); });
+}
+
+// Recompute the stage at U (its intermediates and records), then run it
+// backwards; Ebp in the padded layout.
+void stage_vjp(idp_ctx *c, const double *U, double tau, const double *Ebp, double *Ub, int clear)
+{
+    const idp::StageArgs P = rec_args(c);
+    stage_p(c, P, U, U, c->Estage, 0, 2, tau, 1, clear);
+    run_vjp(c, P, tau, Ebp, Ub);
+}
+
+// One SSP-RK3 step backwards: prep(k) makes the intermediates of stage k
+// (0, 1, 2) current and returns the arguments that hold them.
+template <class F>
+void step_vjp_core(idp_ctx *c, double dt, const double *Ubn, double *Ub, F &&prep)
 {
     const int nc = c->prm.dim + 2;
     const int64_t n = c->n;
     const uint8_t *hold = c->P.hold;
-    stage(c, U, U, c->U1, 1, 2, dt, 1, clear);          // U1
-    stage(c, c->U1, U, c->U2, 2, 2, dt, 0, 0);          // U2
+    hipStream_t st = c->stream;
     // stage 3: U^{n+1} = U + 2/3 (E(U2) - U)
-    idp::launch_adj_ssp(c->stream, n, nc, hold, Ubn, 2.0 / 3.0, c->Eb, c->acc, 1);
-    stage_vjp(c, c->U2, dt, c->Eb, c->bar[1], 0);
+    idp::launch_adj_ssp(st, n, nc, hold, Ubn, 2.0 / 3.0, c->Ebp, c->acc, 1);
+    run_vjp(c, prep(2), dt, c->Ebp, c->bar[1]);
     // stage 2: U2 = U + 1/4 (E(U1) - U)
-    idp::launch_adj_ssp(c->stream, n, nc, hold, c->bar[1], 0.25, c->Eb, c->acc, 0);
-    stage_vjp(c, c->U1, dt, c->Eb, c->bar[2], 0);
+    idp::launch_adj_ssp(st, n, nc, hold, c->bar[1], 0.25, c->Ebp, c->acc, 0);
+    run_vjp(c, prep(1), dt, c->Ebp, c->bar[2]);
     // stage 1: U1 = E(U)
-    idp::launch_adj_ssp(c->stream, n, nc, hold, c->bar[2], 1.0, c->Eb, c->acc, 0);
-    stage_vjp(c, U, dt, c->Eb, c->bar[1], 0);
-    idp::launch_adj_add(c->stream, n * nc, c->bar[1], c->acc);
-    (void)hipMemcpyAsync(Ub, c->acc, size_t(n) * nc * 8, hipMemcpyDeviceToDevice, c->stream);
+    idp::launch_adj_ssp(st, n, nc, hold, c->bar[2], 1.0, c->Ebp, c->acc, 0);
+    run_vjp(c, prep(0), dt, c->Ebp, c->bar[1]);
+    idp::launch_adj_add(st, n * nc, c->bar[1], c->acc);
+    (void)hipMemcpyAsync(Ub, c->acc, size_t(n) * nc * 8, hipMemcpyDeviceToDevice, st);
+}
+
+// One SSP-RK3 step backwards from U, its stages recomputed one at a time.
+void step_vjp(idp_ctx *c, const double *U, double dt, const double *Ubn, double *Ub, int clear)
+{
+    stage(c, U, U, c->U1, 1, 2, dt, 1, clear);           // U1
+    stage(c, c->U1, U, c->U2, 2, 2, dt, 0, 0);           // U2
+    const double *Us[3] = {U, c->U1, c->U2};
+    const idp::StageArgs P = rec_args(c);
+    step_vjp_core(c, dt, Ubn, Ub, [&](int k) -> const idp::StageArgs & {
+        stage_p(c, P, Us[k], Us[k], c->Estage, 0, 2, dt, 1, 0);
+        return P;
+    });
+}
+
+// One step backwards on the intermediates of tape step `slot`.
+void step_vjp_tape(idp_ctx *c, int slot, double dt, const double *Ubn, double *Ub)
+{
+    const idp::StageArgs *T = c->tape.data() + 3 * slot;
+    step_vjp_core(c, dt, Ubn, Ub, [&](int k) -> const idp::StageArgs & { return T[k]; });
 }
 
 int finish(idp_ctx *c)
@@ -832,7 +964,8 @@ int idp_euler_stage_vjp(idp_ctx *c, const double *U, double tau, const double *E
         return IDP_EINVAL;
     int rc = adj_check(c);
     if (rc != IDP_OK) return rc;
-    stage_vjp(c, U, tau, Ebar, Ubar, 1);
+    idp::launch_adj_pad(c->stream, c->n, c->prm.dim + 2, Ebar, c->Ebp);
+    stage_vjp(c, U, tau, c->Ebp, Ubar, 1);
     return finish(c);
 }
 
@@ -856,19 +989,11 @@ int idp_debug_adjoint(idp_ctx *c, int what, double *out)
     case IDP_ADJ_R: return node_to_host(c, c->A.Rt, nc, 0, nc, out);
     case IDP_ADJ_BOUNDS: return node_to_host(c, c->A.bndt, 3, 0, 3, out);
     case IDP_ADJ_ALPHA: return node_to_host(c, c->A.alt, 1, 0, 1, out);
-    case IDP_ADJ_P: {
-        std::vector<double> all(size_t(c->sell_size) * nc);
-        if (hipMemcpy(all.data(), c->A.Pb, all.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
-            return IDP_EHIP;
-        for (int64_t q = 0; q < c->nnz; ++q)
-            for (int r = 0; r < nc; ++r) out[q * nc + r] = all[c->sell_of_csr[q] * nc + r];
-        return IDP_OK;
-    }
     case IDP_ADJ_D: {
         const int64_t np = c->P.npairs;
         std::vector<double> dp(np);
         std::vector<int32_t> pe(np);
-        if (hipMemcpy(dp.data(), c->A.dbp, np * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        if (hipMemcpy(dp.data(), c->A.dLb, np * 8, hipMemcpyDeviceToHost) != hipSuccess ||
             hipMemcpy(pe.data(), c->P.pair_e, np * 4, hipMemcpyDeviceToHost) != hipSuccess)
             return IDP_EHIP;
         // CSR position of each pair's (i, j) entry, value at (i,j); 0 elsewhere
@@ -896,20 +1021,30 @@ int idp_forward_checkpoints(idp_ctx *c, double *U, int n_steps, const double *dt
         if ((rc = dalloc(c, &c->ckpt, slots * state)) != IDP_OK) return rc;
         c->ckpt_slots = slots;
     }
+    if ((rc = tape_reserve(c, every)) != IDP_OK) return rc;
     c->ck_steps = -1;
+    c->tape_last = false;
+    // the last segment runs on the tape, which the backward then starts from
+    const int last0 = ((n_steps - 1) / every) * every;
+    const bool keep = c->tape_steps >= n_steps - last0;
     for (int s = 0; s < n_steps; ++s) {
         if (s % every == 0)
             (void)hipMemcpyAsync(c->ckpt + (s / every) * state, U, state * 8,
                                  hipMemcpyDeviceToDevice, c->stream);
-        stage(c, U, U, c->U1, 1, 1, dt[s], 1, s == 0 ? 1 : 0);
-        stage(c, c->U1, U, c->U1, 2, 0, 0.0, 0, 0);
-        stage(c, c->U1, U, U, 3, 0, 0.0, 0, 0);
+        if (keep && s >= last0) {
+            tape_step(c, s - last0, U, dt[s], s == 0 ? 1 : 0);
+        } else {
+            stage(c, U, U, c->U1, 1, 1, dt[s], 1, s == 0 ? 1 : 0);
+            stage(c, c->U1, U, c->U1, 2, 0, 0.0, 0, 0);
+            stage(c, c->U1, U, U, 3, 0, 0.0, 0, 0);
+        }
     }
     rc = finish(c);
     if (rc >= 0) {
         c->ck_steps = n_steps;
         c->ck_every = every;
         c->ck_dt.assign(dt, dt + n_steps);
+        c->tape_last = keep;
     }
     return rc;
 }
@@ -925,12 +1060,36 @@ int idp_adjoint_checkpoints(idp_ctx *c, int n_steps, const double *dt, int every
     const size_t state = size_t(c->n) * nc;
     const int nck = (n_steps + every - 1) / every;
     double *seg = c->ckpt + int64_t(nck) * state;      // `every` states of one segment
+    const int T = c->tape_steps;
     // the running cotangent alternates between Ubar0 and bar[0]
     double *cur = c->bar[0], *nxt = Ubar0;
     (void)hipMemcpyAsync(cur, Ubar_final, state * 8, hipMemcpyDeviceToDevice, c->stream);
     int first = 1;
+    auto back = [&](auto &&one) {
+        one(cur, nxt);
+        first = 0;
+        double *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    };
     for (int k = nck - 1; k >= 0; --k) {
         const int s0 = k * every, s1 = s0 + every < n_steps ? s0 + every : n_steps;
+        if (T >= s1 - s0) {
+            // the whole segment on the tape (already there for the forward's last)
+            if (!(k == nck - 1 && c->tape_last)) {
+                (void)hipMemcpyAsync(seg, c->ckpt + int64_t(k) * state, state * 8,
+                                     hipMemcpyDeviceToDevice, c->stream);
+                for (int s = s0; s < s1; ++s) {
+                    tape_step(c, s - s0, seg, dt[s], first);
+                    first = 0;
+                }
+            }
+            for (int s = s1 - 1; s >= s0; --s)
+                back([&](double *in, double *out) { step_vjp_tape(c, s - s0, dt[s], in, out); });
+            continue;
+        }
+        // the segment's states, then (with a tape) blocks of T steps recomputed
+        // from their first state onto the tape, else one step at a time
         (void)hipMemcpyAsync(seg, c->ckpt + int64_t(k) * state, state * 8,
                              hipMemcpyDeviceToDevice, c->stream);
         for (int s = s0; s + 1 < s1; ++s) {
@@ -941,14 +1100,29 @@ int idp_adjoint_checkpoints(idp_ctx *c, int n_steps, const double *dt, int every
             stage(c, c->U1, to, to, 3, 0, 0.0, 0, 0);
             first = 0;
         }
-        for (int s = s1 - 1; s >= s0; --s) {
-            step_vjp(c, seg + int64_t(s - s0) * state, dt[s], cur, nxt, first);
-            first = 0;
-            double *tmp = cur;
-            cur = nxt;
-            nxt = tmp;
+        if (T > 0) {
+            for (int b1 = s1; b1 > s0;) {
+                const int b0 = b1 - T > s0 ? b1 - T : s0;
+                (void)hipMemcpyAsync(c->U2, seg + int64_t(b0 - s0) * state, state * 8,
+                                     hipMemcpyDeviceToDevice, c->stream);
+                for (int s = b0; s < b1; ++s) {
+                    tape_step(c, s - b0, c->U2, dt[s], first);
+                    first = 0;
+                }
+                for (int s = b1 - 1; s >= b0; --s)
+                    back([&](double *in, double *out) {
+                        step_vjp_tape(c, s - b0, dt[s], in, out);
+                    });
+                b1 = b0;
+            }
+        } else {
+            for (int s = s1 - 1; s >= s0; --s)
+                back([&](double *in, double *out) {
+                    step_vjp(c, seg + int64_t(s - s0) * state, dt[s], in, out, first);
+                });
         }
     }
+    c->tape_last = false;
     if (cur != Ubar0)
         (void)hipMemcpyAsync(Ubar0, cur, state * 8, hipMemcpyDeviceToDevice, c->stream);
     return finish(c);

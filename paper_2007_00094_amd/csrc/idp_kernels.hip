@@ -388,6 +388,7 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
 #pragma unroll
     for (int r = 0; r < NC; ++r) { R[r] = 0.0; Lw[r] = 0.0; }
     double rho_min = Ai.U[0], rho_max = Ai.U[0], phi_min = Ai.phi;
+    int kmn = 255, kmx = 255, kph = 255;
     int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
     for (int k = 0; k < Lmax_; ++k) {
         const int64_t e = ENTRY(k);
@@ -412,11 +413,12 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
         }
         double rbar = 0.5 * (Ai.U[0] + Aj.U[0]);
         if (dL > 0.0) rbar -= fd[0] / (2.0 * dL);
-        if (rbar < rho_min) rho_min = rbar;
-        if (rbar > rho_max) rho_max = rbar;
-        if (Aj.phi < phi_min) phi_min = Aj.phi;
+        if (rbar < rho_min) { rho_min = rbar; kmn = k; }
+        if (rbar > rho_max) { rho_max = rbar; kmx = k; }
+        if (Aj.phi < phi_min) { phi_min = Aj.phi; kph = k; }
     }
     if (!valid_) return;
+    if (P.argk) P.argk[i] = kmn | (kmx << 8) | (kph << 16);
     const double mi = P.mi[i];
     double *B = P.packB + int64_t(i) * kPack;
     double *W = P.rowB + int64_t(i) * kRowB;
@@ -469,6 +471,7 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
     P.l1[e] = sv;
     P.l1[t] = sv;
     P.l1p[p_] = sv;
+    if (P.side1) P.side1[p_] = lij < lji;
 }
 
 // -------------------------------------------------------- row pass 1
@@ -551,6 +554,7 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
     const double sv = lij < lji ? lij : lji;
     P.l2[e] = sv;
     P.l2[t] = sv;
+    if (P.side2) P.side2[p_] = lij < lji;
 }
 
 // -------------------------------------------------------- row pass 2
@@ -625,13 +629,6 @@ __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, in
 }
 
 // ------------------------------------------------- one launch per sweep
-// Row sweeps: wavefront w of logical block b takes slice 4 b + w.
-#define ROW_SLICE(P) (logical_block(P.per) * (kBlock / kSlice) + threadIdx.x / kSlice)
-#define PAIR_INDEX(P) (logical_block(P.pper) * kBlock + threadIdx.x)
-#define WAVE_LDS(NCH)                                                        \
-    __shared__ double2 lds_[kBlock / kSlice][(NCH) * kLdsRow];               \
-    double2 *const lw = lds_[threadIdx.x / kSlice];
-
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_node(StageArgs P, const double *__restrict__ U,
                                                  int check)

@@ -100,6 +100,79 @@ __device__ __forceinline__ void gather(const double *__restrict__ base, int stri
     __builtin_amdgcn_wave_barrier();
 }
 
+// Variant of gather() whose last chunk is chunk LAST of the record (the
+// first NCH - 1 are chunks 0 .. NCH - 2): a record prefix plus one far slot.
+template <int NCH, int LAST>
+__device__ __forceinline__ void gather_tail(const double *__restrict__ base, int stride, int node,
+                                            double2 *lds, double *out)
+{
+    static_assert(NCH >= 2 && NCH <= 8 && LAST >= NCH - 1, "prefix plus one chunk");
+    constexpr int LPR = NCH > 4 ? 8 : (NCH > 2 ? 4 : 2);
+    constexpr int RPI = kSlice / LPR;
+    const int lane = threadIdx.x % kSlice;
+    const int c = lane % LPR;
+    const int cc = c < NCH ? c : NCH - 1;
+    const int src = cc == NCH - 1 ? LAST : cc;
+    int nd[LPR];
+#pragma unroll
+    for (int it = 0; it < LPR; ++it) {
+        const int v = __shfl(node, it * RPI + lane / LPR);
+        nd[it] = v < 0 ? 0 : v;
+    }
+    double2 val[LPR];
+#pragma unroll
+    for (int it = 0; it < LPR; ++it)
+        val[it] = *reinterpret_cast<const double2 *>(base + int64_t(nd[it]) * stride + 2 * src);
+#pragma unroll
+    for (int it = 0; it < LPR; ++it) lds[cc * kLdsRow + it * RPI + lane / LPR] = val[it];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+        const double2 v = lds[k * kLdsRow + lane];
+        out[2 * k] = v.x;
+        out[2 * k + 1] = v.y;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The store counterpart of gather(): lane l's record `in` (NCH chunks) goes
+// to base + node_l * stride (node < 0: nothing stored).  The records pass
+// through the per-wavefront LDS tile so that each store instruction writes
+// 64 / LPR whole records (one line each) instead of one chunk of 64 lines.
+// Every lane of the wavefront must call it.
+template <int NCH>
+__device__ __forceinline__ void scatter(double *__restrict__ base, int stride, int node,
+                                        double2 *lds, const double *in)
+{
+    static_assert(NCH >= 1 && NCH <= 8, "record of 1 to 8 chunks");
+    constexpr int LPR = NCH > 4 ? 8 : (NCH > 2 ? 4 : (NCH > 1 ? 2 : 1));
+    constexpr int RPI = kSlice / LPR;
+    const int lane = threadIdx.x % kSlice;
+    const int c = lane % LPR;
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) lds[k * kLdsRow + lane] = make_double2(in[2 * k], in[2 * k + 1]);
+    __builtin_amdgcn_wave_barrier();
+    int nd[LPR];
+#pragma unroll
+    for (int it = 0; it < LPR; ++it) nd[it] = __shfl(node, it * RPI + lane / LPR);
+    if (c < NCH) {
+#pragma unroll
+        for (int it = 0; it < LPR; ++it)
+            if (nd[it] >= 0)
+                *reinterpret_cast<double2 *>(base + int64_t(nd[it]) * stride + 2 * c) =
+                    lds[c * kLdsRow + it * RPI + lane / LPR];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Launch shapes of the wavefront sweeps: row sweeps take slice 4 b + w in
+// wavefront w of logical block b; pair sweeps one pair per lane.
+#define ROW_SLICE(P) (logical_block(P.per) * (kBlock / kSlice) + threadIdx.x / kSlice)
+#define PAIR_INDEX(P) (logical_block(P.pper) * kBlock + threadIdx.x)
+#define WAVE_LDS(NCH)                                                        \
+    __shared__ double2 lds_[kBlock / kSlice][(NCH) * kLdsRow];               \
+    double2 *const lw = lds_[threadIdx.x / kSlice];
+
 // Row sweeps: one wavefront per slice s (below send); every lane stays to
 // the end of the slice's longest row; lanes past the node count take node
 // 0 and write nothing.  inst_ is the slice's instance.
