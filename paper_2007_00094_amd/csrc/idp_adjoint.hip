@@ -216,30 +216,54 @@ __device__ __forceinline__ void lambda_vjp(const double *n, const double *Ui, do
 }
 
 // ---------------------------------------------------------- limiter VJP
-// Psi(t) and Psi'(t) backwards: adds to Ub, Pb, tb, phib.
+// Psi(t) = rho eps(V) - phi_min rho^(g+1) on V = U + t P and Psi'(t), with
+// the point kept for the backward (the forward's arithmetic, in its order).
 template <int D>
-__device__ __forceinline__ void psi_vjp(const double *U, const double *P, double t,
+struct PsiPt {
+    double V[D + 2];
+    double rg1, psi, dpsi;
+};
+
+template <int D>
+__device__ __forceinline__ void psi_eval(const double *U, const double *P, double t,
+                                         double phimin, double g, PsiPt<D> &o)
+{
+#pragma unroll
+    for (int k = 0; k < D + 2; ++k) o.V[k] = U[k] + t * P[k];
+    const double rho = o.V[0], E = o.V[D + 1];
+    double m2 = 0.0, mP = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        m2 += o.V[1 + k] * o.V[1 + k];
+        mP += o.V[1 + k] * P[1 + k];
+    }
+    const double rho_eps = rho * E - 0.5 * m2;
+    o.rg1 = fpow(rho, g + 1.0);
+    o.psi = rho_eps - phimin * o.rg1;
+    o.dpsi = P[0] * E + rho * P[D + 1] - mP - phimin * (g + 1.0) * (o.rg1 / rho) * P[0];
+}
+
+// Psi(t) and Psi'(t) backwards at a kept point: adds to Ub, Pb, tb, phib.
+template <int D>
+__device__ __forceinline__ void psi_adj(const PsiPt<D> &o, const double *P, double t,
                                         double phimin, double g, double psib, double dpsib,
                                         double *Ub, double *Pb, double &tb, double &phib)
 {
     constexpr int NC = D + 2;
-    double V[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) V[k] = U[k] + t * P[k];
-    const double rho = V[0], E = V[D + 1];
-    const double rg1 = fpow(rho, g + 1.0);
+    const double rho = o.V[0], E = o.V[D + 1];
+    const double rg1 = o.rg1;
     const double q = rg1 / rho;                      // rho^g
     double Vb[NC];
     Vb[0] = psib * (E - phimin * (g + 1.0) * q) +
             dpsib * (P[D + 1] - phimin * (g + 1.0) * P[0] * g * q / rho);
     Vb[D + 1] = psib * rho + dpsib * P[0];
 #pragma unroll
-    for (int k = 0; k < D; ++k) Vb[1 + k] = -psib * V[1 + k] - dpsib * P[1 + k];
+    for (int k = 0; k < D; ++k) Vb[1 + k] = -psib * o.V[1 + k] - dpsib * P[1 + k];
     phib += -psib * rg1 - dpsib * (g + 1.0) * q * P[0];
     Pb[0] += dpsib * (E - phimin * (g + 1.0) * q);
     Pb[D + 1] += dpsib * rho;
 #pragma unroll
-    for (int k = 0; k < D; ++k) Pb[1 + k] -= dpsib * V[1 + k];
+    for (int k = 0; k < D; ++k) Pb[1 + k] -= dpsib * o.V[1 + k];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         Ub[k] += Vb[k];
@@ -360,9 +384,8 @@ __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, do
     if (c1) tR = 1.0;
     const bool c0 = tR < 0.0;
     if (c0) tR = 0.0;
-    // Newton iterations, recorded
+    // Newton iterations: the brackets recorded, Psi recomputed backwards
     double tLs[kAdjNewtonMax + 1], tRs[kAdjNewtonMax + 1];
-    double pL[kAdjNewtonMax], pR[kAdjNewtonMax], dL[kAdjNewtonMax], dR[kAdjNewtonMax];
     double tL = 0.0;
     int steps = 0, brk = 0;   // brk: 0 none, 1 psiR >= 0 (t = tR), 2 psiL <= tol (t = tL)
     for (int it = 0; it < newton_max; ++it) {
@@ -374,24 +397,21 @@ __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, do
         double psiL, dpsiL;
         psi_line<D>(U, P, tL, phimin, g, psiL, dpsiL);
         if (psiL <= tol) { brk = 2; break; }
-        pL[it] = psiL;
-        pR[it] = psiR;
-        dL[it] = dpsiL;
-        dR[it] = dpsiR;
         quadratic_newton(tL, tR, psiL, psiR, dpsiL, dpsiR, rhoP);
         ++steps;
     }
-    tLs[steps] = tL;
-    tRs[steps] = tR;
     // backwards: cotangents of (tL, tR) at the start of iteration `steps`
     double tLb = 0.0, tRb = 0.0, phib = 0.0;
     if (brk == 1) tRb = tb; else tLb = tb;
     for (int it = steps - 1; it >= 0; --it) {
+        PsiPt<D> R, Lp;
+        psi_eval<D>(U, P, tRs[it], phimin, g, R);
+        psi_eval<D>(U, P, tLs[it], phimin, g, Lp);
         double ntLb = 0.0, ntRb = 0.0, psiLb = 0.0, psiRb = 0.0, dpsiLb = 0.0, dpsiRb = 0.0;
-        newton_vjp(tLs[it], tRs[it], pL[it], pR[it], dL[it], dR[it], rhoP, tLb, tRb, ntLb, ntRb,
+        newton_vjp(tLs[it], tRs[it], Lp.psi, R.psi, Lp.dpsi, R.dpsi, rhoP, tLb, tRb, ntLb, ntRb,
                    psiLb, psiRb, dpsiLb, dpsiRb);
-        psi_vjp<D>(U, P, tRs[it], phimin, g, psiRb, dpsiRb, Ub, Pb, ntRb, phib);
-        psi_vjp<D>(U, P, tLs[it], phimin, g, psiLb, dpsiLb, Ub, Pb, ntLb, phib);
+        psi_adj<D>(R, P, tRs[it], phimin, g, psiRb, dpsiRb, Ub, Pb, ntRb, phib);
+        psi_adj<D>(Lp, P, tLs[it], phimin, g, psiLb, dpsiLb, Ub, Pb, ntLb, phib);
         tLb = ntLb;
         tRb = ntRb;
     }
@@ -452,51 +472,48 @@ __global__ void __launch_bounds__(kBlock) k_adj_lim2(StageArgs P, AdjArgs A)
     WAVE_PAIR_SETUP(P, PAIR_INDEX(P), P.npairs)
     constexpr int NC = D + 2, NU = (NC + 1) / 2;
     using CH = Chunks<D>;
-    NodeB<D> Bi, Bj;
-    double rec[2 * CH::packB], Wi[2 * CH::rowB], Wj[2 * CH::rowB];
-    double Ui[2 * NU], Uj[2 * NU], Ei[2 * NU], Ej[2 * NU];
-    gather<CH::packB>(P.packB, kPack, i, lw, rec);
-    unpack_b<D, true>(rec, Bi);
-    gather<CH::packB>(P.packB, kPack, j, lw, rec);
-    unpack_b<D, true>(rec, Bj);
-    gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
-    gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
-    gather<NU>(P.upass, kRowU, i, lw, Ui);
-    gather<NU>(P.upass, kRowU, j, lw, Uj);
-    gather<NU>(A.Ebp, kEbS, i, lw, Ei);
-    gather<NU>(A.Ebp, kEbS, j, lw, Ej);
     const double dL = P.dp[pq_], m = P.mp[pq_], s1 = P.l1p[pq_];
     const bool iside = P.side2[pq_] != 0;
     double Pij[NC], Pji[NC];
-    direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
-    direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
-    double EPi = 0.0, EPj = 0.0;
-#pragma unroll
-    for (int r = 0; r < NC; ++r) {
-        EPi += Ei[r] * Pij[r];
-        EPj += Ej[r] * Pji[r];
+    {
+        NodeB<D> Bi, Bj;
+        double rec[2 * CH::packB];
+        gather<CH::packB>(P.packB, kPack, i, lw, rec);
+        unpack_b<D, true>(rec, Bi);
+        gather<CH::packB>(P.packB, kPack, j, lw, rec);
+        unpack_b<D, true>(rec, Bj);
+        direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
+        direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
     }
-    const double sb = (1.0 - s1) * (P.lam[i] * EPi + P.lam[j] * EPj);
+    double sb;
+    {
+        double Ei[2 * NU], Ej[2 * NU];
+        gather<NU>(A.Ebp, kEbS, i, lw, Ei);
+        gather<NU>(A.Ebp, kEbS, j, lw, Ej);
+        double EPi = 0.0, EPj = 0.0;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            EPi += Ei[r] * Pij[r];
+            EPj += Ej[r] * Pji[r];
+        }
+        sb = (1.0 - s1) * (P.lam[i] * EPi + P.lam[j] * EPj);
+    }
+    // the candidate that set s2: row a's pass-1 state, bounds, direction
+    const int a_ = iside ? i : j;
+    double Wa[2 * CH::rowB], Ua[2 * NU], Qa[NC];
+    gather<CH::rowB>(P.rowB, kRowB, a_, lw, Wa);
+    gather<NU>(P.upass, kRowU, a_, lw, Ua);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) Qa[r] = (1.0 - s1) * (iside ? Pij[r] : Pji[r]);
     double Ub[NC], Qb[NC], bb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < NC; ++r) { Ub[r] = 0.0; Qb[r] = 0.0; }
-    if (valid_ && sb != 0.0) {
-        const double *Ua = iside ? Ui : Uj;
-        const double *Wa = iside ? Wi : Wj;
-        double Qa[NC], Uc[NC];
-#pragma unroll
-        for (int r = 0; r < NC; ++r) {
-            Qa[r] = (1.0 - s1) * (iside ? Pij[r] : Pji[r]);
-            Uc[r] = Ua[r];
-        }
-        limiter_vjp<D>(Uc, Qa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
+    if (valid_ && sb != 0.0)
+        limiter_vjp<D>(Ua, Qa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
                        Ub, Qb, bb);
-    }
     double ra[kC2S], rz[kC2S], rq[kQS];
 #pragma unroll
-    for (int r = 0; r < kC2S; ++r) rz[r] = 0.0;
-#pragma unroll
-    for (int r = 0; r < kC2S; ++r) ra[r] = 0.0;
+    for (int r = 0; r < kC2S; ++r) { rz[r] = 0.0; ra[r] = 0.0; }
 #pragma unroll
     for (int r = 0; r < NC; ++r) ra[r] = Ub[r];
 #pragma unroll
@@ -550,76 +567,84 @@ __global__ void __launch_bounds__(kBlock) k_adj_pass1(StageArgs P, AdjArgs A)
 // Pb_ij: R_i gains b_ji Z, U_i gains (d^H - d^L) Z, R_j and U_j the same
 // with -Z and b_ij; alpha_i and alpha_j each gain -Z.(U_j - U_i) d^L/2.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_adj_lim1(StageArgs P, AdjArgs A)
+__global__ void __launch_bounds__(kBlock, 2) k_adj_lim1(StageArgs P, AdjArgs A)
 {
     WAVE_LDS(kC1S / 2)
     WAVE_PAIR_SETUP(P, PAIR_INDEX(P), P.npairs)
     constexpr int NC = D + 2, NU = (NC + 1) / 2;
     using CH = Chunks<D>;
-    NodeB<D> Bi, Bj;
-    double rec[2 * CH::packB], Wi[2 * CH::rowB], Wj[2 * CH::rowB];
-    double Ei[2 * NU], Ej[2 * NU], Vi[2 * NU], Vj[2 * NU], Qr[kQS];
-    gather<CH::packB>(P.packB, kPack, i, lw, rec);
-    unpack_b<D, true>(rec, Bi);
-    gather<CH::packB>(P.packB, kPack, j, lw, rec);
-    unpack_b<D, true>(rec, Bj);
-    gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
-    gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
-    gather<NU>(A.Ebp, kEbS, i, lw, Ei);
-    gather<NU>(A.Ebp, kEbS, j, lw, Ej);
-    gather<NU>(A.Upb, kUpS, i, lw, Vi);
-    gather<NU>(A.Upb, kUpS, j, lw, Vj);
     const bool two = P.passes >= 2;
-    if (two) {
-        gather<kQS / 2>(A.Qb, kQS, valid_ ? int(p_) : -1, lw, Qr);
-    } else {
-#pragma unroll
-        for (int r = 0; r < kQS; ++r) Qr[r] = 0.0;
-    }
     const double dL = P.dp[pq_], m = P.mp[pq_], s1 = P.l1p[pq_];
     const double s2 = two ? P.l2[e] : 0.0;
     const bool side1 = P.side1[pq_] != 0;
     const bool side2 = two ? P.side2[pq_] != 0 : true;
     const double li = P.lam[i], lj = P.lam[j];
-    double Pij[NC], Pji[NC];
-    direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
-    direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
-    double EPi = 0.0, EPj = 0.0, VPi = 0.0, VPj = 0.0, QP = 0.0;
-    double Pbi[NC], Pbj[NC];
+    double Pij[NC], Pji[NC], dU[NC], ci, cj, asum;
+    {
+        NodeB<D> Bi, Bj;
+        double rec[2 * CH::packB];
+        gather<CH::packB>(P.packB, kPack, i, lw, rec);
+        unpack_b<D, true>(rec, Bi);
+        gather<CH::packB>(P.packB, kPack, j, lw, rec);
+        unpack_b<D, true>(rec, Bj);
+        direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
+        direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
 #pragma unroll
-    for (int r = 0; r < NC; ++r) {
-        EPi += Ei[r] * Pij[r];
-        EPj += Ej[r] * Pji[r];
-        VPi += Vi[r] * Pij[r];
-        VPj += Vj[r] * Pji[r];
-        QP += Qr[r] * (side2 ? Pij[r] : Pji[r]);
-        const double q = (1.0 - s1) * Qr[r];
-        Pbi[r] = li * s2 * (1.0 - s1) * Ei[r] + li * s1 * Vi[r] + (side2 ? q : 0.0);
-        Pbj[r] = lj * s2 * (1.0 - s1) * Ej[r] + lj * s1 * Vj[r] + (side2 ? 0.0 : q);
+        for (int r = 0; r < NC; ++r) dU[r] = Bj.U[r] - Bi.U[r];
+        ci = Bi.coef;
+        cj = Bj.coef;
+        asum = Bi.alpha + Bj.alpha;
     }
-    const double sb = -s2 * (li * EPi + lj * EPj) - QP + li * VPi + lj * VPj;
+    // P's cotangents and s1's from pass 2, the pass-2 limiter and pass 1;
+    // Z without the pass-1 limiter's share
+    double Z[NC], sb;
+    {
+        double Ei[2 * NU], Ej[2 * NU], Vi[2 * NU], Vj[2 * NU], Qr[kQS];
+        gather<NU>(A.Ebp, kEbS, i, lw, Ei);
+        gather<NU>(A.Ebp, kEbS, j, lw, Ej);
+        gather<NU>(A.Upb, kUpS, i, lw, Vi);
+        gather<NU>(A.Upb, kUpS, j, lw, Vj);
+        if (two) {
+            gather<kQS / 2>(A.Qb, kQS, valid_ ? int(p_) : -1, lw, Qr);
+        } else {
+#pragma unroll
+            for (int r = 0; r < kQS; ++r) Qr[r] = 0.0;
+        }
+        double EPi = 0.0, EPj = 0.0, VPi = 0.0, VPj = 0.0, QP = 0.0;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            EPi += Ei[r] * Pij[r];
+            EPj += Ej[r] * Pji[r];
+            VPi += Vi[r] * Pij[r];
+            VPj += Vj[r] * Pji[r];
+            QP += Qr[r] * (side2 ? Pij[r] : Pji[r]);
+            const double q = (1.0 - s1) * Qr[r];
+            const double Pbi = li * s2 * (1.0 - s1) * Ei[r] + li * s1 * Vi[r] + (side2 ? q : 0.0);
+            const double Pbj = lj * s2 * (1.0 - s1) * Ej[r] + lj * s1 * Vj[r] + (side2 ? 0.0 : q);
+            Z[r] = cj * Pbj - ci * Pbi;
+        }
+        sb = -s2 * (li * EPi + lj * EPj) - QP + li * VPi + lj * VPj;
+    }
+    // the candidate that set s1: row a's U^L, bounds, direction
+    const int a_ = side1 ? i : j;
+    double Wa[2 * CH::rowB], Pa[NC];
+    gather<CH::rowB>(P.rowB, kRowB, a_, lw, Wa);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) Pa[r] = side1 ? Pij[r] : Pji[r];
     double ULb[NC], Pab[NC], bb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < NC; ++r) { ULb[r] = 0.0; Pab[r] = 0.0; }
-    if (valid_ && sb != 0.0) {
-        const double *Wa = side1 ? Wi : Wj;
-        double Pa[NC], Uc[NC];
-#pragma unroll
-        for (int r = 0; r < NC; ++r) {
-            Pa[r] = side1 ? Pij[r] : Pji[r];
-            Uc[r] = Wa[r];
-        }
-        limiter_vjp<D>(Uc, Pa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
+    if (valid_ && sb != 0.0)
+        limiter_vjp<D>(Wa, Pa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
                        ULb, Pab, bb);
-    }
-    double Z[NC], kb = 0.0;
+    const double ca = side1 ? -ci : cj;
+    double kb = 0.0;
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
-        if (side1) Pbi[r] += Pab[r]; else Pbj[r] += Pab[r];
-        Z[r] = Bj.coef * Pbj[r] - Bi.coef * Pbi[r];
-        kb -= Z[r] * (Bj.U[r] - Bi.U[r]);
+        Z[r] += ca * Pab[r];
+        kb -= Z[r] * dU[r];
     }
-    const double dH = dL * (Bi.alpha + Bj.alpha) / 2.0;
+    const double dH = dL * asum / 2.0;
     double re[kC1S], rt[kC1S];
 #pragma unroll
     for (int r = 0; r < kC1S; ++r) { re[r] = 0.0; rt[r] = 0.0; }
@@ -634,7 +659,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_lim1(StageArgs P, AdjArgs A)
     re[14] = rt[14] = dH - dL;
     scatter<kC1S / 2>(A.C, kC1S, valid_ ? int(e) : -1, lw, re);
     scatter<kC1S / 2>(A.C, kC1S, valid_ ? int(t) : -1, lw, rt);
-    if (valid_) A.dLb[p_] = kb * ((Bi.alpha + Bj.alpha) / 2.0 - 1.0);
+    if (valid_) A.dLb[p_] = kb * (asum / 2.0 - 1.0);
 }
 
 // low-order update, bar states and bounds backwards (row).  The row's
