@@ -669,7 +669,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_adj_lim1(StageArgs P, AdjArgs A)
 // share of row i (db4, per entry), alpha_i's own share.  The neighbours'
 // shares are pulled by the neighbours from the node record.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_adj_low(StageArgs P, AdjArgs A)
+__global__ void __launch_bounds__(kBlock, 3) k_adj_low(StageArgs P, AdjArgs A)
 {
     WAVE_LDS(kC1S / 2)
     WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
@@ -952,8 +952,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_alpha(StageArgs P, AdjArgs A)
 }
 
 // graph viscosity backwards (pair): d_ij's total cotangent (the
-// directions', rows i's and j's low order) through the active orientation
-// of the max to both states.
+// directions', rows i's and j's low order) through the orientation that
+// set the max (recorded by the forward) to both states.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_dpair(StageArgs P, AdjArgs A)
 {
@@ -969,44 +969,35 @@ __global__ void __launch_bounds__(kBlock) k_adj_dpair(StageArgs P, AdjArgs A)
 #pragma unroll
     for (int r = 0; r < kC5S; ++r) { Ubi[r] = 0.0; Ubj[r] = 0.0; }
     if (valid_ && db != 0.0) {
-        double c[D], ct[D];
-        load_c<D>(P, e, c);
-        ct[0] = P.ct0[e];
-        ct[1] = P.ct1[e];
-        if (D == 3) ct[D - 1] = P.ct2[e];
-        double aij = 0.0, aji = 0.0;
+        // orientation i -> j: n_ij = c_ij/|c_ij|; j -> i: c_ji (stored at (i, j))
+        const bool fwd = P.sided[pq_] != 0;
+        double c[D];
+        if (fwd) {
+            load_c<D>(P, e, c);
+        } else {
+            c[0] = P.ct0[e];
+            c[1] = P.ct1[e];
+            if (D == 3) c[D - 1] = P.ct2[e];
+        }
+        double a = 0.0;
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-            aij += c[q] * c[q];
-            aji += ct[q] * ct[q];
-        }
-        aij = sqrt(aij);
-        aji = sqrt(aji);
-        const double pi = Ai[NC], ci_ = Ai[NC + 1], pj = Aj[NC], cj_ = Aj[NC + 1];
-        double nij[D], nji[D], t1 = 0.0, t2 = 0.0;
-        if (aij > 0.0) {
-            const double inv = 1.0 / aij;
+        for (int q = 0; q < D; ++q) a += c[q] * c[q];
+        a = sqrt(a);
+        if (a > 0.0) {
+            const double inv = 1.0 / a;
+            double nn[D];
 #pragma unroll
-            for (int q = 0; q < D; ++q) nij[q] = c[q] * inv;
-            t1 = lambda_max<D>(nij, Ai, pi, ci_, Aj, pj, cj_, P.gas) * aij;
+            for (int q = 0; q < D; ++q) nn[q] = c[q] * inv;
+            const double *Aa = fwd ? Ai : Aj, *Ab = fwd ? Aj : Ai;
+            NodeCot<D> ba, bb;
+            cot_zero<D>(ba);
+            cot_zero<D>(bb);
+            lambda_vjp<D>(nn, Aa, Aa[NC], Aa[NC + 1], Ab, Ab[NC], Ab[NC + 1], P.gas, db * a, ba,
+                          bb);
+            double *Ua = fwd ? Ubi : Ubj, *Uo = fwd ? Ubj : Ubi;
+            node_vjp<D>(Aa, Aa[NC], Aa[NC + 1], 0.0, 0.0, P.gamma, ba, false, Ua);
+            node_vjp<D>(Ab, Ab[NC], Ab[NC + 1], 0.0, 0.0, P.gamma, bb, false, Uo);
         }
-        if (aji > 0.0) {
-            const double inv = 1.0 / aji;
-#pragma unroll
-            for (int q = 0; q < D; ++q) nji[q] = ct[q] * inv;
-            t2 = lambda_max<D>(nji, Aj, pj, cj_, Ai, pi, ci_, P.gas) * aji;
-        }
-        NodeCot<D> bi, bj;
-        cot_zero<D>(bi);
-        cot_zero<D>(bj);
-        if (t1 > t2) {
-            if (aij > 0.0)
-                lambda_vjp<D>(nij, Ai, pi, ci_, Aj, pj, cj_, P.gas, db * aij, bi, bj);
-        } else if (aji > 0.0) {
-            lambda_vjp<D>(nji, Aj, pj, cj_, Ai, pi, ci_, P.gas, db * aji, bj, bi);
-        }
-        node_vjp<D>(Ai, pi, ci_, 0.0, 0.0, P.gamma, bi, false, Ubi);
-        node_vjp<D>(Aj, pj, cj_, 0.0, 0.0, P.gamma, bj, false, Ubj);
     }
     scatter<kC5S / 2>(A.C, kC5S, valid_ ? int(e) : -1, lw, Ubi);
     scatter<kC5S / 2>(A.C, kC5S, valid_ ? int(t) : -1, lw, Ubj);

@@ -84,7 +84,8 @@ struct idp_ctx {
     bool adj_ready = false;
     double *Estage = nullptr, *U2 = nullptr, *Ebp = nullptr, *acc = nullptr;
     double *bar[3] = {nullptr, nullptr, nullptr};
-    uint8_t *side1 = nullptr, *side2 = nullptr;   // records of a recomputed stage
+    uint8_t *sided = nullptr, *side1 = nullptr, *side2 = nullptr;   // records of a
+                                                                    // recomputed stage
     int32_t *argk = nullptr;
     double *ckpt = nullptr;          // [slots][n][nc]
     int64_t ckpt_slots = 0;
@@ -780,6 +781,7 @@ int adj_setup(idp_ctx *c)
     ADJ_ALLOC(c->U2, n * nc);
     ADJ_ALLOC(c->acc, n * nc);
     for (int k = 0; k < 3; ++k) ADJ_ALLOC(c->bar[k], n * nc);
+    ADJ_ALLOC(c->sided, np);
     ADJ_ALLOC(c->side1, np);
     ADJ_ALLOC(c->side2, np);
     ADJ_ALLOC(c->argk, n);
@@ -798,6 +800,7 @@ int adj_check(idp_ctx *c)
 idp::StageArgs rec_args(const idp_ctx *c)
 {
     idp::StageArgs P = c->P;
+    P.sided = c->sided;
     P.side1 = c->side1;
     P.side2 = c->side2;
     P.argk = c->argk;
@@ -812,7 +815,7 @@ size_t tape_slot_bytes(const idp_ctx *c)
     const size_t S = size_t(c->sell_size), np = size_t(c->P.npairs), n = size_t(c->n);
     return 3 * al256(S * 8) + 2 * al256(np * 8) + 2 * al256(n * idp::kPack * 8) +
            al256(n * idp::kRowB * 8) + al256(n * idp::kRowU * 8) + al256(n * 8) +
-           2 * al256(np) + al256(n * 4);
+           3 * al256(np) + al256(n * 4);
 }
 
 // Room for `steps` steps (fewer if device memory is short: the largest
@@ -864,6 +867,7 @@ int tape_reserve(idp_ctx *c, int steps)
         P.rowB = reinterpret_cast<double *>(take(n * idp::kRowB * 8));
         P.upass = reinterpret_cast<double *>(take(n * idp::kRowU * 8));
         P.alpha = reinterpret_cast<double *>(take(n * 8));
+        P.sided = reinterpret_cast<uint8_t *>(take(np));
         P.side1 = reinterpret_cast<uint8_t *>(take(np));
         P.side2 = reinterpret_cast<uint8_t *>(take(np));
         P.argk = reinterpret_cast<int32_t *>(take(n * 4));

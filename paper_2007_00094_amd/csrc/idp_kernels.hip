@@ -296,6 +296,7 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
     P.d[e] = dd;
     P.d[t] = dd;
     P.dp[p_] = dd;
+    if (P.sided) P.sided[p_] = t1 > t2;
 }
 
 // --------------------------------------------------------- row diagonal

@@ -53,11 +53,12 @@ struct StageArgs {
     double *d;                  // [sell] d_ij, diagonal d_ii
     double *l1, *l2;            // [sell] min(l_ij, l_ji) of pass 1, 2
     double *packA, *alpha, *packB, *rowB, *upass, *taui;
-    // records for the stage adjoint (null: not kept): which side of a pair
-    // set min(l_ij, l_ji) (1: the row of pair_i), per limiter pass; and per
-    // node the row positions k of the entries that set rho_min, rho_max and
-    // phi_min (bits 0-7, 8-15, 16-23; 255: the node itself)
-    uint8_t *side1, *side2;
+    // records for the stage adjoint (null: not kept): which orientation
+    // set d_ij = max(...) (1: i -> j), which side of a pair set min(l_ij,
+    // l_ji) (1: the row of pair_i) per limiter pass; and per node the row
+    // positions k of the entries that set rho_min, rho_max and phi_min
+    // (bits 0-7, 8-15, 16-23; 255: the node itself)
+    uint8_t *sided, *side1, *side2;
     int32_t *argk;
     // instances: a batch of independent meshes shares one context; their
     // slices, pairs and nodes are contiguous and never mixed
