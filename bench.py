@@ -147,6 +147,68 @@ def batched_bench(steps):
             "speedup_vs_loop": t_loop / t_batch}
 
 
+def adjoint_bench(steps, every):
+    """Checkpointed adjoint of the 65^3 smooth-blob run: forward with
+    checkpoints every `every` steps, then the backward (recomputation
+    included) of the gradient of the kinetic energy in [0.4, 0.6]^3 at the
+    final time; dt frozen from a base run.  One warm pair, one timed pair."""
+    import torch
+    from paper_2007_00094_amd import inputs
+    from paper_2007_00094_amd.solver import Solver
+    mesh, U0 = inputs.workload("adjoint_3d", n=65)
+    s = Solver(mesh)
+    U = torch.tensor(U0, device="cuda")
+    dts = []
+    for _ in range(steps):
+        dt, st = s.step(U)
+        assert st in (0, 1), f"base run failed: {st}"
+        dts.append(dt)
+    # cotangent of J = sum_{x_i in box} m_i |m_i|^2 / (2 rho_i) at the final state
+    box = torch.tensor(np.all((mesh.coords >= 0.4) & (mesh.coords <= 0.6), axis=1), device="cuda")
+    mi = torch.tensor(s.matrices()["m_i"], device="cuda")
+    Uf = U.clone().requires_grad_(True)
+    mom = Uf[:, 1:4]
+    J = (mi * box * (mom * mom).sum(1) / (2 * Uf[:, 0])).sum()
+    J.backward()
+    W = Uf.grad.detach().clone()
+    res = []
+    for _ in range(2):
+        U = torch.tensor(U0, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.forward_checkpoints(U, dts, every)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        g = s.adjoint_checkpoints(dts, every, W)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        res.append((tf, tb))
+    tf, tb = res[-1]
+    assert torch.isfinite(g).all()
+    # per-kernel split of one more backward
+    U = torch.tensor(U0, device="cuda")
+    s.forward_checkpoints(U, dts, every)
+    s.set_timing(True)
+    s.adjoint_checkpoints(dts, every, W)
+    torch.cuda.synchronize()
+    kt = s.kernel_times()
+    s.set_timing(False)
+    vjp_ms, vjp_n = kt["stage_vjp"]
+    fwd_ms = sum(ms for k, (ms, c) in kt.items() if k not in ("stage_vjp",))
+    fwd_stages = kt["pair_viscosity"][1]
+    s.close()
+    return {"workload": "adjoint_3d_65^3_morton: isothermal Gaussian density blobs (p = rho), "
+                        "at rest; gradient of the kinetic energy in [0.4, 0.6]^3 at the final "
+                        "time w.r.t. U0",
+            "nodes": mesh.n_nodes, "steps": steps, "checkpoint_every": every,
+            "forward_ms": tf * 1e3, "adjoint_ms": tb * 1e3,
+            "adjoint_over_forward": tb / tf,
+            "stage_vjp_ms": vjp_ms / vjp_n, "stage_vjps": vjp_n,
+            "recomputed_stages": fwd_stages, "recompute_ms": fwd_ms,
+            "forward_ms_per_step": tf / steps * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +219,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched measurement")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--cpu-radius", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--newton-max", type=int, default=2,
@@ -237,6 +301,12 @@ def main():
         batched = batched_bench(args.batch_steps)
         log(f"  batched {batched['batched_ms_per_step']:.2f} ms/step, loop "
             f"{batched['loop_ms_per_step']:.2f} ms/step, {batched['speedup_vs_loop']:.2f}x")
+    adjoint = None
+    if not args.no_adjoint:
+        log(f"adjoint: 65^3, {args.adjoint_steps} steps, checkpoints every 20")
+        adjoint = adjoint_bench(args.adjoint_steps, 20)
+        log(f"  forward {adjoint['forward_ms']:.1f} ms, adjoint {adjoint['adjoint_ms']:.1f} ms, "
+            f"ratio {adjoint['adjoint_over_forward']:.2f}, stage VJP {adjoint['stage_vjp_ms']:.3f} ms")
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a patch)")
@@ -262,6 +332,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "batched": batched,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
 
