@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched measurement")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    ap.add_argument("--no-staging", action="store_true",
+                    help="row sweeps gather from memory instead of staging in LDS")
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--cpu-radius", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=12)
@@ -252,7 +254,8 @@ def main():
     mesh, U0 = inputs.workload("mach3_3d", n=args.n, order=args.order)
     log(f"mesh {mesh.n_nodes} nodes, {mesh.n_cells} cells in {time.perf_counter() - t:.1f} s")
     t = time.perf_counter()
-    s = Solver(mesh, asynchronous=True, newton_max=args.newton_max)
+    s = Solver(mesh, asynchronous=True, newton_max=args.newton_max,
+               staging=not args.no_staging)
     torch.cuda.synchronize()
     log(f"solver created: nnz {s.nnz}, {s.device_bytes / 2**30:.1f} GiB device, "
         f"{time.perf_counter() - t:.1f} s")
@@ -325,7 +328,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"mach3_3d_{args.n}^3_{args.order}",
-                   "newton_max_iter": args.newton_max,
+                   "newton_max_iter": args.newton_max, "lds_staging": not args.no_staging,
                    "nodes": mesh.n_nodes, "nnz": s.nnz, "stages": stages,
                    "parallelism": "single GPU"},
         "roofline": roofline,

@@ -52,6 +52,10 @@ extern "C" {
 /* flags for idp_params.flags */
 #define IDP_FLAG_ASYNC 1        /* idp_step does not synchronise; errors are
                                    sticky and read with idp_get_status     */
+#define IDP_FLAG_NO_STAGING 2   /* row sweeps gather every neighbour record
+                                   from memory instead of staging each row
+                                   block's neighbourhood in LDS (same results,
+                                   bit for bit; for tests and measurement)  */
 
 /* Parameters of the scheme.  gamma: ratio of specific heats (Section 2);
  * cfl: c_cfl of Section 3.3 (0 < cfl <= 1); limiter_passes: 1 or 2

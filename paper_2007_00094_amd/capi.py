@@ -23,6 +23,7 @@ IDP_EDT = -6
 IDP_ENOTSUP = -7
 IDP_EWAIT = -8
 IDP_FLAG_ASYNC = 1
+IDP_FLAG_NO_STAGING = 2
 IDP_SCHED_LAUNCHES = 1
 IDP_SCHED_PERSISTENT = 2
 

@@ -291,6 +291,80 @@ static int concat(const std::vector<HostGraph> &parts, HostGraph &g, BatchLayout
     return IDP_OK;
 }
 
+int build_halos(const HostGraph &g, int64_t nblocks, int hmax, Halos &h)
+{
+    try {
+        const int64_t nb = (g.nslices + 3) / 4;
+        h.cnt.assign(size_t(nblocks), 0);
+        h.start.assign(size_t(nblocks), 0);
+        h.loc.assign(size_t(g.sell_size), 0);
+        std::vector<std::vector<int32_t>> lists(static_cast<size_t>(nb));
+        bool oom = false;
+#pragma omp parallel
+        {
+            std::vector<int32_t> stamp;
+            std::vector<uint16_t> pos;
+            try {
+                stamp.assign(size_t(g.n), -1);
+                pos.assign(size_t(g.n), 0);
+            } catch (const std::bad_alloc &) {
+#pragma omp atomic write
+                oom = true;
+            }
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t b = 0; b < nb; ++b) {
+                if (stamp.empty()) continue;
+                std::vector<int32_t> &L = lists[size_t(b)];
+                const int64_t s1 = std::min<int64_t>(4 * b + 4, g.nslices);
+                for (int64_t s = 4 * b; s < s1; ++s)
+                    for (int lane = 0; lane < kSellC; ++lane) {
+                        const int64_t r = s * kSellC + lane;
+                        if (g.perm[r] < 0) continue;
+                        for (int k = 0; k < g.row_len[r]; ++k) {
+                            const int32_t c = g.scol[g.slice_off[s] + int64_t(k) * kSellC + lane];
+                            if (stamp[c] != int32_t(b)) {
+                                stamp[c] = int32_t(b);
+                                L.push_back(c);
+                            }
+                        }
+                    }
+                if (int64_t(L.size()) > hmax) {
+                    h.cnt[size_t(b)] = -1;
+                    std::vector<int32_t>().swap(L);
+                    continue;
+                }
+                std::sort(L.begin(), L.end());
+                h.cnt[size_t(b)] = int32_t(L.size());
+                for (size_t q = 0; q < L.size(); ++q) pos[L[q]] = uint16_t(q);
+                for (int64_t s = 4 * b; s < s1; ++s)
+                    for (int lane = 0; lane < kSellC; ++lane) {
+                        const int64_t r = s * kSellC + lane;
+                        if (g.perm[r] < 0) continue;
+                        for (int k = 0; k < g.row_len[r]; ++k) {
+                            const int64_t e = g.slice_off[s] + int64_t(k) * kSellC + lane;
+                            h.loc[size_t(e)] = pos[g.scol[e]];
+                        }
+                    }
+            }
+        }
+        if (oom) return IDP_ENOMEM;
+        int64_t tot = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            h.start[size_t(b)] = tot;
+            tot += int64_t(lists[size_t(b)].size());
+        }
+        for (int64_t b = nb; b < nblocks; ++b) h.start[size_t(b)] = tot;
+        h.node.resize(size_t(tot));
+#pragma omp parallel for schedule(static)
+        for (int64_t b = 0; b < nb; ++b)
+            std::copy(lists[size_t(b)].begin(), lists[size_t(b)].end(),
+                      h.node.begin() + h.start[size_t(b)]);
+    } catch (const std::bad_alloc &) {
+        return IDP_ENOMEM;
+    }
+    return IDP_OK;
+}
+
 int concat_graphs(const std::vector<HostGraph> &parts, HostGraph &g, BatchLayout &lay)
 {
     if (parts.empty()) return IDP_EINVAL;

@@ -56,6 +56,22 @@ struct HostGraph {
 int build_graph(HostGraph &g, int dim, int64_t n, int64_t ncells,
                 const int64_t *cells);
 
+// Neighbourhoods of row blocks, for staging in LDS.  Block b holds the rows
+// of slices 4b .. 4b+3; its halo is the ascending set of the columns of
+// those rows.  cnt[b] = its size, or -1 if it exceeds hmax (the block then
+// gathers from memory); node[start[b] + q] is its q-th node and loc[e] the
+// halo position of entry e's column (entries of blocks with cnt < 0: 0).
+struct Halos {
+    std::vector<int64_t> start;   // [nblocks]
+    std::vector<int32_t> cnt;     // [nblocks]
+    std::vector<int32_t> node;
+    std::vector<uint16_t> loc;    // [sell_size]
+};
+
+// nblocks >= ceil(nslices / 4) (blocks past the last slice: empty).
+// Returns 0 or IDP_ENOMEM.
+int build_halos(const HostGraph &g, int64_t nblocks, int hmax, Halos &h);
+
 // Where each instance of a concatenated batch lives (k = 0..ninst, the
 // last entry is the total): nodes, cells, CSR entries, slices, SELL
 // entries, pairs.

@@ -448,6 +448,31 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
     HIPTRY(hipMemcpyAsync(pi, g.pair_i.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemcpyAsync(pj, g.pair_j.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemsetAsync(c->scal, 0, scal_bytes(K), c->stream));
+    // neighbourhoods of the row blocks for the LDS-staged row sweeps
+    if (!(p.flags & IDP_FLAG_NO_STAGING)) {
+        idp::Halos h;
+        const int64_t nblk = int64_t(P.per) * idp::kXcd;
+        TRY(idp::build_halos(g, nblk, idp::kHaloMax, h));
+        int64_t *hs;
+        int32_t *hc, *hn;
+        uint16_t *hl;
+        TRY(dalloc(c, &hs, nblk));
+        TRY(dalloc(c, &hc, nblk));
+        TRY(dalloc(c, &hn, int64_t(h.node.size())));
+        TRY(dalloc(c, &hl, S));
+        HIPTRY(hipMemcpyAsync(hs, h.start.data(), nblk * 8, hipMemcpyHostToDevice, c->stream));
+        HIPTRY(hipMemcpyAsync(hc, h.cnt.data(), nblk * 4, hipMemcpyHostToDevice, c->stream));
+        if (!h.node.empty())
+            HIPTRY(hipMemcpyAsync(hn, h.node.data(), h.node.size() * 4, hipMemcpyHostToDevice,
+                                  c->stream));
+        HIPTRY(hipMemcpyAsync(hl, h.loc.data(), S * 2, hipMemcpyHostToDevice, c->stream));
+        // the host vectors die at the end of this scope: wait for the copies
+        HIPTRY(hipStreamSynchronize(c->stream));
+        P.halo_start = hs;
+        P.halo_cnt = hc;
+        P.halo_node = hn;
+        P.loc = hl;
+    }
 
     // matrices on the device (temporary mesh arrays)
     {

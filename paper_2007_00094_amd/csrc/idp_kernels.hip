@@ -303,15 +303,15 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
 // Step 2: d_ii = -sum_{j != i} d_ij (columns ascending), tau_i, the
 // instance's min tau_i (into taumin[instance]); indicator alpha_i
 // (Section 3.8) over all j in I(i).
-template <int D>
+template <int D, class F>
 __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int64_t send,
                                            int with_alpha, unsigned long long *taumin,
-                                           double2 *lw)
+                                           const F &fetch)
 {
     WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
     constexpr int NC = D + 2;
-    constexpr int NCH = (NC + 4 + D) / 2;   // U, p, c, eta/rho, v, phi
+    constexpr int NCH = kDiagChunks<D>;
     const double g = P.gamma;
     NodeA<D> Ai;
     load_a<D>(P.packA + int64_t(i) * kPack, Ai);
@@ -333,7 +333,7 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
             double c[D];
             load_c<D>(P, e, c);
             double rec[2 * NCH];
-            gather<NCH>(P.packA, kPack, in ? j : -1, lw, rec);
+            fetch(fetch.token(e), in ? j : -1, rec);
             if (!in) continue;
             NodeA<D> Aj;
             unpack_a<D>(rec, Aj);
@@ -477,9 +477,9 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
 
 // -------------------------------------------------------- row pass 1
 // Step 5, first half: U_i = U^L_i + sum_{j != i} lambda_i s_ij P_ij.
-template <int D>
+template <int D, class F>
 __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, int64_t send,
-                                            double2 *lw)
+                                            const F &fetch)
 {
     WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
@@ -494,16 +494,32 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
     const double tau = P.tau[inst_];
     const double lam = P.lam[i];
     const double coef = tau / (lam * Bi.m);
-    int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+    // the next entry's column, scalars and fetch token are loaded one
+    // entry ahead
+    int jn = 0, tn = 0;
+    double ln = 0.0, dn = 0.0, mn = 0.0;
+    if (Lmax_ > 0) {
+        const int64_t e0 = ENTRY(0);
+        jn = P.scol[e0];
+        tn = fetch.token(e0);
+        ln = P.l1[e0];
+        dn = P.d[e0];
+        mn = P.mij[e0];
+    }
     for (int k = 0; k < Lmax_; ++k) {
-        const int64_t e = ENTRY(k);
-        const int j = jn;
-        if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
-        const double l = P.l1[e], dL = P.d[e], m = P.mij[e];
+        const int j = jn, tk = tn;
+        const double l = ln, dL = dn, m = mn;
+        if (k + 1 < Lmax_) {
+            const int64_t e1 = ENTRY(k + 1);
+            jn = P.scol[e1];
+            tn = fetch.token(e1);
+            ln = P.l1[e1];
+            dn = P.d[e1];
+            mn = P.mij[e1];
+        }
         const bool act = k < L && j != i;
-        if (k < L && j == i) P.l1[e] = 1.0;
         double rec[2 * CH::packBrow];
-        gather<CH::packBrow>(P.packB, kPack, act ? j : -1, lw, rec);
+        fetch(tk, act ? j : -1, rec);
         if (!act) continue;
         NodeB<D> Bj;
         unpack_b<D, false>(rec, Bj);
@@ -513,6 +529,7 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
         for (int r = 0; r < NC; ++r) V[r] += lam * l * Pd[r];
     }
     if (!valid_) return;
+    P.l1[ENTRY(P.diag_k[r_])] = 1.0;   // the diagonal's s1 (pass 2 reads it as 1)
     double *Up = P.upass + int64_t(i) * kRowU;
 #pragma unroll
     for (int r = 0; r < NC; ++r) Up[r] = V[r];
@@ -562,10 +579,10 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
 // Step 6: U_i += sum_{j != i} lambda_i s2_ij (1 - s1_ij) P_ij, then
 // mode 0: out = E(U); 1: out = E (stage 1); 2: out = U0 + 1/4 (E - U0);
 // 3: out = U0 + 2/3 (E - U0); modes 1-3 keep held nodes at U0.
-template <int D>
+template <int D, class F>
 __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, int64_t send,
                                             const double *U0, double *out, int mode,
-                                            double2 *lw)
+                                            const F &fetch)
 {
     WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
@@ -581,16 +598,32 @@ __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, in
         const double tau = P.tau[inst_];
         const double lam = P.lam[i];
         const double coef = tau / (lam * Bi.m);
-        int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+        int jn = 0, tn = 0;
+        double s1n = 0.0, s2n = 0.0, dn = 0.0, mn = 0.0;
+        if (Lmax_ > 0) {
+            const int64_t e0 = ENTRY(0);
+            jn = P.scol[e0];
+            tn = fetch.token(e0);
+            s1n = P.l1[e0];
+            s2n = P.l2[e0];
+            dn = P.d[e0];
+            mn = P.mij[e0];
+        }
         for (int k = 0; k < Lmax_; ++k) {
-            const int64_t e = ENTRY(k);
-            const int j = jn;
-            if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
-            const double s1 = P.l1[e], s2 = P.l2[e], dL = P.d[e], m = P.mij[e];
+            const int j = jn, tk = tn;
+            const double s1 = s1n, s2 = s2n, dL = dn, m = mn;
+            if (k + 1 < Lmax_) {
+                const int64_t e1 = ENTRY(k + 1);
+                jn = P.scol[e1];
+                tn = fetch.token(e1);
+                s1n = P.l1[e1];
+                s2n = P.l2[e1];
+                dn = P.d[e1];
+                mn = P.mij[e1];
+            }
             const bool act = k < L && j != i;
-            if (k < L && j == i) P.l2[e] = 1.0;
             double rec[2 * CH::packBrow];
-            gather<CH::packBrow>(P.packB, kPack, act ? j : -1, lw, rec);
+            fetch(tk, act ? j : -1, rec);
             if (!act) continue;
             NodeB<D> Bj;
             unpack_b<D, false>(rec, Bj);
@@ -604,6 +637,7 @@ __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, in
         }
     }
     if (!valid_) return;
+    if (P.passes >= 2) P.l2[ENTRY(P.diag_k[r_])] = 1.0;   // the diagonal's s2
     double *o = out + int64_t(i) * NC;
     if (mode == 0) {
 #pragma unroll
@@ -648,7 +682,8 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
 {
     WAVE_LDS((D + 6 + D) / 2)
-    diag_sweep<D>(P, ROW_SLICE(P), P.nslices, with_alpha, P.taumin, lw);
+    diag_sweep<D>(P, ROW_SLICE(P), P.nslices, with_alpha, P.taumin,
+                  GatherFetch<kDiagChunks<D>>{P.packA, lw});
 }
 
 template <int D>
@@ -668,7 +703,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_pass1a(StageArgs P)
 {
     WAVE_LDS(Chunks<D>::packBrow)
-    pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, lw);
+    pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
 }
 
 template <int D>
@@ -683,7 +718,39 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
                                                   int mode)
 {
     WAVE_LDS(Chunks<D>::packBrow)
-    pass2_sweep<D>(P, ROW_SLICE(P), P.nslices, U0, out, mode, lw);
+    pass2_sweep<D>(P, ROW_SLICE(P), P.nslices, U0, out, mode,
+                   GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
+}
+
+// LDS-staged row sweeps (the two passes): the block first stages its rows'
+// neighbourhood (the records of its halo nodes, up to 75 KB) and its rows
+// then read their neighbours from LDS; a block whose halo did not fit
+// gathers as above, with its wavefront tiles inside the same buffer.  The
+// diagonal sweep measured slower staged (7.8 vs 5.7 ms at 257^3): two
+// waves per SIMD leave its flux arithmetic and loads too little cover.
+#define HALO_SWEEP(NCH, BASE, CALL)                                          \
+    __shared__ double2 sh_[kHaloMax * kHaloChunks];                          \
+    const int64_t hb_ = logical_block(P.per);                                \
+    if (stage_halo<NCH>(P, hb_, BASE, sh_)) {                                \
+        const HaloFetch<NCH> f_{sh_, P.loc};                                 \
+        CALL;                                                                \
+    } else {                                                                 \
+        const GatherFetch<NCH> f_{BASE, sh_ + (threadIdx.x / kSlice) * NCH * kLdsRow}; \
+        CALL;                                                                \
+    }
+
+template <int D>
+__global__ void __launch_bounds__(kBlock, 2) k_pass1a_h(StageArgs P)
+{
+    HALO_SWEEP(Chunks<D>::packBrow, P.packB, pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, f_))
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock, 2) k_pass2_h(StageArgs P, const double *U0,
+                                                       double *out, int mode)
+{
+    HALO_SWEEP(Chunks<D>::packBrow, P.packB,
+               pass2_sweep<D>(P, ROW_SLICE(P), P.nslices, U0, out, mode, f_))
 }
 
 // ------------------------------------------------ persistent batch launch
@@ -778,12 +845,19 @@ __global__ void __launch_bounds__(kBlock) k_persistent(StageArgs P, BatchArgs B)
             case 0: node_sweep<D>(P, lin, e0, stage == 0 ? B.U : B.U1,
                                   stage == 0 ? B.check : 0); break;
             case 1: dpair_sweep<D>(P, lin, e1, lw); break;
-            case 2: diag_sweep<D>(P, sl, e2, 1, B.taumin2 + (sg & 1) * P.ninst, lw); break;
+            case 2:
+                diag_sweep<D>(P, sl, e2, 1, B.taumin2 + (sg & 1) * P.ninst,
+                              GatherFetch<kDiagChunks<D>>{P.packA, lw});
+                break;
             case 3: low_sweep<D>(P, sl, e2); break;
             case 4: lim1_sweep<D>(P, lin, e1, lw); break;
-            case 5: pass1_sweep<D>(P, sl, e2, lw); break;
+            case 5:
+                pass1_sweep<D>(P, sl, e2, GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
+                break;
             case 6: lim2_sweep<D>(P, lin, e1, lw); break;
-            default: pass2_sweep<D>(P, sl, e2, B.U, stage == 2 ? B.U : B.U1, stage + 1, lw);
+            default:
+                pass2_sweep<D>(P, sl, e2, B.U, stage == 2 ? B.U : B.U1, stage + 1,
+                               GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
             }
         }
         __threadfence();   // release: this item's stores before its completion count
@@ -873,11 +947,20 @@ void launch_diag(const StageArgs &P, hipStream_t st, int with_alpha)
 }
 void launch_low(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_low, grid_rows(P), P); }
 void launch_lim1p(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_lim1p, grid_pairs(P), P); }
-void launch_pass1a(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_pass1a, grid_rows(P), P); }
+void launch_pass1a(const StageArgs &P, hipStream_t st)
+{
+    if (P.halo_cnt)
+        LAUNCH_D(k_pass1a_h, grid_rows(P), P);
+    else
+        LAUNCH_D(k_pass1a, grid_rows(P), P);
+}
 void launch_lim2p(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_lim2p, grid_pairs(P), P); }
 void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out, int mode)
 {
-    LAUNCH_D(k_pass2, grid_rows(P), P, U0, out, mode);
+    if (P.halo_cnt)
+        LAUNCH_D(k_pass2_h, grid_rows(P), P, U0, out, mode);
+    else
+        LAUNCH_D(k_pass2, grid_rows(P), P, U0, out, mode);
 }
 
 void launch_batch_init(const StageArgs &P, const BatchArgs &B, hipStream_t st, int clear_status)

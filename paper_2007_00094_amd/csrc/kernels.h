@@ -17,6 +17,8 @@ constexpr int kPackAlpha = 12;  // pack A slot of alpha_i (written by k_diag)
 constexpr int kPackCoef = 12;   // pack B slot of tau/(lambda_i m_i)
 constexpr int kRowB = 8;      // doubles per node: U^L (nc), bounds (3)
 constexpr int kRowU = 8;      // doubles per node: state after pass 1
+constexpr int kHaloMax = 800;   // records of a row block's neighbourhood staged in LDS
+constexpr int kHaloChunks = 6;  // 16-byte chunks per staged record (800 x 6: 75 KB)
 
 // status bits (device int)
 constexpr int kErrState = 1;
@@ -60,6 +62,12 @@ struct StageArgs {
     // (bits 0-7, 8-15, 16-23; 255: the node itself)
     uint8_t *sided, *side1, *side2;
     int32_t *argk;
+    // neighbourhoods of the row blocks (4 slices) for LDS staging, or null:
+    // [per * 8] start in halo_node and size (-1: too large, gathers instead);
+    // [sell] position of entry e's column in its block's halo
+    const int64_t *halo_start;
+    const int32_t *halo_cnt, *halo_node;
+    const uint16_t *loc;
     // instances: a batch of independent meshes shares one context; their
     // slices, pairs and nodes are contiguous and never mixed
     int ninst;

@@ -165,6 +165,72 @@ __device__ __forceinline__ void scatter(double *__restrict__ base, int stride, i
     __builtin_amdgcn_wave_barrier();
 }
 
+// chunks of pack A a diagonal sweep reads: U, p, c, eta/rho, v, phi
+template <int D> constexpr int kDiagChunks = (D + 2 + 4 + D) / 2;
+
+// Where a row sweep takes its neighbours' records from.  GatherFetch: the
+// wavefront's cooperative gather from global memory (every lane of the
+// wavefront calls it).  HaloFetch: the block's neighbourhood staged in LDS,
+// entry e's record at halo position loc[e] (per lane).  token(e) is loaded
+// one entry ahead; node < 0: nothing wanted, rec untouched.
+template <int NCH>
+struct GatherFetch {
+    const double *base;
+    double2 *lw;
+    // what the fetch of entry e needs ahead of time (nothing here)
+    __device__ __forceinline__ int token(int64_t e) const
+    {
+        (void)e;
+        return 0;
+    }
+    __device__ __forceinline__ void operator()(int tok, int node, double *rec) const
+    {
+        (void)tok;
+        gather<NCH>(base, kPack, node, lw, rec);
+    }
+};
+
+template <int NCH>
+struct HaloFetch {
+    const double2 *halo;
+    const uint16_t *loc;
+    __device__ __forceinline__ int token(int64_t e) const { return int(loc[e]); }
+    __device__ __forceinline__ void operator()(int tok, int node, double *rec) const
+    {
+        if (node < 0) return;
+        const double2 *h = halo + tok * NCH;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const double2 v = h[k];
+            rec[2 * k] = v.x;
+            rec[2 * k + 1] = v.y;
+        }
+    }
+};
+
+// LDS staging of a row block's neighbourhood: the first NCH chunks of the
+// record (stride kPack) of every node in the block's halo, in halo order.
+// Every thread of the block calls it (it ends in a block barrier); false
+// if the block's halo did not fit (its rows then gather from memory).
+template <int NCH>
+__device__ __forceinline__ bool stage_halo(const StageArgs &P, int64_t b, const double *base,
+                                           double2 *halo)
+{
+    static_assert(NCH <= kHaloChunks, "halo record");
+    const int cnt = P.halo_cnt[b];
+    if (cnt < 0) return false;
+    const int64_t h0 = P.halo_start[b];
+    const int tot = cnt * NCH;
+#pragma unroll 4
+    for (int q = int(threadIdx.x); q < tot; q += kBlock) {
+        const int r = q / NCH, c = q - r * NCH;
+        halo[q] = *reinterpret_cast<const double2 *>(
+            base + int64_t(P.halo_node[h0 + r]) * kPack + 2 * c);
+    }
+    __syncthreads();
+    return true;
+}
+
 // Launch shapes of the wavefront sweeps: row sweeps take slice 4 b + w in
 // wavefront w of logical block b; pair sweeps one pair per lane.
 #define ROW_SLICE(P) (logical_block(P.per) * (kBlock / kSlice) + threadIdx.x / kSlice)

@@ -175,6 +175,40 @@ def test_max_dt_and_free_stream(torch, oracle_mod):
     s.close()
 
 
+STAGING_CASES = [
+    ("mach3 3D 33^3 Morton (staged blocks)", 3, 33, "morton", "mach3"),
+    ("four-quadrant 2D 65^2 lex (staged blocks)", 2, 65, "lex", "quad"),
+    ("sphere 3D 17^3 random (every halo too large: gathers)", 3, 17, "random", "sphere"),
+]
+
+
+@pytest.mark.parametrize("name,dim,n,order,ic", STAGING_CASES)
+def test_lds_staging_is_bitwise_the_gather_path(torch, oracle_mod, name, dim, n, order, ic):
+    """Row sweeps that stage their block's neighbourhood in LDS give the
+    same bits as the cooperative gathers, and both the oracle's."""
+    announce(f"LDS staging vs gathers: {name}")
+    from paper_2007_00094_amd.solver import Solver
+    mesh = inputs.q1_grid(n, dim, 0.2, seed=0, order=order, perm_seed=1)
+    U0 = {"mach3": lambda: inputs.ic_mach3_blobs(mesh.coords),
+          "quad": lambda: inputs.ic_four_quadrant(mesh.coords),
+          "sphere": lambda: inputs.ic_sphere(mesh.coords)}[ic]()
+    outs = []
+    for staging in (True, False):
+        s = Solver(mesh, staging=staging)
+        U = torch.tensor(U0, device="cuda")
+        for _ in range(3):
+            s.step(U)
+        outs.append(U.cpu().numpy())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    o = oracle_mod.Oracle(mesh, dirichlet=mesh.boundary)
+    V = U0.copy()
+    for _ in range(3):
+        V, _, st = o.step(V)
+        assert st == 0
+    assert np.array_equal(outs[0], V)
+
+
 def test_determinism(torch):
     announce("determinism: two runs, sphere 3D 13^3")
     mesh = inputs.q1_grid(13, 3, 0.2, seed=0, order="random")
