@@ -371,10 +371,13 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
 }
 
 // ------------------------------------------------------ row low order
-// Step 3.  Its per-entry arithmetic (two fluxes, a division) hides the
-// latency of plain per-lane record loads better than a cooperative gather.
+// Step 3.  In 3D its per-entry arithmetic (two fluxes, a division) hides
+// the latency of plain per-lane record loads better than a cooperative
+// gather; in 2D (half the arithmetic per entry) the gather is used.
+template <int D> constexpr bool kLowCoop = D == 2;
 template <int D>
-__device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int64_t send)
+__device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int64_t send,
+                                          double2 *lw)
 {
     WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
@@ -399,10 +402,20 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
         double c[D];
         load_c<D>(P, e, c);
         const double dL = P.d[e];
-        if (!act) continue;
         NodeA<D> Aj;
-        load_a<D>(P.packA + int64_t(j) * kPack, Aj);
-        const double alpha_j = P.packA[int64_t(j) * kPack + kPackAlpha];
+        double alpha_j;
+        if (kLowCoop<D>) {
+            constexpr int NCH = kDiagChunks<D> + 1;   // pack A to phi, and alpha's chunk
+            double rec[2 * NCH];
+            gather_tail<NCH, kPackAlpha / 2>(P.packA, kPack, act ? j : -1, lw, rec);
+            if (!act) continue;
+            unpack_a<D>(rec, Aj);
+            alpha_j = rec[2 * (NCH - 1)];
+        } else {
+            if (!act) continue;
+            load_a<D>(P.packA + int64_t(j) * kPack, Aj);
+            alpha_j = P.packA[int64_t(j) * kPack + kPackAlpha];
+        }
         const double dH = dL * (alpha_i + alpha_j) / 2.0;
         double Fj[NC][D], fd[NC];
         flux<D>(Aj.U, Aj.v, Aj.p, Fj);
@@ -689,7 +702,8 @@ __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
 {
-    low_sweep<D>(P, ROW_SLICE(P), P.nslices);
+    WAVE_LDS(kLowCoop<D> ? kDiagChunks<D> + 1 : 1)
+    low_sweep<D>(P, ROW_SLICE(P), P.nslices, lw);
 }
 
 template <int D>
@@ -849,7 +863,7 @@ __global__ void __launch_bounds__(kBlock) k_persistent(StageArgs P, BatchArgs B)
                 diag_sweep<D>(P, sl, e2, 1, B.taumin2 + (sg & 1) * P.ninst,
                               GatherFetch<kDiagChunks<D>>{P.packA, lw});
                 break;
-            case 3: low_sweep<D>(P, sl, e2); break;
+            case 3: low_sweep<D>(P, sl, e2, lw); break;
             case 4: lim1_sweep<D>(P, lin, e1, lw); break;
             case 5:
                 pass1_sweep<D>(P, sl, e2, GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
