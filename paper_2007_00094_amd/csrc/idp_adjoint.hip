@@ -477,11 +477,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_lim2(StageArgs P, AdjArgs A)
     double Pij[NC], Pji[NC];
     {
         NodeB<D> Bi, Bj;
-        double rec[2 * CH::packB];
-        gather<CH::packB>(P.packB, kPack, i, lw, rec);
-        unpack_b<D, true>(rec, Bi);
-        gather<CH::packB>(P.packB, kPack, j, lw, rec);
-        unpack_b<D, true>(rec, Bj);
+        gather_b<D>(P.packB, i, lw, Bi);
+        gather_b<D>(P.packB, j, lw, Bj);
         direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
         direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
     }
@@ -582,11 +579,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_adj_lim1(StageArgs P, AdjArgs A)
     double Pij[NC], Pji[NC], dU[NC], ci, cj, asum;
     {
         NodeB<D> Bi, Bj;
-        double rec[2 * CH::packB];
-        gather<CH::packB>(P.packB, kPack, i, lw, rec);
-        unpack_b<D, true>(rec, Bi);
-        gather<CH::packB>(P.packB, kPack, j, lw, rec);
-        unpack_b<D, true>(rec, Bj);
+        gather_b<D>(P.packB, i, lw, Bi);
+        gather_b<D>(P.packB, j, lw, Bj);
         direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
         direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
 #pragma unroll

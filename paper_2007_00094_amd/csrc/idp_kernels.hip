@@ -464,11 +464,9 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
     using CH = Chunks<D>;
     const double dL = P.dp[pq_], m = P.mp[pq_];
     NodeB<D> Bi, Bj;
-    double rec[2 * CH::packB], Wi[2 * CH::rowB], Wj[2 * CH::rowB];
-    gather<CH::packB>(P.packB, kPack, i, lw, rec);
-    unpack_b<D, true>(rec, Bi);
-    gather<CH::packB>(P.packB, kPack, j, lw, rec);
-    unpack_b<D, true>(rec, Bj);
+    double Wi[2 * CH::rowB], Wj[2 * CH::rowB];
+    gather_b<D>(P.packB, i, lw, Bi);
+    gather_b<D>(P.packB, j, lw, Bj);
     gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
     gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
     if (!valid_) return;
@@ -562,12 +560,10 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
     const double dL = P.dp[pq_], m = P.mp[pq_];
     const double l = P.l1p[pq_];
     NodeB<D> Bi, Bj;
-    double rec[2 * CH::packB], Wi[2 * CH::rowB], Wj[2 * CH::rowB];
+    double Wi[2 * CH::rowB], Wj[2 * CH::rowB];
     double Ui[2 * CH::upass], Uj[2 * CH::upass];
-    gather<CH::packB>(P.packB, kPack, i, lw, rec);
-    unpack_b<D, true>(rec, Bi);
-    gather<CH::packB>(P.packB, kPack, j, lw, rec);
-    unpack_b<D, true>(rec, Bj);
+    gather_b<D>(P.packB, i, lw, Bi);
+    gather_b<D>(P.packB, j, lw, Bj);
     gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
     gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
     gather<CH::upass>(P.upass, kRowU, i, lw, Ui);

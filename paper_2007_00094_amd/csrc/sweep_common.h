@@ -107,6 +107,10 @@ __device__ __forceinline__ void gather_tail(const double *__restrict__ base, int
                                             double2 *lds, double *out)
 {
     static_assert(NCH >= 2 && NCH <= 8 && LAST >= NCH - 1, "prefix plus one chunk");
+    if constexpr (LAST == NCH - 1) {
+        gather<NCH>(base, stride, node, lds, out);   // contiguous after all
+        return;
+    }
     constexpr int LPR = NCH > 4 ? 8 : (NCH > 2 ? 4 : 2);
     constexpr int RPI = kSlice / LPR;
     const int lane = threadIdx.x % kSlice;
@@ -329,6 +333,26 @@ __device__ __forceinline__ void unpack_b(const double *o, NodeB<D> &B)
     B.alpha = o[2 * NC];
     B.m = o[2 * NC + 1];
     B.coef = WITH_COEF ? o[kPackCoef] : 0.0;
+}
+
+// Pack B record of `node` with the coefficient, gathered cooperatively:
+// U, R, alpha, m (2 nc + 2 doubles) and the coefficient's chunk (in 2D the
+// record's middle chunk is skipped).  Every lane of the wavefront calls it.
+template <int D>
+__device__ __forceinline__ void gather_b(const double *__restrict__ packB, int node, double2 *lw,
+                                         NodeB<D> &B)
+{
+    constexpr int NC = D + 2, NB = (2 * NC + 2) / 2;
+    double rec[2 * (NB + 1)];
+    gather_tail<NB + 1, kPackCoef / 2>(packB, kPack, node, lw, rec);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        B.U[k] = rec[k];
+        B.R[k] = rec[NC + k];
+    }
+    B.alpha = rec[2 * NC];
+    B.m = rec[2 * NC + 1];
+    B.coef = rec[2 * NB];
 }
 
 // eq. def-p: P_ij = tau/(lambda_i m_i) (b_ij R_j - b_ji R_i + (d^H - d^L)(U_j - U_i)),
