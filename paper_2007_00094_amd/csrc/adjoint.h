@@ -12,10 +12,10 @@ namespace idp {
 // cooperative gathers have even strides (16-byte chunks).
 constexpr int kEbS = 8;    // node: stage-output cotangent (nc), padded
 constexpr int kUpS = 8;    // node: pass-1 state's cotangent (nc), bounds' (3)
-constexpr int kC2S = 8;    // entry: pass-2 limiter's state (nc) and bounds (3) cotangents
-constexpr int kC1S = 16;   // entry: pass-1 limiter's U^L (nc) and bounds (3) cotangents
-                           // [0, 8); direction cotangent Z (nc) [8, 13); alpha's
-                           // share [13]; d^H - d^L [14]
+constexpr int kLimS = 8;   // pair: the active candidate's state (nc) and bounds (3)
+                           // cotangents of one limiter pass (written only if nonzero)
+constexpr int kZS = 8;     // entry: direction cotangent +-Z (nc) [0, 5), alpha's share [5],
+                           // d^H - d^L [6], the pass-1 limiter record of the row [7]
 constexpr int kC5S = 6;    // entry: state cotangent (nc) from the graph viscosity
 constexpr int kQS = 6;     // pair: cotangent of the pass-2 direction (nc)
 constexpr int kNS = 16;    // node: Lw's (nc) [0, 5), R's (nc) [5, 10), bounds' [10, 13)
@@ -25,9 +25,11 @@ constexpr int kIS = 8;     // node: the indicator's a and b (nc) cotangents [0, 
                            // eta/rho [6]
 
 // Work arrays of one stage's vector-Jacobian product (device).  The
-// per-entry buffer C holds, in turn, the pass-2 limiter records (kC2S), the
-// pass-1 limiter and direction records (kC1S) and the graph-viscosity
-// records (kC5S): each is dead before the next is written.
+// per-entry buffer C holds the direction records (kZS), then the
+// graph-viscosity records (kC5S); the pair buffer Lim the pass-2, then the
+// pass-1 limiter records.  Each is dead before the next is written.  A
+// limiter record exists only where the active candidate's cotangents are
+// nonzero (a limited pair); an entry finds it through its index (-1: none).
 struct AdjArgs {
     double tau;
     const double *Ebp;  // [n][kEbS] cotangent of the stage output E(U)
@@ -38,7 +40,9 @@ struct AdjArgs {
     double *Up4, *Up6;  // [n][nc] parts of U's cotangent (low order; indicator and
                         // the neighbours' low order)
     double *alb;        // [n] alpha's cotangent from the directions and its own R
-    double *C;          // [sell][kC1S]
+    double *C;          // [sell][kZS]
+    int32_t *lim2e;     // [sell] pass-2 limiter record of the entry's row, or -1
+    double *Lim;        // [npairs][kLimS]
     double *db4;        // [sell] d_ij's cotangent from row i's low-order update
     double *Qb;         // [npairs][kQS]
     double *dLb;        // [npairs] d_ij's cotangent: the directions', then the total

@@ -460,15 +460,37 @@ __device__ __forceinline__ int id_hi(double v)
     return int((unsigned)((unsigned long long)__double_as_longlong(v) >> 32));
 }
 
+// A pair's limiter record, if the active candidate's cotangents are not
+// all zero: stored at Lim[p]; returns p, else -1.
+template <int D>
+__device__ __forceinline__ int put_lim(double *Lim, int64_t p, bool valid, const double *Ub,
+                                       const double *bb)
+{
+    constexpr int NC = D + 2;
+    bool nz = false;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) nz = nz || Ub[r] != 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) nz = nz || bb[q] != 0.0;
+    if (!valid || !nz) return -1;
+    double *o = Lim + p * kLimS;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) o[r] = Ub[r];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) o[NC + q] = bb[q];
+    return int(p);
+}
+
 // pass 2 and its limiter backwards (pair).  E_i = U_i' + sum_j lambda_i
 // s2_ij (1 - s1_ij) P_ij gives s2's cotangent; the candidate that set
 // s2 = min(l_ij, l_ji) is run backwards (Alg. 2/3 on the line U_a' + t
-// (1 - s1) P_a): its state and bounds cotangents go to the entry of its row
-// (zeros to the other), the direction's cotangent to the pair.
+// (1 - s1) P_a): its state and bounds cotangents go to the pair's limiter
+// record (indexed from the entry of its row), the direction's to the pair.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_lim2(StageArgs P, AdjArgs A)
 {
     WAVE_LDS(Chunks<D>::packB)
+    static_assert(kTile_ > 0 && Chunks<D>::packB >= kQS / 2 && Chunks<D>::packB >= Chunks<D>::rowB, "tile fits every record");
     WAVE_PAIR_SETUP(P, PAIR_INDEX(P), P.npairs)
     constexpr int NC = D + 2, NU = (NC + 1) / 2;
     using CH = Chunks<D>;
@@ -508,26 +530,22 @@ __global__ void __launch_bounds__(kBlock) k_adj_lim2(StageArgs P, AdjArgs A)
     if (valid_ && sb != 0.0)
         limiter_vjp<D>(Ua, Qa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
                        Ub, Qb, bb);
-    double ra[kC2S], rz[kC2S], rq[kQS];
-#pragma unroll
-    for (int r = 0; r < kC2S; ++r) { rz[r] = 0.0; ra[r] = 0.0; }
-#pragma unroll
-    for (int r = 0; r < NC; ++r) ra[r] = Ub[r];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) ra[NC + q] = bb[q];
+    double rq[kQS];
 #pragma unroll
     for (int r = 0; r < kQS; ++r) rq[r] = r < NC ? Qb[r] : 0.0;
-    scatter<kC2S / 2>(A.C, kC2S, valid_ ? int(e) : -1, lw, iside ? ra : rz);
-    scatter<kC2S / 2>(A.C, kC2S, valid_ ? int(t) : -1, lw, iside ? rz : ra);
     scatter<kQS / 2>(A.Qb, kQS, valid_ ? int(p_) : -1, lw, rq);
+    const int rec = put_lim<D>(A.Lim, p_, valid_, Ub, bb);
+    if (valid_) {
+        A.lim2e[e] = iside ? rec : -1;
+        A.lim2e[t] = iside ? -1 : rec;
+    }
 }
 
-// pass 1 backwards (row): U_i' = E_i's cotangent plus the pass-2 limiter's
-// records of the row; the bounds' cotangents so far.
+// pass 1 backwards (row): U_i' = E_i's cotangent plus the pass-2 limiter
+// records of the row's pairs; the bounds' cotangents so far.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_pass1(StageArgs P, AdjArgs A)
 {
-    WAVE_LDS(kC2S / 2)
     WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
     (void)inst_;   // one instance: adjoints run on single meshes
     constexpr int NC = D + 2;
@@ -539,9 +557,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_pass1(StageArgs P, AdjArgs A)
         for (int k = 0; k < Lmax_; ++k) {
             const int64_t e = ENTRY(k);
             const bool act = k < L && k != dk;
-            double rec[kC2S];
-            gather<kC2S / 2>(A.C, kC2S, act ? int(e) : -1, lw, rec);
-            if (!act) continue;
+            const int q_ = act ? A.lim2e[e] : -1;
+            if (q_ < 0) continue;
+            const double *rec = A.Lim + int64_t(q_) * kLimS;
 #pragma unroll
             for (int r = 0; r < NC; ++r) u[r] += rec[r];
 #pragma unroll
@@ -566,7 +584,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_pass1(StageArgs P, AdjArgs A)
 template <int D>
 __global__ void __launch_bounds__(kBlock, 2) k_adj_lim1(StageArgs P, AdjArgs A)
 {
-    WAVE_LDS(kC1S / 2)
+    WAVE_LDS(Chunks<D>::packB)
+    static_assert(kTile_ > 0 && Chunks<D>::packB >= kZS / 2 && Chunks<D>::packB >= kQS / 2, "tile fits every record");
     WAVE_PAIR_SETUP(P, PAIR_INDEX(P), P.npairs)
     constexpr int NC = D + 2, NU = (NC + 1) / 2;
     using CH = Chunks<D>;
@@ -639,20 +658,18 @@ __global__ void __launch_bounds__(kBlock, 2) k_adj_lim1(StageArgs P, AdjArgs A)
         kb -= Z[r] * dU[r];
     }
     const double dH = dL * asum / 2.0;
-    double re[kC1S], rt[kC1S];
+    const int rec = put_lim<D>(A.Lim, p_, valid_, ULb, bb);
+    double re[kZS], rt[kZS];
 #pragma unroll
-    for (int r = 0; r < kC1S; ++r) { re[r] = 0.0; rt[r] = 0.0; }
-    double *ra = side1 ? re : rt;
+    for (int r = 0; r < kZS; ++r) { re[r] = 0.0; rt[r] = 0.0; }
 #pragma unroll
-    for (int r = 0; r < NC; ++r) ra[r] = ULb[r];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) ra[NC + q] = bb[q];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) { re[8 + r] = Z[r]; rt[8 + r] = -Z[r]; }
-    re[13] = rt[13] = kb * dL / 2.0;
-    re[14] = rt[14] = dH - dL;
-    scatter<kC1S / 2>(A.C, kC1S, valid_ ? int(e) : -1, lw, re);
-    scatter<kC1S / 2>(A.C, kC1S, valid_ ? int(t) : -1, lw, rt);
+    for (int r = 0; r < NC; ++r) { re[r] = Z[r]; rt[r] = -Z[r]; }
+    re[5] = rt[5] = kb * dL / 2.0;
+    re[6] = rt[6] = dH - dL;
+    re[7] = __longlong_as_double((long long)(side1 ? rec : -1));
+    rt[7] = __longlong_as_double((long long)(side1 ? -1 : rec));
+    scatter<kZS / 2>(A.C, kZS, valid_ ? int(e) : -1, lw, re);
+    scatter<kZS / 2>(A.C, kZS, valid_ ? int(t) : -1, lw, rt);
     if (valid_) A.dLb[p_] = kb * (asum / 2.0 - 1.0);
 }
 
@@ -665,7 +682,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_adj_lim1(StageArgs P, AdjArgs A)
 template <int D>
 __global__ void __launch_bounds__(kBlock, 3) k_adj_low(StageArgs P, AdjArgs A)
 {
-    WAVE_LDS(kC1S / 2)
+    WAVE_LDS(kNS / 2)
+    static_assert(kTile_ > 0 && kNS / 2 >= kZS / 2, "tile fits every record");
     WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
     (void)inst_;   // one instance: adjoints run on single meshes
     constexpr int NC = D + 2, NU = (NC + 1) / 2;
@@ -687,19 +705,24 @@ __global__ void __launch_bounds__(kBlock, 3) k_adj_low(StageArgs P, AdjArgs A)
     for (int k = 0; k < Lmax_; ++k) {
         const int64_t e = ENTRY(k);
         const bool act = k < L && k != dk;
-        double rec[kC1S];
-        gather<kC1S / 2>(A.C, kC1S, act ? int(e) : -1, lw, rec);
+        double rec[kZS];
+        gather<kZS / 2>(A.C, kZS, act ? int(e) : -1, lw, rec);
         if (!act) continue;
         const double b = -P.mij[e] / mi;
 #pragma unroll
         for (int r = 0; r < NC; ++r) {
-            ULb[r] += rec[r];
-            Rb[r] += b * rec[8 + r];
-            Ud[r] += rec[14] * rec[8 + r];
+            Rb[r] += b * rec[r];
+            Ud[r] += rec[6] * rec[r];
         }
+        alb += rec[5];
+        const int q_ = int(__double_as_longlong(rec[7]));
+        if (q_ >= 0) {
+            const double *lr = A.Lim + int64_t(q_) * kLimS;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) bnd[q] += rec[NC + q];
-        alb += rec[13];
+            for (int r = 0; r < NC; ++r) ULb[r] += lr[r];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) bnd[q] += lr[NC + q];
+        }
     }
     double Lwb[NC];
 #pragma unroll
@@ -806,6 +829,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_alpha(StageArgs P, AdjArgs A)
 {
     WAVE_LDS(kNS / 2)
+    static_assert(kTile_ > 0 && kNS / 2 >= kIS / 2, "tile fits every record");
     WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
     (void)inst_;   // one instance: adjoints run on single meshes
     constexpr int NC = D + 2;
@@ -954,6 +978,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_dpair(StageArgs P, AdjArgs A)
     constexpr int NC = D + 2;
     constexpr int NCH = (NC + 3) / 2;   // U, p, c
     WAVE_LDS(NCH)
+    static_assert(kTile_ >= kC5S / 2, "tile fits every record");
     WAVE_PAIR_SETUP(P, PAIR_INDEX(P), P.npairs)
     double Ai[2 * NCH], Aj[2 * NCH];
     gather<NCH>(P.packA, kPack, i, lw, Ai);
@@ -1005,6 +1030,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_adj_final(StageArgs P, AdjArgs A)
 {
     WAVE_LDS(kIS / 2)
+    static_assert(kTile_ > 0 && kIS / 2 >= kC5S / 2, "tile fits every record");
     WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
     (void)inst_;   // one instance: adjoints run on single meshes
     constexpr int NC = D + 2;

@@ -448,12 +448,11 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
     HIPTRY(hipMemcpyAsync(pi, g.pair_i.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemcpyAsync(pj, g.pair_j.data(), g.npairs * 4, hipMemcpyHostToDevice, c->stream));
     HIPTRY(hipMemsetAsync(c->scal, 0, scal_bytes(K), c->stream));
-    // neighbourhoods of the row blocks for the LDS-staged row sweeps (3D:
-    // in 2D the gathers measured faster)
-    if (dim == 3 && !(p.flags & IDP_FLAG_NO_STAGING)) {
+    // neighbourhoods of the row blocks for the LDS-staged row sweeps
+    if (!(p.flags & IDP_FLAG_NO_STAGING)) {
         idp::Halos h;
         const int64_t nblk = int64_t(P.per) * idp::kXcd;
-        TRY(idp::build_halos(g, nblk, idp::kHaloMax, h));
+        TRY(idp::build_halos(g, nblk, dim == 3 ? idp::kHaloMax3 : idp::kHaloMax2, h));
         int64_t *hs;
         int32_t *hc, *hn;
         uint16_t *hl;
@@ -795,7 +794,9 @@ int adj_setup(idp_ctx *c)
     ADJ_ALLOC(A.Up4, n * nc);
     ADJ_ALLOC(A.Up6, n * nc);
     ADJ_ALLOC(A.alb, n);
-    ADJ_ALLOC(A.C, S * idp::kC1S);
+    ADJ_ALLOC(A.C, S * idp::kZS);
+    ADJ_ALLOC(A.lim2e, S);
+    ADJ_ALLOC(A.Lim, np * idp::kLimS);
     ADJ_ALLOC(A.db4, S);
     ADJ_ALLOC(A.Qb, np * idp::kQS);
     ADJ_ALLOC(A.dLb, np);

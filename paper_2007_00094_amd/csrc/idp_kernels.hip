@@ -373,11 +373,11 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
 // ------------------------------------------------------ row low order
 // Step 3.  In 3D its per-entry arithmetic (two fluxes, a division) hides
 // the latency of plain per-lane record loads better than a cooperative
-// gather; in 2D (half the arithmetic per entry) the gather is used.
-template <int D> constexpr bool kLowCoop = D == 2;
-template <int D>
+// gather or LDS staging; in 2D (half the arithmetic per entry) the
+// neighbours come from LDS, or from a cooperative gather.
+template <int D, class F>
 __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int64_t send,
-                                          double2 *lw)
+                                          const F &fetch)
 {
     WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
@@ -402,20 +402,13 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
         double c[D];
         load_c<D>(P, e, c);
         const double dL = P.d[e];
+        constexpr int NCH = kLowChunks<D>;   // pack A to phi, and alpha's chunk
+        double rec[2 * NCH];
+        fetch(fetch.token(e), act ? j : -1, rec);
+        if (!act) continue;
         NodeA<D> Aj;
-        double alpha_j;
-        if (kLowCoop<D>) {
-            constexpr int NCH = kDiagChunks<D> + 1;   // pack A to phi, and alpha's chunk
-            double rec[2 * NCH];
-            gather_tail<NCH, kPackAlpha / 2>(P.packA, kPack, act ? j : -1, lw, rec);
-            if (!act) continue;
-            unpack_a<D>(rec, Aj);
-            alpha_j = rec[2 * (NCH - 1)];
-        } else {
-            if (!act) continue;
-            load_a<D>(P.packA + int64_t(j) * kPack, Aj);
-            alpha_j = P.packA[int64_t(j) * kPack + kPackAlpha];
-        }
+        unpack_a<D>(rec, Aj);
+        const double alpha_j = rec[2 * (NCH - 1)];
         const double dH = dL * (alpha_i + alpha_j) / 2.0;
         double Fj[NC][D], fd[NC];
         flux<D>(Aj.U, Aj.v, Aj.p, Fj);
@@ -698,9 +691,34 @@ __global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
 {
-    WAVE_LDS(kLowCoop<D> ? kDiagChunks<D> + 1 : 1)
-    low_sweep<D>(P, ROW_SLICE(P), P.nslices, lw);
+    if constexpr (D == 3) {
+        low_sweep<D>(P, ROW_SLICE(P), P.nslices,
+                     LaneTailFetch<kLowChunks<D>, kPackAlpha / 2>{P.packA});
+    } else {
+        WAVE_LDS(kLowChunks<D>)
+        low_sweep<D>(P, ROW_SLICE(P), P.nslices,
+                     GatherTailFetch<kLowChunks<D>, kPackAlpha / 2>{P.packA, lw});
+    }
 }
+
+// the persistent worker's low-order fetch: per lane in 3D, gathered in 2D
+template <int D>
+struct LowFetch {
+    const double *base;
+    double2 *lw;
+    __device__ __forceinline__ int token(int64_t e) const
+    {
+        (void)e;
+        return 0;
+    }
+    __device__ __forceinline__ void operator()(int tok, int node, double *rec) const
+    {
+        if constexpr (D == 3)
+            LaneTailFetch<kLowChunks<D>, kPackAlpha / 2>{base}(tok, node, rec);
+        else
+            GatherTailFetch<kLowChunks<D>, kPackAlpha / 2>{base, lw}(tok, node, rec);
+    }
+};
 
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_lim1p(StageArgs P)
@@ -732,35 +750,47 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
                    GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
 }
 
-// LDS-staged row sweeps (the two passes): the block first stages its rows'
-// neighbourhood (the records of its halo nodes, up to 75 KB) and its rows
-// then read their neighbours from LDS; a block whose halo did not fit
-// gathers as above, with its wavefront tiles inside the same buffer.  The
-// diagonal sweep measured slower staged (7.8 vs 5.7 ms at 257^3): two
-// waves per SIMD leave its flux arithmetic and loads too little cover.
-#define HALO_SWEEP(NCH, BASE, CALL)                                          \
-    __shared__ double2 sh_[kHaloMax * kHaloChunks];                          \
+// LDS-staged row sweeps: the block first stages its rows' neighbourhood
+// (the records of its halo nodes, up to 75 KB in 3D, 48 KB in 2D) and its
+// rows then read their neighbours from LDS; a block whose halo did not fit
+// gathers as above, with its wavefront tiles inside the same buffer.
+// Staged: the two passes, and in 2D the low-order sweep.  The diagonal
+// sweep measured slower staged in both dimensions (3D 7.8 vs 5.7 ms at
+// 257^3, 2D 0.77 vs 0.58 ms on the 64-mesh batch) and keeps the gathers.
+#define HALO_SWEEP(NCH, LAST, BASE, CALL)                                    \
+    __shared__ double2 sh_[kHaloMaxD<D> * (NCH)];                            \
     const int64_t hb_ = logical_block(P.per);                                \
-    if (stage_halo<NCH>(P, hb_, BASE, sh_)) {                                \
+    if (stage_halo<NCH, LAST>(P, hb_, BASE, sh_)) {                          \
         const HaloFetch<NCH> f_{sh_, P.loc};                                 \
         CALL;                                                                \
     } else {                                                                 \
-        const GatherFetch<NCH> f_{BASE, sh_ + (threadIdx.x / kSlice) * NCH * kLdsRow}; \
+        const GatherTailFetch<NCH, LAST> f_{BASE,                            \
+                                            sh_ + (threadIdx.x / kSlice) * (NCH) * kLdsRow}; \
         CALL;                                                                \
     }
 
 template <int D>
-__global__ void __launch_bounds__(kBlock, 2) k_pass1a_h(StageArgs P)
+__global__ void __launch_bounds__(kBlock) k_pass1a_h(StageArgs P)
 {
-    HALO_SWEEP(Chunks<D>::packBrow, P.packB, pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, f_))
+    constexpr int NCH = Chunks<D>::packBrow;
+    HALO_SWEEP(NCH, NCH - 1, P.packB, pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, f_))
 }
 
 template <int D>
-__global__ void __launch_bounds__(kBlock, 2) k_pass2_h(StageArgs P, const double *U0,
-                                                       double *out, int mode)
+__global__ void __launch_bounds__(kBlock) k_pass2_h(StageArgs P, const double *U0, double *out,
+                                                    int mode)
 {
-    HALO_SWEEP(Chunks<D>::packBrow, P.packB,
+    constexpr int NCH = Chunks<D>::packBrow;
+    HALO_SWEEP(NCH, NCH - 1, P.packB,
                pass2_sweep<D>(P, ROW_SLICE(P), P.nslices, U0, out, mode, f_))
+}
+
+// staged low-order sweep: launched for 2D meshes only
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_low_h(StageArgs P)
+{
+    HALO_SWEEP(kLowChunks<D>, kPackAlpha / 2, P.packA,
+               low_sweep<D>(P, ROW_SLICE(P), P.nslices, f_))
 }
 
 // ------------------------------------------------ persistent batch launch
@@ -859,7 +889,7 @@ __global__ void __launch_bounds__(kBlock) k_persistent(StageArgs P, BatchArgs B)
                 diag_sweep<D>(P, sl, e2, 1, B.taumin2 + (sg & 1) * P.ninst,
                               GatherFetch<kDiagChunks<D>>{P.packA, lw});
                 break;
-            case 3: low_sweep<D>(P, sl, e2, lw); break;
+            case 3: low_sweep<D>(P, sl, e2, LowFetch<D>{P.packA, lw}); break;
             case 4: lim1_sweep<D>(P, lin, e1, lw); break;
             case 5:
                 pass1_sweep<D>(P, sl, e2, GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
@@ -955,7 +985,13 @@ void launch_diag(const StageArgs &P, hipStream_t st, int with_alpha)
 {
     LAUNCH_D(k_diag, grid_rows(P), P, with_alpha);
 }
-void launch_low(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_low, grid_rows(P), P); }
+void launch_low(const StageArgs &P, hipStream_t st)
+{
+    if (P.halo_cnt && P.dim == 2)
+        hipLaunchKernelGGL(k_low_h<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    else
+        LAUNCH_D(k_low, grid_rows(P), P);
+}
 void launch_lim1p(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_lim1p, grid_pairs(P), P); }
 void launch_pass1a(const StageArgs &P, hipStream_t st)
 {

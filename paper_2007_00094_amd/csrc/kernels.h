@@ -17,8 +17,11 @@ constexpr int kPackAlpha = 12;  // pack A slot of alpha_i (written by k_diag)
 constexpr int kPackCoef = 12;   // pack B slot of tau/(lambda_i m_i)
 constexpr int kRowB = 8;      // doubles per node: U^L (nc), bounds (3)
 constexpr int kRowU = 8;      // doubles per node: state after pass 1
-constexpr int kHaloMax = 800;   // records of a row block's neighbourhood staged in LDS
-constexpr int kHaloChunks = 6;  // 16-byte chunks per staged record (800 x 6: 75 KB)
+// records of a row block's neighbourhood staged in LDS (3D: about 700 at
+// Morton order, 2D: about 350), at most 6 chunks each (75 KB, 48 KB)
+constexpr int kHaloMax3 = 800;
+constexpr int kHaloMax2 = 512;
+template <int D> constexpr int kHaloMaxD = D == 3 ? kHaloMax3 : kHaloMax2;
 
 // status bits (device int)
 constexpr int kErrState = 1;

@@ -169,8 +169,10 @@ __device__ __forceinline__ void scatter(double *__restrict__ base, int stride, i
     __builtin_amdgcn_wave_barrier();
 }
 
-// chunks of pack A a diagonal sweep reads: U, p, c, eta/rho, v, phi
+// chunks of pack A a diagonal sweep reads: U, p, c, eta/rho, v, phi; the
+// low-order sweep reads the same and alpha's chunk
 template <int D> constexpr int kDiagChunks = (D + 2 + 4 + D) / 2;
+template <int D> constexpr int kLowChunks = kDiagChunks<D> + 1;
 
 // Where a row sweep takes its neighbours' records from.  GatherFetch: the
 // wavefront's cooperative gather from global memory (every lane of the
@@ -216,11 +218,11 @@ struct HaloFetch {
 // record (stride kPack) of every node in the block's halo, in halo order.
 // Every thread of the block calls it (it ends in a block barrier); false
 // if the block's halo did not fit (its rows then gather from memory).
-template <int NCH>
+template <int NCH, int LAST = NCH - 1>
 __device__ __forceinline__ bool stage_halo(const StageArgs &P, int64_t b, const double *base,
                                            double2 *halo)
 {
-    static_assert(NCH <= kHaloChunks, "halo record");
+    static_assert(NCH <= 6 && LAST >= NCH - 1, "halo record");
     const int cnt = P.halo_cnt[b];
     if (cnt < 0) return false;
     const int64_t h0 = P.halo_start[b];
@@ -228,18 +230,60 @@ __device__ __forceinline__ bool stage_halo(const StageArgs &P, int64_t b, const 
 #pragma unroll 4
     for (int q = int(threadIdx.x); q < tot; q += kBlock) {
         const int r = q / NCH, c = q - r * NCH;
+        const int src = c == NCH - 1 ? LAST : c;
         halo[q] = *reinterpret_cast<const double2 *>(
-            base + int64_t(P.halo_node[h0 + r]) * kPack + 2 * c);
+            base + int64_t(P.halo_node[h0 + r]) * kPack + 2 * src);
     }
     __syncthreads();
     return true;
 }
+
+// Fetches of chunks 0 .. NCH-2 and chunk LAST of a record: per lane
+// (LaneTailFetch) or wavefront-cooperative (GatherTailFetch).
+template <int NCH, int LAST>
+struct LaneTailFetch {
+    const double *base;
+    __device__ __forceinline__ int token(int64_t e) const
+    {
+        (void)e;
+        return 0;
+    }
+    __device__ __forceinline__ void operator()(int tok, int node, double *rec) const
+    {
+        (void)tok;
+        if (node < 0) return;
+        const double *a = base + int64_t(node) * kPack;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int src = k == NCH - 1 ? LAST : k;
+            rec[2 * k] = a[2 * src];
+            rec[2 * k + 1] = a[2 * src + 1];
+        }
+    }
+};
+
+template <int NCH, int LAST>
+struct GatherTailFetch {
+    const double *base;
+    double2 *lw;
+    __device__ __forceinline__ int token(int64_t e) const
+    {
+        (void)e;
+        return 0;
+    }
+    __device__ __forceinline__ void operator()(int tok, int node, double *rec) const
+    {
+        (void)tok;
+        gather_tail<NCH, LAST>(base, kPack, node, lw, rec);
+    }
+};
 
 // Launch shapes of the wavefront sweeps: row sweeps take slice 4 b + w in
 // wavefront w of logical block b; pair sweeps one pair per lane.
 #define ROW_SLICE(P) (logical_block(P.per) * (kBlock / kSlice) + threadIdx.x / kSlice)
 #define PAIR_INDEX(P) (logical_block(P.pper) * kBlock + threadIdx.x)
 #define WAVE_LDS(NCH)                                                        \
+    [[maybe_unused]] constexpr int kTile_ = (NCH);  /* chunks per record */ \
     __shared__ double2 lds_[kBlock / kSlice][(NCH) * kLdsRow];               \
     double2 *const lw = lds_[threadIdx.x / kSlice];
 
