@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--order", default="morton", choices=["morton", "random", "lex"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched measurement")
-    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--no-staging", action="store_true",
                     help="row sweeps gather from memory instead of staging in LDS")

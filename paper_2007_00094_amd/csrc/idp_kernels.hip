@@ -218,30 +218,33 @@ __global__ void k_tau(StageArgs P, double dt_in, int mode)
 // iend; with check, flags inadmissible input.
 template <int D>
 __device__ __forceinline__ void node_sweep(const StageArgs &P, int64_t i, int64_t iend,
-                                           const double *__restrict__ U, int check)
+                                           const double *__restrict__ U, int check, double2 *lw)
 {
-    if (i >= iend) return;
+    // whole wavefronts past the end leave; the rest store their records
+    // with one cooperative scatter (lanes past the end store nothing)
+    if (i - int64_t(threadIdx.x % kSlice) >= iend) return;
     if (failed(P)) return;
-    constexpr int NC = D + 2;
+    constexpr int NC = D + 2, NCH = kDiagChunks<D>;
+    const bool valid = i < iend;
+    const int64_t ii = valid ? i : 0;
     double u[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) u[k] = U[i * NC + k];
+    for (int k = 0; k < NC; ++k) u[k] = U[ii * NC + k];
     const double g = P.gamma;
     const double eps = internal_energy<D>(u);
-    const double p = pressure<D>(u, g);
-    const double c = speed_of_sound<D>(u, g);
-    const double er = harten_entropy<D>(u, g) / u[0];
-    const double phi = specific_entropy<D>(u, g);
-    double *A = P.packA + i * kPack;
+    double A[2 * NCH];
 #pragma unroll
     for (int k = 0; k < NC; ++k) A[k] = u[k];
-    A[NC + 0] = p;
-    A[NC + 1] = c;
-    A[NC + 2] = er;
+    A[NC + 0] = pressure<D>(u, g);
+    A[NC + 1] = speed_of_sound<D>(u, g);
+    A[NC + 2] = harten_entropy<D>(u, g) / u[0];
 #pragma unroll
     for (int k = 0; k < D; ++k) A[NC + 3 + k] = u[1 + k] / u[0];
-    A[NC + 3 + D] = phi;
-    if (check) {
+    A[NC + 3 + D] = specific_entropy<D>(u, g);
+#pragma unroll
+    for (int k = NC + 4 + D; k < 2 * NCH; ++k) A[k] = 0.0;
+    scatter<NCH>(P.packA, kPack, valid ? int(i) : -1, lw, A);
+    if (check && valid) {
         bool ok = u[0] > 0.0 && eps > 0.0;
 #pragma unroll
         for (int k = 0; k < NC; ++k) ok = ok && isfinite(u[k]);
@@ -670,7 +673,8 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_node(StageArgs P, const double *__restrict__ U,
                                                  int check)
 {
-    node_sweep<D>(P, int64_t(blockIdx.x) * kBlock + threadIdx.x, P.n, U, check);
+    WAVE_LDS(kDiagChunks<D>)
+    node_sweep<D>(P, int64_t(blockIdx.x) * kBlock + threadIdx.x, P.n, U, check, lw);
 }
 
 template <int D>
@@ -883,7 +887,7 @@ __global__ void __launch_bounds__(kBlock) k_persistent(StageArgs P, BatchArgs B)
             const int64_t sl = first + u;                               // slice
             switch (s) {
             case 0: node_sweep<D>(P, lin, e0, stage == 0 ? B.U : B.U1,
-                                  stage == 0 ? B.check : 0); break;
+                                  stage == 0 ? B.check : 0, lw); break;
             case 1: dpair_sweep<D>(P, lin, e1, lw); break;
             case 2:
                 diag_sweep<D>(P, sl, e2, 1, B.taumin2 + (sg & 1) * P.ninst,
