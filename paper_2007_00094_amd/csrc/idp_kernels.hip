@@ -685,7 +685,7 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
 }
 
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_diag(StageArgs P, int with_alpha)
+__global__ void __launch_bounds__(kBlock, 4) k_diag(StageArgs P, int with_alpha)
 {
     WAVE_LDS((D + 6 + D) / 2)
     diag_sweep<D>(P, ROW_SLICE(P), P.nslices, with_alpha, P.taumin,
