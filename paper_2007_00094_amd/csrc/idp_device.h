@@ -201,6 +201,46 @@ __host__ __device__ inline GasC make_gas(double g)
     return G;
 }
 
+// psi_branch(rho_i, p_i, c_i, p_max) + psi_branch(rho_j, p_j, c_j, p_max),
+// p_max = max(p_i, p_j): the same for both orientations of a pair (the sum
+// commutes), so a pair evaluates it once.
+template <int D>
+__device__ __forceinline__ double psi_sum(double rhoi, double pi, double ci, double rhoj,
+                                          double pj, double cj, const GasC &G)
+{
+    const double pmax = pi > pj ? pi : pj;
+    return psi_branch<D>(rhoi, pi, ci, pmax, G.g) + psi_branch<D>(rhoj, pj, cj, pmax, G.g);
+}
+
+// lambda_max with the two states' psi_branch sum S given.
+template <int D>
+__device__ __forceinline__ double lambda_max_s(const double *n, const double *Ui, double pi,
+                                               double ci, const double *Uj, double pj,
+                                               double cj, double S, const GasC &G)
+{
+    double mti = 0.0, mtj = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) mti += n[k] * Ui[1 + k];
+#pragma unroll
+    for (int k = 0; k < D; ++k) mtj += n[k] * Uj[1 + k];
+    const double ui = mti / Ui[0];
+    const double uj = mtj / Uj[0];
+    const double num = ci + cj - G.half_gm1 * (uj - ui);
+    const double den = ci * fpow(pi / pj, G.e_den) + cj;
+    const double ptilde = pj * fpow(pos_part(num) / den, G.e_p);
+    const double pmax = pi > pj ? pi : pj;
+    const double psi = S + uj - ui;
+    double pstar;
+    if (psi < 0.0)
+        pstar = ptilde;
+    else
+        pstar = pmax < ptilde ? pmax : ptilde;
+    const double lam1 = ui - ci * sqrt(1.0 + G.f * pos_part((pstar - pi) / pi));
+    const double lam3 = uj + cj * sqrt(1.0 + G.f * pos_part((pstar - pj) / pj));
+    const double a = neg_part(lam1), b = pos_part(lam3);
+    return a > b ? a : b;
+}
+
 template <int D>
 __device__ __forceinline__ double lambda_max(const double *n, const double *Ui,
                                              double pi, double ci, const double *Uj,

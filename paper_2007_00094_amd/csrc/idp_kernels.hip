@@ -281,19 +281,23 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
     aij = sqrt(aij);
     aji = sqrt(aji);
     double t1 = 0.0, t2 = 0.0;
+    // the psi_branch terms of the two states serve both orientations
+    const double S = (aij > 0.0 || aji > 0.0)
+                         ? psi_sum<D>(Ai[0], Ai[NC], Ai[NC + 1], Aj[0], Aj[NC], Aj[NC + 1], P.gas)
+                         : 0.0;
     if (aij > 0.0) {
         const double inv = 1.0 / aij;
         double nn[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) nn[q] = c[q] * inv;
-        t1 = lambda_max<D>(nn, Ai, Ai[NC], Ai[NC + 1], Aj, Aj[NC], Aj[NC + 1], P.gas) * aij;
+        t1 = lambda_max_s<D>(nn, Ai, Ai[NC], Ai[NC + 1], Aj, Aj[NC], Aj[NC + 1], S, P.gas) * aij;
     }
     if (aji > 0.0) {
         const double inv = 1.0 / aji;
         double nn[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) nn[q] = ct[q] * inv;
-        t2 = lambda_max<D>(nn, Aj, Aj[NC], Aj[NC + 1], Ai, Ai[NC], Ai[NC + 1], P.gas) * aji;
+        t2 = lambda_max_s<D>(nn, Aj, Aj[NC], Aj[NC + 1], Ai, Ai[NC], Ai[NC + 1], S, P.gas) * aji;
     }
     const double dd = t1 > t2 ? t1 : t2;
     P.d[e] = dd;
