@@ -230,6 +230,8 @@ def main():
                     help="run only that measurement and print its object (for profiling)")
     ap.add_argument("--no-staging", action="store_true",
                     help="row sweeps gather from memory instead of staging in LDS")
+    ap.add_argument("--sell-sigma", type=int, default=64,
+                    help="SELL-C-sigma sorting window in rows (multiple of 64; 0: all rows)")
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--cpu-radius", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=12)
@@ -269,7 +271,7 @@ def main():
     log(f"mesh {mesh.n_nodes} nodes, {mesh.n_cells} cells in {time.perf_counter() - t:.1f} s")
     t = time.perf_counter()
     s = Solver(mesh, asynchronous=True, newton_max=args.newton_max,
-               staging=not args.no_staging)
+               staging=not args.no_staging, sell_sigma=args.sell_sigma)
     torch.cuda.synchronize()
     log(f"solver created: nnz {s.nnz}, {s.device_bytes / 2**30:.1f} GiB device, "
         f"{time.perf_counter() - t:.1f} s")
@@ -353,6 +355,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"mach3_3d_{args.n}^3_{args.order}",
                    "newton_max_iter": args.newton_max, "lds_staging": not args.no_staging,
+                   "sell_sigma": args.sell_sigma,
                    "nodes": mesh.n_nodes, "nnz": s.nnz, "stages": stages,
                    "parallelism": "single GPU"},
         "roofline": roofline,

@@ -62,7 +62,11 @@ extern "C" {
  * (Section 3.5 asks for at least two); newton_max_iter, newton_tol: the
  * iteration cap and the tolerance TOL of Alg. 2 (the paper gives no
  * values; defaults 2 and 1e-10); relax_bounds must be 0 (the relaxation
- * of the remark in Section 3.9 is not part of this build).              */
+ * of the remark in Section 3.9 is not part of this build).  sell_sigma:
+ * the sorting window sigma of the SELL-C-sigma row layout (Section 4.3;
+ * C = 64): rows are sorted by length, longest first and stable, within
+ * consecutive windows of sell_sigma rows (a positive multiple of 64), or
+ * across all rows (0, the default).  Results do not depend on it.       */
 typedef struct {
     int dim;
     double gamma;
@@ -72,12 +76,14 @@ typedef struct {
     double newton_tol;
     int relax_bounds;
     int flags;
+    int sell_sigma;
 } idp_params;
 
 typedef struct idp_ctx idp_ctx;
 
 /* Fill p with the defaults for dimension dim (gamma 1.4, cfl 0.5, two
- * passes, 2 Newton steps, TOL 1e-10, no relaxation, synchronous).
+ * passes, 2 Newton steps, TOL 1e-10, no relaxation, synchronous, rows
+ * sorted across the whole mesh).
  * Returns IDP_EINVAL if dim is not 2 or 3.                               */
 int idp_default_params(idp_params *p, int dim);
 

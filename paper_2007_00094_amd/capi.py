@@ -42,7 +42,7 @@ class idp_params(C.Structure):
     _fields_ = [("dim", C.c_int), ("gamma", C.c_double), ("cfl", C.c_double),
                 ("limiter_passes", C.c_int), ("newton_max_iter", C.c_int),
                 ("newton_tol", C.c_double), ("relax_bounds", C.c_int),
-                ("flags", C.c_int)]
+                ("flags", C.c_int), ("sell_sigma", C.c_int)]
 
 
 class idp_schedule(C.Structure):

@@ -9,7 +9,7 @@
 namespace idp {
 
 static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
-                 const int64_t *cells)
+                 const int64_t *cells, int sigma)
 {
     const int nv = 1 << dim;
     g.dim = dim;
@@ -90,23 +90,28 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
         }
     if (bad) return IDP_EINVAL;
 
-    // SELL-64: rows by length, longest first, stable in node id
+    // SELL-64: rows by length, longest first, stable in node id, within
+    // windows of sigma rows (all rows if sigma = 0)
     g.nslices = (n + kSellC - 1) / kSellC;
     const int64_t nrows = g.nslices * kSellC;
     g.perm.assign(nrows, -1);
     g.row_len.assign(nrows, 0);
     g.diag_k.assign(nrows, 0);
     {
-        std::vector<int64_t> cnt(maxlen + 2, 0);
-        for (int64_t i = 0; i < n; ++i) cnt[g.row_ptr[i + 1] - g.row_ptr[i]]++;
-        std::vector<int64_t> start(maxlen + 2, 0);
-        int64_t acc = 0;
-        for (int L = maxlen; L >= 0; --L) { start[L] = acc; acc += cnt[L]; }
-        for (int64_t i = 0; i < n; ++i) {
-            const int L = int(g.row_ptr[i + 1] - g.row_ptr[i]);
-            const int64_t r = start[L]++;
-            g.perm[r] = int32_t(i);
-            g.row_len[r] = L;
+        const int64_t win = sigma > 0 ? int64_t(sigma) : (n > 0 ? n : 1);
+        std::vector<int64_t> cnt(maxlen + 2), start(maxlen + 2);
+        for (int64_t w0 = 0; w0 < n; w0 += win) {
+            const int64_t w1 = w0 + win < n ? w0 + win : n;
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int64_t i = w0; i < w1; ++i) cnt[g.row_ptr[i + 1] - g.row_ptr[i]]++;
+            int64_t acc = w0;
+            for (int L = maxlen; L >= 0; --L) { start[L] = acc; acc += cnt[L]; }
+            for (int64_t i = w0; i < w1; ++i) {
+                const int L = int(g.row_ptr[i + 1] - g.row_ptr[i]);
+                const int64_t r = start[L]++;
+                g.perm[r] = int32_t(i);
+                g.row_len[r] = L;
+            }
         }
     }
     g.slice_w.resize(g.nslices);
@@ -195,10 +200,10 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
 }
 
 int build_graph(HostGraph &g, int dim, int64_t n, int64_t ncells,
-                const int64_t *cells)
+                const int64_t *cells, int sigma)
 {
     try {
-        return build(g, dim, n, ncells, cells);
+        return build(g, dim, n, ncells, cells, sigma);
     } catch (const std::bad_alloc &) {
         return IDP_ENOMEM;
     }

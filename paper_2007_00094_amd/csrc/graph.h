@@ -3,9 +3,9 @@
 // The stencil I(i) (Section 3.1) is the set of nodes that share a cell with
 // node i, i included.  Rows are kept in CSR with ascending columns; for the
 // device the rows are additionally packed as SELL-C-sigma with C = 64 (one
-// wavefront lane per row) and sigma = all rows: rows sorted by length,
-// longest first, stable in node id, so that the slices of full-stencil
-// interior rows carry no padding (the paper's SELL-C-sigma layout, Section
+// wavefront lane per row) and sigma = all rows by default: rows sorted by
+// length, longest first, stable in node id, so that the slices of
+// full-stencil interior rows carry no padding (the paper's SELL-C-sigma layout, Section
 // 4.3, with the slice height set to the wavefront width instead of the
 // SIMD width).  Entry k of the row in lane l of slice s sits at
 // slice_off[s] + 64 k + l.
@@ -52,9 +52,10 @@ struct HostGraph {
 };
 
 // Returns 0 or a negative idp error code (IDP_EINVAL for ids out of range,
-// IDP_ENOMEM).  cells is [ncells][2^dim] (int64 node ids).
+// IDP_ENOMEM).  cells is [ncells][2^dim] (int64 node ids).  Rows are sorted
+// by length within windows of sigma rows (a multiple of 64; 0: all rows).
 int build_graph(HostGraph &g, int dim, int64_t n, int64_t ncells,
-                const int64_t *cells);
+                const int64_t *cells, int sigma = 0);
 
 // Neighbourhoods of row blocks, for staging in LDS.  Block b holds the rows
 // of slices 4b .. 4b+3; its halo is the ascending set of the columns of

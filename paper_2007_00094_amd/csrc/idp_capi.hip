@@ -246,6 +246,7 @@ int idp_default_params(idp_params *p, int dim)
     p->newton_tol = 1e-10;
     p->relax_bounds = 0;
     p->flags = 0;
+    p->sell_sigma = 0;
     return IDP_OK;
 }
 
@@ -278,7 +279,8 @@ int check_params(const idp_params &p)
 {
     if ((p.dim != 2 && p.dim != 3) || !(p.gamma > 1.0) || !(p.cfl > 0.0) ||
         !(p.cfl <= 1.0) || (p.limiter_passes != 1 && p.limiter_passes != 2) ||
-        p.newton_max_iter < 0 || p.newton_max_iter > 64 || !(p.newton_tol >= 0.0))
+        p.newton_max_iter < 0 || p.newton_max_iter > 64 || !(p.newton_tol >= 0.0) ||
+        p.sell_sigma < 0 || p.sell_sigma % idp::kSellC != 0)
         return IDP_EINVAL;
     if (p.relax_bounds) return IDP_ENOTSUP;
     return IDP_OK;
@@ -310,7 +312,7 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
     int rc = IDP_OK;
     try {
         if (K == 1) {
-            rc = idp::build_graph(g, dim, meshes[0].n_nodes, n_cells, cells);
+            rc = idp::build_graph(g, dim, meshes[0].n_nodes, n_cells, cells, p.sell_sigma);
             auto &L = c->lay;
             L.node = {0, g.n};
             L.cell = {0, g.ncells};
@@ -322,7 +324,7 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
             std::vector<idp::HostGraph> parts(K);
             for (int k = 0; k < K && rc == IDP_OK; ++k)
                 rc = idp::build_graph(parts[k], dim, meshes[k].n_nodes, meshes[k].n_cells,
-                                      meshes[k].cells);
+                                      meshes[k].cells, p.sell_sigma);
             if (rc == IDP_OK) rc = idp::concat_graphs(parts, g, c->lay);
             if (rc == IDP_OK) {
                 const auto &L = c->lay;

@@ -24,7 +24,8 @@ def _require_torch_gpu():
 class Solver:
     def __init__(self, mesh=None, *, dim=None, coords=None, cells=None,
                  dirichlet=None, gamma=1.4, cfl=0.5, passes=2, newton_max=2,
-                 newton_tol=1e-10, asynchronous=False, stream=None, staging=True):
+                 newton_tol=1e-10, asynchronous=False, stream=None, staging=True,
+                 sell_sigma=0):
         torch = _require_torch_gpu()
         if mesh is not None:
             dim, coords, cells = mesh.dim, mesh.coords, mesh.cells
@@ -43,6 +44,7 @@ class Solver:
         p.newton_tol = float(newton_tol)
         p.flags = (capi.IDP_FLAG_ASYNC if asynchronous else 0) | \
             (0 if staging else capi.IDP_FLAG_NO_STAGING)
+        p.sell_sigma = int(sell_sigma)
         self.params = p
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         hd = None
@@ -200,7 +202,7 @@ class BatchSolver:
     """
 
     def __init__(self, meshes, *, dirichlet=None, gamma=1.4, cfl=0.5, passes=2,
-                 newton_max=2, newton_tol=1e-10, stream=None, staging=True):
+                 newton_max=2, newton_tol=1e-10, stream=None, staging=True, sell_sigma=0):
         torch = _require_torch_gpu()
         meshes = list(meshes)
         if not meshes:
@@ -217,6 +219,7 @@ class BatchSolver:
         p.limiter_passes, p.newton_max_iter = int(passes), int(newton_max)
         p.newton_tol = float(newton_tol)
         p.flags = 0 if staging else capi.IDP_FLAG_NO_STAGING
+        p.sell_sigma = int(sell_sigma)
         self.params = p
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         K = self.count

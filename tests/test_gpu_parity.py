@@ -209,6 +209,26 @@ def test_lds_staging_is_bitwise_the_gather_path(torch, oracle_mod, name, dim, n,
     assert np.array_equal(outs[0], V)
 
 
+@pytest.mark.parametrize("dim,n,sigma", [(3, 33, 64), (3, 17, 256), (2, 65, 64)])
+def test_sell_window_is_bitwise(torch, oracle_mod, dim, n, sigma):
+    """Rows sorted by length within windows of sigma rows (SELL-C-sigma of
+    Section 4.3) instead of across the mesh: same bits as the oracle."""
+    announce(f"SELL window sigma={sigma}: dim={dim} n={n} Morton")
+    from paper_2007_00094_amd.solver import Solver
+    mesh = inputs.q1_grid(n, dim, 0.2, seed=0, order="morton")
+    U0 = inputs.ic_four_quadrant(mesh.coords) if dim == 2 else inputs.ic_mach3_blobs(mesh.coords)
+    s = Solver(mesh, sell_sigma=sigma)
+    U = torch.tensor(U0, device="cuda")
+    o = oracle_mod.Oracle(mesh, dirichlet=mesh.boundary)
+    V = U0.copy()
+    for _ in range(3):
+        s.step(U)
+        V, _, st = o.step(V)
+        assert st == 0
+    assert np.array_equal(U.cpu().numpy(), V)
+    s.close()
+
+
 def test_determinism(torch):
     announce("determinism: two runs, sphere 3D 13^3")
     mesh = inputs.q1_grid(13, 3, 0.2, seed=0, order="random")
