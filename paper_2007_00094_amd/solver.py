@@ -301,3 +301,39 @@ class BatchSolver:
             C.byref(nc)))
         names = ["launches"] + [f"persistent_tile{t}" for t in (4, 16, 32, 64, 128, 256)]
         return best, {names[i]: float(ms[i]) for i in range(nc.value)}
+
+
+def tune_layout(mesh, U0, steps: int = 2, sigmas=(0, 64), staging=(True, False), **kw):
+    """Layout autotuner for one mesh: times `steps` SSP-RK3 steps from U0
+    (host array) under every combination of the SELL sorting window
+    (`sell_sigma`) and the LDS staging of the row sweeps, each in a fresh
+    context, and returns (the fastest combination as Solver keyword
+    arguments, {(sigma, staging): ms per step}).  Every combination must
+    give the same state bit for bit; a mismatch raises."""
+    import time
+    torch = _require_torch_gpu()
+    times, ref, best = {}, None, None
+    for sg in sigmas:
+        for st in staging:
+            s = Solver(mesh, asynchronous=True, sell_sigma=sg, staging=st, **kw)
+            U = torch.tensor(U0, device="cuda")
+            s.step(U)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                s.step(U)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            status = s.status()
+            s.close()
+            if status not in (0, 1):
+                raise RuntimeError(f"step failed under sigma={sg}, staging={st}: {status}")
+            out = U.cpu().numpy()
+            if ref is None:
+                ref = out
+            elif not np.array_equal(out, ref):
+                raise RuntimeError(f"sigma={sg}, staging={st} changed the result")
+            times[(sg, st)] = ms
+            if best is None or ms < times[best]:
+                best = (sg, st)
+    return {"sell_sigma": best[0], "staging": best[1]}, times

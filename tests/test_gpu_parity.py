@@ -294,3 +294,13 @@ def test_async_steps_and_status(torch, oracle_mod):
         Uo, _, _ = o.step(Uo)
     assert np.array_equal(U.cpu().numpy(), Uo)
     s.close()
+
+
+def test_layout_tuner_returns_a_candidate_and_candidates_agree(torch):
+    announce("layout autotuner: 3D 17^3 Morton, sigma x staging")
+    from paper_2007_00094_amd.solver import tune_layout
+    mesh = inputs.q1_grid(17, 3, 0.2, seed=0, order="morton")
+    U0 = inputs.ic_mach3_blobs(mesh.coords)
+    best, times = tune_layout(mesh, U0, steps=1)
+    assert len(times) == 4 and (best["sell_sigma"], best["staging"]) in times
+    assert all(t > 0 for t in times.values())
