@@ -463,22 +463,22 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
     constexpr int NC = D + 2;
     using CH = Chunks<D>;
     const double dL = P.dp[pq_], m = P.mp[pq_];
-    NodeB<D> Bi, Bj;
-    double Wi[2 * CH::rowB], Wj[2 * CH::rowB];
-    gather_b<D>(P.packB, i, lw, Bi);
-    gather_b<D>(P.packB, j, lw, Bj);
-    gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
-    gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
+    // both directions first, so that the node packs are dead before the
+    // rows' bounds are gathered, one side at a time
+    double Pij[NC], Pji[NC];
+    {
+        NodeB<D> Bi, Bj;
+        gather_b<D>(P.packB, i, lw, Bi);
+        gather_b<D>(P.packB, j, lw, Bj);
+        direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
+        direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
+    }
+    double W[2 * CH::rowB];
+    gather<CH::rowB>(P.rowB, kRowB, i, lw, W);
+    const double lij = valid_ ? row_limiter<D>(W, W, Pij, P) : 0.0;
+    gather<CH::rowB>(P.rowB, kRowB, j, lw, W);
     if (!valid_) return;
-    double Pd[NC], U[NC];
-    direction<D>(Bi, Bj, Bi.coef, dL, m, Pd);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) U[r] = Wi[r];
-    const double lij = row_limiter<D>(U, Wi, Pd, P);
-    direction<D>(Bj, Bi, Bj.coef, dL, m, Pd);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) U[r] = Wj[r];
-    const double lji = row_limiter<D>(U, Wj, Pd, P);
+    const double lji = row_limiter<D>(W, W, Pji, P);
     const double sv = lij < lji ? lij : lji;
     P.l1[e] = sv;
     P.l1[t] = sv;
@@ -559,25 +559,33 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
     using CH = Chunks<D>;
     const double dL = P.dp[pq_], m = P.mp[pq_];
     const double l = P.l1p[pq_];
-    NodeB<D> Bi, Bj;
-    double Wi[2 * CH::rowB], Wj[2 * CH::rowB];
-    double Ui[2 * CH::upass], Uj[2 * CH::upass];
-    gather_b<D>(P.packB, i, lw, Bi);
-    gather_b<D>(P.packB, j, lw, Bj);
-    gather<CH::rowB>(P.rowB, kRowB, i, lw, Wi);
-    gather<CH::rowB>(P.rowB, kRowB, j, lw, Wj);
-    gather<CH::upass>(P.upass, kRowU, i, lw, Ui);
-    gather<CH::upass>(P.upass, kRowU, j, lw, Uj);
+    double Pij[NC], Pji[NC];
+    {
+        NodeB<D> Bi, Bj;
+        gather_b<D>(P.packB, i, lw, Bi);
+        gather_b<D>(P.packB, j, lw, Bj);
+        direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
+        direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
+    }
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        Pij[r] = (1.0 - l) * Pij[r];
+        Pji[r] = (1.0 - l) * Pji[r];
+    }
+    // per side: the pass-1 state and the two chunks of the row record that
+    // hold the bounds (slots NC .. NC + 2 of U^L, bounds)
+    constexpr int B0 = 2 * (NC / 2), BO = NC - B0;
+    double U[2 * CH::upass], Wb[4];
+    gather<CH::upass>(P.upass, kRowU, i, lw, U);
+    gather<2>(P.rowB + B0, kRowB, i, lw, Wb);
+    const double lij = valid_ ? limiter<D>(U, Pij, Wb[BO], Wb[BO + 1], Wb[BO + 2], P.gamma,
+                                           P.newton_max, P.tol)
+                              : 0.0;
+    gather<CH::upass>(P.upass, kRowU, j, lw, U);
+    gather<2>(P.rowB + B0, kRowB, j, lw, Wb);
     if (!valid_) return;
-    double Pd[NC], U[NC];
-    direction<D>(Bi, Bj, Bi.coef, dL, m, Pd);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) { Pd[r] = (1.0 - l) * Pd[r]; U[r] = Ui[r]; }
-    const double lij = row_limiter<D>(U, Wi, Pd, P);
-    direction<D>(Bj, Bi, Bj.coef, dL, m, Pd);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) { Pd[r] = (1.0 - l) * Pd[r]; U[r] = Uj[r]; }
-    const double lji = row_limiter<D>(U, Wj, Pd, P);
+    const double lji = limiter<D>(U, Pji, Wb[BO], Wb[BO + 1], Wb[BO + 2], P.gamma,
+                                  P.newton_max, P.tol);
     const double sv = lij < lji ? lij : lji;
     P.l2[e] = sv;
     P.l2[t] = sv;
