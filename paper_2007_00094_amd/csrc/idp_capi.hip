@@ -403,6 +403,7 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
     TRY(dalloc(c, &P.mi, g.n));
     TRY(dalloc(c, &P.lam, g.n));
     TRY(dalloc(c, &P.packA, g.n * idp::kPack));
+    TRY(dalloc(c, &P.packL, g.n * idp::kPackL));
     TRY(dalloc(c, &P.packB, g.n * idp::kPack));
     TRY(dalloc(c, &P.rowB, g.n * idp::kRowB));
     TRY(dalloc(c, &P.upass, g.n * idp::kRowU));

@@ -224,7 +224,7 @@ __device__ __forceinline__ void node_sweep(const StageArgs &P, int64_t i, int64_
     // with one cooperative scatter (lanes past the end store nothing)
     if (i - int64_t(threadIdx.x % kSlice) >= iend) return;
     if (failed(P)) return;
-    constexpr int NC = D + 2, NCH = kDiagChunks<D>;
+    constexpr int NC = D + 2, NCH = kPackAChunks<D>;
     const bool valid = i < iend;
     const int64_t ii = valid ? i : 0;
     double u[NC];
@@ -244,6 +244,15 @@ __device__ __forceinline__ void node_sweep(const StageArgs &P, int64_t i, int64_
 #pragma unroll
     for (int k = NC + 4 + D; k < 2 * NCH; ++k) A[k] = 0.0;
     scatter<NCH>(P.packA, kPack, valid ? int(i) : -1, lw, A);
+    // the low-order sweep's record: U, p, phi (alpha follows from k_diag)
+    double L[kPackL];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) L[k] = u[k];
+    L[NC] = A[NC];
+    L[NC + 1] = A[NC + 3 + D];
+#pragma unroll
+    for (int k = NC + 2; k < kPackL; ++k) L[k] = 0.0;
+    scatter<kPackL / 2>(P.packL, kPackL, valid ? int(i) : -1, lw, L);
     if (check && valid) {
         bool ok = u[0] > 0.0 && eps > 0.0;
 #pragma unroll
@@ -342,8 +351,14 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
             double rec[2 * NCH];
             fetch(fetch.token(e), in ? j : -1, rec);
             if (!in) continue;
+            // U, p, c, eta/rho; v = m/rho exactly as the node pass has it
             NodeA<D> Aj;
-            unpack_a<D>(rec, Aj);
+#pragma unroll
+            for (int r = 0; r < NC; ++r) Aj.U[r] = rec[r];
+            Aj.p = rec[NC];
+            Aj.er = rec[NC + 2];
+#pragma unroll
+            for (int q = 0; q < D; ++q) Aj.v[q] = Aj.U[1 + q] / Aj.U[0];
             double mc = 0.0;
 #pragma unroll
             for (int q = 0; q < D; ++q) mc += Aj.U[1 + q] * c[q];
@@ -373,15 +388,18 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
         for (int r = 0; r < NC; ++r) Dn += fabs(etap[r] - (r == 0 ? Ai.er : 0.0)) * fabs(b[r]);
         const double al = Dn > 0.0 ? N / Dn : 0.0;
         P.alpha[i] = al;
-        P.packA[int64_t(i) * kPack + kPackAlpha] = al;
+        P.packL[int64_t(i) * kPackL + kPackLAlpha] = al;
+        // pack A's copy is read only by the stage adjoint, which runs on
+        // stages recomputed with their records kept
+        if (P.argk) P.packA[int64_t(i) * kPack + kPackAlpha] = al;
     }
 }
 
 // ------------------------------------------------------ row low order
-// Step 3.  In 3D its per-entry arithmetic (two fluxes, a division) hides
-// the latency of plain per-lane record loads better than a cooperative
-// gather or LDS staging; in 2D (half the arithmetic per entry) the
-// neighbours come from LDS, or from a cooperative gather.
+// Step 3.  The neighbours' records (pack L, 64 bytes) come from the row
+// block's LDS staging, else from per-lane loads (3D: its per-entry
+// arithmetic hides them better than a cooperative gather) or a cooperative
+// gather (2D).
 template <int D, class F>
 __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int64_t send,
                                           const F &fetch)
@@ -409,13 +427,19 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
         double c[D];
         load_c<D>(P, e, c);
         const double dL = P.d[e];
-        constexpr int NCH = kLowChunks<D>;   // pack A to phi, and alpha's chunk
-        double rec[2 * NCH];
+        // the neighbour's record U, p, phi, alpha (pack L); v = m/rho is
+        // recomputed exactly as the node pass computes it
+        double rec[kPackL];
         fetch(fetch.token(e), act ? j : -1, rec);
         if (!act) continue;
         NodeA<D> Aj;
-        unpack_a<D>(rec, Aj);
-        const double alpha_j = rec[2 * (NCH - 1)];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) Aj.U[r] = rec[r];
+        Aj.p = rec[NC];
+        Aj.phi = rec[NC + 1];
+#pragma unroll
+        for (int k = 0; k < D; ++k) Aj.v[k] = Aj.U[1 + k] / Aj.U[0];
+        const double alpha_j = rec[kPackLAlpha];
         const double dH = dL * (alpha_i + alpha_j) / 2.0;
         double Fj[NC][D], fd[NC];
         flux<D>(Aj.U, Aj.v, Aj.p, Fj);
@@ -685,7 +709,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_node(StageArgs P, const double *__restrict__ U,
                                                  int check)
 {
-    WAVE_LDS(kDiagChunks<D>)
+    WAVE_LDS(kPackAChunks<D>)
     node_sweep<D>(P, int64_t(blockIdx.x) * kBlock + threadIdx.x, P.n, U, check, lw);
 }
 
@@ -699,7 +723,7 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
 template <int D>
 __global__ void __launch_bounds__(kBlock, 4) k_diag(StageArgs P, int with_alpha)
 {
-    WAVE_LDS((D + 6 + D) / 2)
+    WAVE_LDS(kDiagChunks<D>)
     diag_sweep<D>(P, ROW_SLICE(P), P.nslices, with_alpha, P.taumin,
                   GatherFetch<kDiagChunks<D>>{P.packA, lw});
 }
@@ -707,13 +731,13 @@ __global__ void __launch_bounds__(kBlock, 4) k_diag(StageArgs P, int with_alpha)
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
 {
+    constexpr int NCH = kPackL / 2;
     if constexpr (D == 3) {
-        low_sweep<D>(P, ROW_SLICE(P), P.nslices,
-                     LaneTailFetch<kLowChunks<D>, kPackAlpha / 2>{P.packA});
+        low_sweep<D>(P, ROW_SLICE(P), P.nslices, LaneTailFetch<NCH, NCH - 1, kPackL>{P.packL});
     } else {
-        WAVE_LDS(kLowChunks<D>)
+        WAVE_LDS(NCH)
         low_sweep<D>(P, ROW_SLICE(P), P.nslices,
-                     GatherTailFetch<kLowChunks<D>, kPackAlpha / 2>{P.packA, lw});
+                     GatherTailFetch<NCH, NCH - 1, kPackL>{P.packL, lw});
     }
 }
 
@@ -729,10 +753,11 @@ struct LowFetch {
     }
     __device__ __forceinline__ void operator()(int tok, int node, double *rec) const
     {
+        constexpr int NCH = kPackL / 2;
         if constexpr (D == 3)
-            LaneTailFetch<kLowChunks<D>, kPackAlpha / 2>{base}(tok, node, rec);
+            LaneTailFetch<NCH, NCH - 1, kPackL>{base}(tok, node, rec);
         else
-            GatherTailFetch<kLowChunks<D>, kPackAlpha / 2>{base, lw}(tok, node, rec);
+            GatherTailFetch<NCH, NCH - 1, kPackL>{base, lw}(tok, node, rec);
     }
 };
 
@@ -773,14 +798,14 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
 // Staged: the two passes, and in 2D the low-order sweep.  The diagonal
 // sweep measured slower staged in both dimensions (3D 7.8 vs 5.7 ms at
 // 257^3, 2D 0.77 vs 0.58 ms on the 64-mesh batch) and keeps the gathers.
-#define HALO_SWEEP(NCH, LAST, BASE, CALL)                                    \
+#define HALO_SWEEP(NCH, LAST, STRIDE, BASE, CALL)                            \
     __shared__ double2 sh_[kHaloMaxD<D> * (NCH)];                            \
     const int64_t hb_ = logical_block(P.per);                                \
-    if (stage_halo<NCH, LAST>(P, hb_, BASE, sh_)) {                          \
+    if (stage_halo<NCH, LAST, STRIDE>(P, hb_, BASE, sh_)) {                  \
         const HaloFetch<NCH> f_{sh_, P.loc};                                 \
         CALL;                                                                \
     } else {                                                                 \
-        const GatherTailFetch<NCH, LAST> f_{BASE,                            \
+        const GatherTailFetch<NCH, LAST, STRIDE> f_{BASE,                    \
                                             sh_ + (threadIdx.x / kSlice) * (NCH) * kLdsRow}; \
         CALL;                                                                \
     }
@@ -789,7 +814,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_pass1a_h(StageArgs P)
 {
     constexpr int NCH = Chunks<D>::packBrow;
-    HALO_SWEEP(NCH, NCH - 1, P.packB, pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, f_))
+    HALO_SWEEP(NCH, NCH - 1, kPack, P.packB, pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, f_))
 }
 
 template <int D>
@@ -797,15 +822,15 @@ __global__ void __launch_bounds__(kBlock) k_pass2_h(StageArgs P, const double *U
                                                     int mode)
 {
     constexpr int NCH = Chunks<D>::packBrow;
-    HALO_SWEEP(NCH, NCH - 1, P.packB,
+    HALO_SWEEP(NCH, NCH - 1, kPack, P.packB,
                pass2_sweep<D>(P, ROW_SLICE(P), P.nslices, U0, out, mode, f_))
 }
 
-// staged low-order sweep: launched for 2D meshes only
+// staged low-order sweep
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_low_h(StageArgs P)
 {
-    HALO_SWEEP(kLowChunks<D>, kPackAlpha / 2, P.packA,
+    HALO_SWEEP(kPackL / 2, kPackL / 2 - 1, kPackL, P.packL,
                low_sweep<D>(P, ROW_SLICE(P), P.nslices, f_))
 }
 
@@ -905,7 +930,7 @@ __global__ void __launch_bounds__(kBlock) k_persistent(StageArgs P, BatchArgs B)
                 diag_sweep<D>(P, sl, e2, 1, B.taumin2 + (sg & 1) * P.ninst,
                               GatherFetch<kDiagChunks<D>>{P.packA, lw});
                 break;
-            case 3: low_sweep<D>(P, sl, e2, LowFetch<D>{P.packA, lw}); break;
+            case 3: low_sweep<D>(P, sl, e2, LowFetch<D>{P.packL, lw}); break;
             case 4: lim1_sweep<D>(P, lin, e1, lw); break;
             case 5:
                 pass1_sweep<D>(P, sl, e2, GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
@@ -1003,8 +1028,8 @@ void launch_diag(const StageArgs &P, hipStream_t st, int with_alpha)
 }
 void launch_low(const StageArgs &P, hipStream_t st)
 {
-    if (P.halo_cnt && P.dim == 2)
-        hipLaunchKernelGGL(k_low_h<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    if (P.halo_cnt)
+        LAUNCH_D(k_low_h, grid_rows(P), P);
     else
         LAUNCH_D(k_low, grid_rows(P), P);
 }

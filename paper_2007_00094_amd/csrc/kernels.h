@@ -17,6 +17,9 @@ constexpr int kPackAlpha = 12;  // pack A slot of alpha_i (written by k_diag)
 constexpr int kPackCoef = 12;   // pack B slot of tau/(lambda_i m_i)
 constexpr int kRowB = 8;      // doubles per node: U^L (nc), bounds (3)
 constexpr int kRowU = 8;      // doubles per node: state after pass 1
+constexpr int kPackL = 8;     // doubles per node: the low-order sweep's neighbour
+                              // record U (nc), p, phi, alpha [kPackLAlpha]
+constexpr int kPackLAlpha = 7;
 // records of a row block's neighbourhood staged in LDS (3D: about 700 at
 // Morton order, 2D: about 350), at most 6 chunks each (75 KB, 48 KB)
 constexpr int kHaloMax3 = 800;
@@ -58,6 +61,7 @@ struct StageArgs {
     double *d;                  // [sell] d_ij, diagonal d_ii
     double *l1, *l2;            // [sell] min(l_ij, l_ji) of pass 1, 2
     double *packA, *alpha, *packB, *rowB, *upass, *taui;
+    double *packL;              // [n][kPackL]
     // records for the stage adjoint (null: not kept): which orientation
     // set d_ij = max(...) (1: i -> j), which side of a pair set min(l_ij,
     // l_ji) (1: the row of pair_i) per limiter pass; and per node the row

@@ -169,10 +169,10 @@ __device__ __forceinline__ void scatter(double *__restrict__ base, int stride, i
     __builtin_amdgcn_wave_barrier();
 }
 
-// chunks of pack A a diagonal sweep reads: U, p, c, eta/rho, v, phi; the
-// low-order sweep reads the same and alpha's chunk
-template <int D> constexpr int kDiagChunks = (D + 2 + 4 + D) / 2;
-template <int D> constexpr int kLowChunks = kDiagChunks<D> + 1;
+// chunks of pack A as the node pass writes it: U, p, c, eta/rho, v, phi;
+// the diagonal sweep reads U, p, c, eta/rho (and recomputes v = m/rho)
+template <int D> constexpr int kPackAChunks = (D + 2 + 4 + D) / 2;
+template <int D> constexpr int kDiagChunks = (D + 2 + 3 + 1) / 2;
 
 // Where a row sweep takes its neighbours' records from.  GatherFetch: the
 // wavefront's cooperative gather from global memory (every lane of the
@@ -215,10 +215,10 @@ struct HaloFetch {
 };
 
 // LDS staging of a row block's neighbourhood: the first NCH chunks of the
-// record (stride kPack) of every node in the block's halo, in halo order.
+// record (STRIDE doubles per node) of every node in the block's halo, in halo order.
 // Every thread of the block calls it (it ends in a block barrier); false
 // if the block's halo did not fit (its rows then gather from memory).
-template <int NCH, int LAST = NCH - 1>
+template <int NCH, int LAST = NCH - 1, int STRIDE = kPack>
 __device__ __forceinline__ bool stage_halo(const StageArgs &P, int64_t b, const double *base,
                                            double2 *halo)
 {
@@ -232,7 +232,7 @@ __device__ __forceinline__ bool stage_halo(const StageArgs &P, int64_t b, const 
         const int r = q / NCH, c = q - r * NCH;
         const int src = c == NCH - 1 ? LAST : c;
         halo[q] = *reinterpret_cast<const double2 *>(
-            base + int64_t(P.halo_node[h0 + r]) * kPack + 2 * src);
+            base + int64_t(P.halo_node[h0 + r]) * STRIDE + 2 * src);
     }
     __syncthreads();
     return true;
@@ -240,7 +240,7 @@ __device__ __forceinline__ bool stage_halo(const StageArgs &P, int64_t b, const 
 
 // Fetches of chunks 0 .. NCH-2 and chunk LAST of a record: per lane
 // (LaneTailFetch) or wavefront-cooperative (GatherTailFetch).
-template <int NCH, int LAST>
+template <int NCH, int LAST, int STRIDE = kPack>
 struct LaneTailFetch {
     const double *base;
     __device__ __forceinline__ int token(int64_t e) const
@@ -252,7 +252,7 @@ struct LaneTailFetch {
     {
         (void)tok;
         if (node < 0) return;
-        const double *a = base + int64_t(node) * kPack;
+        const double *a = base + int64_t(node) * STRIDE;
 #pragma unroll
         for (int k = 0; k < NCH; ++k) {
             const int src = k == NCH - 1 ? LAST : k;
@@ -262,7 +262,7 @@ struct LaneTailFetch {
     }
 };
 
-template <int NCH, int LAST>
+template <int NCH, int LAST, int STRIDE = kPack>
 struct GatherTailFetch {
     const double *base;
     double2 *lw;
@@ -274,7 +274,7 @@ struct GatherTailFetch {
     __device__ __forceinline__ void operator()(int tok, int node, double *rec) const
     {
         (void)tok;
-        gather_tail<NCH, LAST>(base, kPack, node, lw, rec);
+        gather_tail<NCH, LAST>(base, STRIDE, node, lw, rec);
     }
 };
 
