@@ -243,7 +243,12 @@ __device__ __forceinline__ void node_sweep(const StageArgs &P, int64_t i, int64_
     A[NC + 3 + D] = specific_entropy<D>(u, g);
 #pragma unroll
     for (int k = NC + 4 + D; k < 2 * NCH; ++k) A[k] = 0.0;
-    scatter<NCH>(P.packA, kPack, valid ? int(i) : -1, lw, A);
+    // the forward sweeps read pack A's first kDiagChunks chunks; v and phi
+    // only the stage adjoint, which runs on stages recomputed with records
+    if (P.argk)
+        scatter<NCH>(P.packA, kPack, valid ? int(i) : -1, lw, A);
+    else
+        scatter<kDiagChunks<D>>(P.packA, kPack, valid ? int(i) : -1, lw, A);
     // the low-order sweep's record: U, p, phi (alpha follows from k_diag)
     double L[kPackL];
 #pragma unroll
@@ -330,24 +335,24 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
     constexpr int NCH = kDiagChunks<D>;
     const double g = P.gamma;
     NodeA<D> Ai;
-    load_a<D>(P.packA + int64_t(i) * kPack, Ai);
+    load_a_fwd<D>(P.packA + int64_t(i) * kPack, Ai);
     double Fi[NC][D];
     flux<D>(Ai.U, Ai.v, Ai.p, Fi);
     double dsum = 0.0, a = 0.0;
     double b[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) b[r] = 0.0;
-    int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+    int jn = Lmax_ > 0 ? ld_stream(P.scol + ENTRY(0)) : 0;
     for (int k = 0; k < Lmax_; ++k) {
         const int64_t e = ENTRY(k);
         const int j = jn;
-        if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
+        if (k + 1 < Lmax_) jn = ld_stream(P.scol + ENTRY(k + 1));
         const bool in = k < L;
-        const double dd = P.d[e];
+        const double dd = ld_stream(P.d + e);
         if (in && j != i) dsum += dd;
         if (with_alpha) {
             double c[D];
-            load_c<D>(P, e, c);
+            load_c_stream<D>(P, e, c);
             double rec[2 * NCH];
             fetch(fetch.token(e), in ? j : -1, rec);
             if (!in) continue;
@@ -407,8 +412,17 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
     WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
     constexpr int NC = D + 2;
+    // the row's own record: U, p and phi from pack L, v recomputed
     NodeA<D> Ai;
-    load_a<D>(P.packA + int64_t(i) * kPack, Ai);
+    {
+        const double *a = P.packL + int64_t(i) * kPackL;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) Ai.U[r] = a[r];
+        Ai.p = a[NC];
+        Ai.phi = a[NC + 1];
+#pragma unroll
+        for (int k = 0; k < D; ++k) Ai.v[k] = Ai.U[1 + k] / Ai.U[0];
+    }
     const double alpha_i = P.alpha[i];
     const double tau = P.tau[inst_];
     double Fi[NC][D];
@@ -418,15 +432,15 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
     for (int r = 0; r < NC; ++r) { R[r] = 0.0; Lw[r] = 0.0; }
     double rho_min = Ai.U[0], rho_max = Ai.U[0], phi_min = Ai.phi;
     int kmn = 255, kmx = 255, kph = 255;
-    int jn = Lmax_ > 0 ? P.scol[ENTRY(0)] : 0;
+    int jn = Lmax_ > 0 ? ld_stream(P.scol + ENTRY(0)) : 0;
     for (int k = 0; k < Lmax_; ++k) {
         const int64_t e = ENTRY(k);
         const int j = jn;
-        if (k + 1 < Lmax_) jn = P.scol[ENTRY(k + 1)];
+        if (k + 1 < Lmax_) jn = ld_stream(P.scol + ENTRY(k + 1));
         const bool act = k < L && j != i;
         double c[D];
-        load_c<D>(P, e, c);
-        const double dL = P.d[e];
+        load_c_stream<D>(P, e, c);
+        const double dL = ld_stream(P.d + e);
         // the neighbour's record U, p, phi, alpha (pack L); v = m/rho is
         // recomputed exactly as the node pass computes it
         double rec[kPackL];
