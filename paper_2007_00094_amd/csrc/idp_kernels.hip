@@ -482,10 +482,18 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
     }
     B[2 * NC] = alpha_i;
     B[2 * NC + 1] = mi;
+    // the records are written whole (unused slots zero): a partly written
+    // line costs the memory a read-modify-write
+#pragma unroll
+    for (int r = 2 * NC + 2; r < kPackCoef; ++r) B[r] = 0.0;
     B[kPackCoef] = tau / (P.lam[i] * mi);   // tau/(lambda_i m_i) of eq. def-p
+#pragma unroll
+    for (int r = kPackCoef + 1; r < kPack; ++r) B[r] = 0.0;
     W[NC + 0] = rho_min;
     W[NC + 1] = rho_max;
     W[NC + 2] = phi_min;
+#pragma unroll
+    for (int r = NC + 3; r < kRowB; ++r) W[r] = 0.0;
 }
 
 // ------------------------------------------------------ pair limiter 1
@@ -579,9 +587,13 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
     }
     if (!valid_) return;
     P.l1[ENTRY(P.diag_k[r_])] = 1.0;   // the diagonal's s1 (pass 2 reads it as 1)
+    // whole 64-byte records: a partly written line costs the memory a
+    // read-modify-write
     double *Up = P.upass + int64_t(i) * kRowU;
 #pragma unroll
     for (int r = 0; r < NC; ++r) Up[r] = V[r];
+#pragma unroll
+    for (int r = NC; r < kRowU; ++r) Up[r] = 0.0;
 }
 
 // ------------------------------------------------------ pair limiter 2
