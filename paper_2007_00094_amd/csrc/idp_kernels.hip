@@ -283,8 +283,14 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
     ct[1] = P.ct1[e];
     if (D == 3) ct[D - 1] = P.ct2[e];
     double Ai[2 * NCH], Aj[2 * NCH];
-    gather<NCH>(P.packA, kPack, i, lw, Ai);
-    gather<NCH>(P.packA, kPack, j, lw, Aj);
+    {
+        // both records' loads in flight before either passes through LDS
+        dchunk vi[GatherShape<NCH>::LPR], vj[GatherShape<NCH>::LPR];
+        gather_issue<NCH>(P.packA, kPack, i, vi);
+        gather_issue<NCH>(P.packA, kPack, j, vj);
+        gather_exchange<NCH>(lw, vi, Ai);
+        gather_exchange<NCH>(lw, vj, Aj);
+    }
     if (!valid_) return;
     double aij = 0.0, aji = 0.0;
 #pragma unroll
@@ -510,21 +516,41 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
     using CH = Chunks<D>;
     const double dL = P.dp[pq_], m = P.mp[pq_];
     // both directions first, so that the node packs are dead before the
-    // rows' bounds are gathered, one side at a time
+    // rows' bounds are gathered.  2D: each phase has the loads of both rows
+    // in flight before either passes through LDS; 3D (more registers per
+    // record): one row at a time, which keeps four waves per SIMD
     double Pij[NC], Pji[NC];
     {
         NodeB<D> Bi, Bj;
-        gather_b<D>(P.packB, i, lw, Bi);
-        gather_b<D>(P.packB, j, lw, Bj);
+        if constexpr (D == 2) {
+            gather_b2<D>(P.packB, i, j, lw, Bi, Bj);
+        } else {
+            gather_b<D>(P.packB, i, lw, Bi);
+            gather_b<D>(P.packB, j, lw, Bj);
+        }
         direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
         direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
     }
-    double W[2 * CH::rowB];
-    gather<CH::rowB>(P.rowB, kRowB, i, lw, W);
-    const double lij = valid_ ? row_limiter<D>(W, W, Pij, P) : 0.0;
-    gather<CH::rowB>(P.rowB, kRowB, j, lw, W);
-    if (!valid_) return;
-    const double lji = row_limiter<D>(W, W, Pji, P);
+    constexpr int NW = CH::rowB;
+    double lij, lji;
+    if constexpr (D == 2) {
+        dchunk vi[GatherShape<NW>::LPR], vj[GatherShape<NW>::LPR];
+        gather_issue<NW>(P.rowB, kRowB, i, vi);
+        gather_issue<NW>(P.rowB, kRowB, j, vj);
+        double Wi[2 * NW], Wj[2 * NW];
+        gather_exchange<NW>(lw, vi, Wi);
+        gather_exchange<NW>(lw, vj, Wj);
+        if (!valid_) return;
+        lij = row_limiter<D>(Wi, Wi, Pij, P);
+        lji = row_limiter<D>(Wj, Wj, Pji, P);
+    } else {
+        double W[2 * NW];
+        gather<NW>(P.rowB, kRowB, i, lw, W);
+        lij = valid_ ? row_limiter<D>(W, W, Pij, P) : 0.0;
+        gather<NW>(P.rowB, kRowB, j, lw, W);
+        if (!valid_) return;
+        lji = row_limiter<D>(W, W, Pji, P);
+    }
     const double sv = lij < lji ? lij : lji;
     P.l1[e] = sv;
     P.l1[t] = sv;
@@ -612,8 +638,12 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
     double Pij[NC], Pji[NC];
     {
         NodeB<D> Bi, Bj;
-        gather_b<D>(P.packB, i, lw, Bi);
-        gather_b<D>(P.packB, j, lw, Bj);
+        if constexpr (D == 2) {
+            gather_b2<D>(P.packB, i, j, lw, Bi, Bj);
+        } else {
+            gather_b<D>(P.packB, i, lw, Bi);
+            gather_b<D>(P.packB, j, lw, Bj);
+        }
         direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
         direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
     }
@@ -623,19 +653,40 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
         Pji[r] = (1.0 - l) * Pji[r];
     }
     // per side: the pass-1 state and the two chunks of the row record that
-    // hold the bounds (slots NC .. NC + 2 of U^L, bounds)
-    constexpr int B0 = 2 * (NC / 2), BO = NC - B0;
-    double U[2 * CH::upass], Wb[4];
-    gather<CH::upass>(P.upass, kRowU, i, lw, U);
-    gather<2>(P.rowB + B0, kRowB, i, lw, Wb);
-    const double lij = valid_ ? limiter<D>(U, Pij, Wb[BO], Wb[BO + 1], Wb[BO + 2], P.gamma,
-                                           P.newton_max, P.tol)
-                              : 0.0;
-    gather<CH::upass>(P.upass, kRowU, j, lw, U);
-    gather<2>(P.rowB + B0, kRowB, j, lw, Wb);
-    if (!valid_) return;
-    const double lji = limiter<D>(U, Pji, Wb[BO], Wb[BO + 1], Wb[BO + 2], P.gamma,
-                                  P.newton_max, P.tol);
+    // hold the bounds (slots NC .. NC + 2 of U^L, bounds); in 2D the loads of
+    // both sides are in flight before the first passes through LDS
+    constexpr int B0 = 2 * (NC / 2), BO = NC - B0, NU = CH::upass;
+    double lij, lji;
+    if constexpr (D == 2) {
+        dchunk ui[GatherShape<NU>::LPR], uj[GatherShape<NU>::LPR];
+        dchunk wi[GatherShape<2>::LPR], wj[GatherShape<2>::LPR];
+        gather_issue<NU>(P.upass, kRowU, i, ui);
+        gather_issue<2>(P.rowB + B0, kRowB, i, wi);
+        gather_issue<NU>(P.upass, kRowU, j, uj);
+        gather_issue<2>(P.rowB + B0, kRowB, j, wj);
+        double Ui[2 * NU], Uj[2 * NU], Wbi[4], Wbj[4];
+        gather_exchange<NU>(lw, ui, Ui);
+        gather_exchange<2>(lw, wi, Wbi);
+        gather_exchange<NU>(lw, uj, Uj);
+        gather_exchange<2>(lw, wj, Wbj);
+        if (!valid_) return;
+        lij = limiter<D>(Ui, Pij, Wbi[BO], Wbi[BO + 1], Wbi[BO + 2], P.gamma, P.newton_max,
+                         P.tol);
+        lji = limiter<D>(Uj, Pji, Wbj[BO], Wbj[BO + 1], Wbj[BO + 2], P.gamma, P.newton_max,
+                         P.tol);
+    } else {
+        double U[2 * NU], Wb[4];
+        gather<NU>(P.upass, kRowU, i, lw, U);
+        gather<2>(P.rowB + B0, kRowB, i, lw, Wb);
+        lij = valid_ ? limiter<D>(U, Pij, Wb[BO], Wb[BO + 1], Wb[BO + 2], P.gamma,
+                                  P.newton_max, P.tol)
+                     : 0.0;
+        gather<NU>(P.upass, kRowU, j, lw, U);
+        gather<2>(P.rowB + B0, kRowB, j, lw, Wb);
+        if (!valid_) return;
+        lji = limiter<D>(U, Pji, Wb[BO], Wb[BO + 1], Wb[BO + 2], P.gamma, P.newton_max,
+                         P.tol);
+    }
     const double sv = lij < lji ? lij : lji;
     P.l2[e] = sv;
     P.l2[t] = sv;

@@ -93,36 +93,72 @@ __device__ __forceinline__ T ld_stream(const T *p)
 constexpr int kLdsRow = kSlice + 1;   // double2 per chunk row (+1: bank skew)
 constexpr int kMaxChunks = 7;         // largest record gathered (pack B with coefficient)
 
-template <int NCH>
-__device__ __forceinline__ void gather(const double *__restrict__ base, int stride, int node,
-                                       double2 *lds, double *out)
-{
+// A 16-byte chunk in registers (a native vector: its copies stay loads and
+// stores that the optimiser can keep in registers)
+typedef double dchunk __attribute__((ext_vector_type(2)));
+
+// Lanes per record and records per load instruction of an NCH-chunk gather.
+template <int NCH> struct GatherShape {
     static_assert(NCH >= 1 && NCH <= 8, "record of 1 to 8 chunks");
-    constexpr int LPR = NCH > 4 ? 8 : (NCH > 2 ? 4 : (NCH > 1 ? 2 : 1));
-    constexpr int RPI = kSlice / LPR;
+    static constexpr int LPR = NCH > 4 ? 8 : (NCH > 2 ? 4 : (NCH > 1 ? 2 : 1));
+    static constexpr int RPI = kSlice / LPR;
+};
+
+// The loads of a gather: chunks 0 .. NCH-2 and chunk LAST of the records
+// the lanes want, as lane l holds them (val[it] = chunk l % LPR of the
+// record of lane it * RPI + l / LPR); nothing waits for them yet.
+template <int NCH, int LAST = NCH - 1>
+__device__ __forceinline__ void gather_issue(const double *__restrict__ base, int stride,
+                                             int node, dchunk (&val)[GatherShape<NCH>::LPR])
+{
+    static_assert(LAST >= NCH - 1, "prefix plus one chunk");
+    using S = GatherShape<NCH>;
     const int lane = threadIdx.x % kSlice;
-    const int c = lane % LPR;
+    const int c = lane % S::LPR;
     const int cc = c < NCH ? c : NCH - 1;   // spare lanes repeat the last chunk
-    int nd[LPR];
+    const int src = cc == NCH - 1 ? LAST : cc;
+    int nd[S::LPR];
 #pragma unroll
-    for (int it = 0; it < LPR; ++it) {
-        const int v = __shfl(node, it * RPI + lane / LPR);
+    for (int it = 0; it < S::LPR; ++it) {
+        const int v = __shfl(node, it * S::RPI + lane / S::LPR);
         nd[it] = v < 0 ? 0 : v;
     }
-    double2 val[LPR];
 #pragma unroll
-    for (int it = 0; it < LPR; ++it)
-        val[it] = *reinterpret_cast<const double2 *>(base + int64_t(nd[it]) * stride + 2 * cc);
+    for (int it = 0; it < S::LPR; ++it)
+        val[it] = *reinterpret_cast<const dchunk *>(base + int64_t(nd[it]) * stride + 2 * src);
+}
+
+// The chunks of gather_issue() to their owners through the wavefront's LDS
+// tile: out = the lane's own record (NCH chunks).
+template <int NCH>
+__device__ __forceinline__ void gather_exchange(double2 *lds,
+                                                const dchunk (&val)[GatherShape<NCH>::LPR],
+                                                double *out)
+{
+    using S = GatherShape<NCH>;
+    const int lane = threadIdx.x % kSlice;
+    const int c = lane % S::LPR;
+    const int cc = c < NCH ? c : NCH - 1;
+    dchunk *const t = reinterpret_cast<dchunk *>(lds);
 #pragma unroll
-    for (int it = 0; it < LPR; ++it) lds[cc * kLdsRow + it * RPI + lane / LPR] = val[it];
+    for (int it = 0; it < S::LPR; ++it) t[cc * kLdsRow + it * S::RPI + lane / S::LPR] = val[it];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int k = 0; k < NCH; ++k) {
-        const double2 v = lds[k * kLdsRow + lane];
+        const dchunk v = t[k * kLdsRow + lane];
         out[2 * k] = v.x;
         out[2 * k + 1] = v.y;
     }
     __builtin_amdgcn_wave_barrier();
+}
+
+template <int NCH>
+__device__ __forceinline__ void gather(const double *__restrict__ base, int stride, int node,
+                                       double2 *lds, double *out)
+{
+    dchunk val[GatherShape<NCH>::LPR];
+    gather_issue<NCH>(base, stride, node, val);
+    gather_exchange<NCH>(lds, val, out);
 }
 
 // Variant of gather() whose last chunk is chunk LAST of the record (the
@@ -132,36 +168,9 @@ __device__ __forceinline__ void gather_tail(const double *__restrict__ base, int
                                             double2 *lds, double *out)
 {
     static_assert(NCH >= 2 && NCH <= 8 && LAST >= NCH - 1, "prefix plus one chunk");
-    if constexpr (LAST == NCH - 1) {
-        gather<NCH>(base, stride, node, lds, out);   // contiguous after all
-        return;
-    }
-    constexpr int LPR = NCH > 4 ? 8 : (NCH > 2 ? 4 : 2);
-    constexpr int RPI = kSlice / LPR;
-    const int lane = threadIdx.x % kSlice;
-    const int c = lane % LPR;
-    const int cc = c < NCH ? c : NCH - 1;
-    const int src = cc == NCH - 1 ? LAST : cc;
-    int nd[LPR];
-#pragma unroll
-    for (int it = 0; it < LPR; ++it) {
-        const int v = __shfl(node, it * RPI + lane / LPR);
-        nd[it] = v < 0 ? 0 : v;
-    }
-    double2 val[LPR];
-#pragma unroll
-    for (int it = 0; it < LPR; ++it)
-        val[it] = *reinterpret_cast<const double2 *>(base + int64_t(nd[it]) * stride + 2 * src);
-#pragma unroll
-    for (int it = 0; it < LPR; ++it) lds[cc * kLdsRow + it * RPI + lane / LPR] = val[it];
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int k = 0; k < NCH; ++k) {
-        const double2 v = lds[k * kLdsRow + lane];
-        out[2 * k] = v.x;
-        out[2 * k + 1] = v.y;
-    }
-    __builtin_amdgcn_wave_barrier();
+    dchunk val[GatherShape<NCH>::LPR];
+    gather_issue<NCH, LAST>(base, stride, node, val);
+    gather_exchange<NCH>(lds, val, out);
 }
 
 // The store counterpart of gather(): lane l's record `in` (NCH chunks) goes
@@ -430,6 +439,25 @@ __device__ __forceinline__ void gather_b(const double *__restrict__ packB, int n
     }
     B.alpha = rec[2 * NC];
     B.m = rec[2 * NC + 1];
+    B.coef = rec[2 * NB];
+}
+
+// Pack B records (with the coefficient) of two nodes, the loads of both
+// in flight before either passes through the LDS tile.
+template <int D>
+__device__ __forceinline__ void gather_b2(const double *__restrict__ packB, int na, int nb,
+                                          double2 *lw, NodeB<D> &A, NodeB<D> &B)
+{
+    constexpr int NC = D + 2, NB = (2 * NC + 2) / 2, NCH = NB + 1;
+    dchunk va[GatherShape<NCH>::LPR], vb[GatherShape<NCH>::LPR];
+    gather_issue<NCH, kPackCoef / 2>(packB, kPack, na, va);
+    gather_issue<NCH, kPackCoef / 2>(packB, kPack, nb, vb);
+    double rec[2 * NCH];
+    gather_exchange<NCH>(lw, va, rec);
+    unpack_b<D, false>(rec, A);
+    A.coef = rec[2 * NB];
+    gather_exchange<NCH>(lw, vb, rec);
+    unpack_b<D, false>(rec, B);
     B.coef = rec[2 * NB];
 }
 
