@@ -367,7 +367,9 @@ __device__ __forceinline__ void newton_vjp(double tL, double tR, double psiL, do
 // bb = (rho_min, rho_max, phi_min) cotangents.
 constexpr int kAdjNewtonMax = 8;
 
-template <int D>
+// NMAX: the compile-time bound of newton_max; at NMAX <= 2 the loops unroll
+// and the recorded brackets stay in registers.
+template <int D, int NMAX>
 __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, double rmin,
                                             double rmax, double phimin, double g,
                                             int newton_max, double tol, double tb,
@@ -385,10 +387,13 @@ __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, do
     const bool c0 = tR < 0.0;
     if (c0) tR = 0.0;
     // Newton iterations: the brackets recorded, Psi recomputed backwards
-    double tLs[kAdjNewtonMax + 1], tRs[kAdjNewtonMax + 1];
+    constexpr bool kUnroll = NMAX <= 2;
+    double tLs[NMAX + 1], tRs[NMAX + 1];
     double tL = 0.0;
     int steps = 0, brk = 0;   // brk: 0 none, 1 psiR >= 0 (t = tR), 2 psiL <= tol (t = tL)
-    for (int it = 0; it < newton_max; ++it) {
+#pragma unroll(kUnroll ? NMAX : 1)
+    for (int it = 0; it < NMAX; ++it) {
+        if (it >= newton_max) break;
         tLs[it] = tL;
         tRs[it] = tR;
         double psiR, dpsiR;
@@ -403,7 +408,9 @@ __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, do
     // backwards: cotangents of (tL, tR) at the start of iteration `steps`
     double tLb = 0.0, tRb = 0.0, phib = 0.0;
     if (brk == 1) tRb = tb; else tLb = tb;
-    for (int it = steps - 1; it >= 0; --it) {
+#pragma unroll(kUnroll ? NMAX : 1)
+    for (int it = NMAX - 1; it >= 0; --it) {
+        if (it >= steps) continue;
         PsiPt<D> R, Lp;
         psi_eval<D>(U, P, tRs[it], phimin, g, R);
         psi_eval<D>(U, P, tLs[it], phimin, g, Lp);
@@ -486,7 +493,7 @@ __device__ __forceinline__ int put_lim(double *Lim, int64_t p, bool valid, const
 // s2 = min(l_ij, l_ji) is run backwards (Alg. 2/3 on the line U_a' + t
 // (1 - s1) P_a): its state and bounds cotangents go to the pair's limiter
 // record (indexed from the entry of its row), the direction's to the pair.
-template <int D>
+template <int D, int NMAX>
 __global__ void __launch_bounds__(kBlock) k_adj_lim2(StageArgs P, AdjArgs A)
 {
     WAVE_LDS(Chunks<D>::packB)
@@ -528,7 +535,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_lim2(StageArgs P, AdjArgs A)
 #pragma unroll
     for (int r = 0; r < NC; ++r) { Ub[r] = 0.0; Qb[r] = 0.0; }
     if (valid_ && sb != 0.0)
-        limiter_vjp<D>(Ua, Qa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
+        limiter_vjp<D, NMAX>(Ua, Qa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
                        Ub, Qb, bb);
     double rq[kQS];
 #pragma unroll
@@ -581,7 +588,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_pass1(StageArgs P, AdjArgs A)
 // backwards.  Both directions then reduce to Z = coef_j Pb_ji - coef_i
 // Pb_ij: R_i gains b_ji Z, U_i gains (d^H - d^L) Z, R_j and U_j the same
 // with -Z and b_ij; alpha_i and alpha_j each gain -Z.(U_j - U_i) d^L/2.
-template <int D>
+template <int D, int NMAX>
 __global__ void __launch_bounds__(kBlock, 2) k_adj_lim1(StageArgs P, AdjArgs A)
 {
     WAVE_LDS(Chunks<D>::packB)
@@ -648,7 +655,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_adj_lim1(StageArgs P, AdjArgs A)
 #pragma unroll
     for (int r = 0; r < NC; ++r) { ULb[r] = 0.0; Pab[r] = 0.0; }
     if (valid_ && sb != 0.0)
-        limiter_vjp<D>(Wa, Pa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
+        limiter_vjp<D, NMAX>(Wa, Pa, Wa[NC], Wa[NC + 1], Wa[NC + 2], P.gamma, P.newton_max, P.tol, sb,
                        ULb, Pab, bb);
     const double ca = side1 ? -ci : cj;
     double kb = 0.0;
@@ -1125,11 +1132,27 @@ static inline int pairs_grid(const StageArgs &P) { return P.pper * kXcd; }
         }                                                                                \
     } while (0)
 
+// the limiter VJPs by the compile-time bound of newton_max
+#define ADJ_LAUNCH_N(K, grid)                                                            \
+    do {                                                                                 \
+        if (grid > 0) {                                                                  \
+            const bool small = P.newton_max <= 2;                                        \
+            if (P.dim == 2 && small)                                                     \
+                hipLaunchKernelGGL((K<2, 2>), dim3(grid), dim3(kBlock), 0, st, P, A);    \
+            else if (P.dim == 2)                                                         \
+                hipLaunchKernelGGL((K<2, kAdjNewtonMax>), dim3(grid), dim3(kBlock), 0, st, P, A); \
+            else if (small)                                                              \
+                hipLaunchKernelGGL((K<3, 2>), dim3(grid), dim3(kBlock), 0, st, P, A);    \
+            else                                                                         \
+                hipLaunchKernelGGL((K<3, kAdjNewtonMax>), dim3(grid), dim3(kBlock), 0, st, P, A); \
+        }                                                                                \
+    } while (0)
+
 void launch_stage_vjp(const StageArgs &P, const AdjArgs &A, hipStream_t st)
 {
-    if (P.passes >= 2) ADJ_LAUNCH(k_adj_lim2, pairs_grid(P));
+    if (P.passes >= 2) ADJ_LAUNCH_N(k_adj_lim2, pairs_grid(P));
     ADJ_LAUNCH(k_adj_pass1, rows_grid(P));
-    ADJ_LAUNCH(k_adj_lim1, pairs_grid(P));
+    ADJ_LAUNCH_N(k_adj_lim1, pairs_grid(P));
     ADJ_LAUNCH(k_adj_low, rows_grid(P));
     ADJ_LAUNCH(k_adj_alpha, rows_grid(P));
     ADJ_LAUNCH(k_adj_dpair, pairs_grid(P));

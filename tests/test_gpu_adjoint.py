@@ -79,6 +79,26 @@ def test_stage_vjp_matches_reference(torch, oracle_mod, ref_mod, case):
     assert ok, err
 
 
+@pytest.mark.parametrize("newton_max", [1, 4])
+def test_stage_vjp_with_other_newton_bounds(torch, oracle_mod, ref_mod, newton_max):
+    # newton_max <= 2 and above run different instantiations of the limiter
+    # VJPs (brackets kept in registers, or in an indexed array)
+    announce(f"stage VJP vs reference adjoint: generic_3d_9, newton_max={newton_max}")
+    from paper_2007_00094_amd.solver import Solver
+    m, U0 = generic(9, 3)
+    s = Solver(m, newton_max=newton_max)
+    o = oracle_mod.Oracle(m, dirichlet=m.boundary, newton_max=newton_max)
+    ref = ref_mod.Reference(o, dirichlet=m.boundary, newton_max=newton_max)
+    tau = o.max_dt(U0)
+    W = np.random.default_rng(5).normal(size=U0.shape)
+    got = s.euler_stage_vjp(torch.tensor(U0, device="cuda"), tau,
+                            torch.tensor(W, device="cuda")).cpu().numpy()
+    Ut = torch.tensor(U0, requires_grad=True)
+    (torch.tensor(W) * ref.stage(Ut, tau)).sum().backward()
+    ok, err = close(got, Ut.grad.numpy())
+    assert ok, err
+
+
 def test_step_vjp_matches_reference(torch, oracle_mod, ref_mod):
     announce("step VJP vs reference adjoint: generic_3d_9 after 2 steps")
     from paper_2007_00094_amd.solver import Solver
