@@ -46,22 +46,29 @@ def algorithmic_bytes(dim, n, nnz):
     reads or writes counted once (neighbour gathers and transposed reads
     assumed cached), from the data layout of the library."""
     nc = dim + 2
-    pack = 8 * (2 * dim + 6)        # node pack A / B: used doubles
-    packb = 8 * (2 * nc + 2)
-    rowb = 8 * (nc + 3)
+    packa = 8 * (nc + 3)       # pack A as the forward reads it: U, p, c, eta/rho
+    packl = 8 * (nc + 3)       # pack L: U, p, phi, alpha
+    packb = 8 * (2 * nc + 2)   # pack B: U, R, alpha, m
+    coef = 8                   # pack B's tau/(lambda_i m_i)
+    rowb = 8 * (nc + 3)        # U^L, bounds
     cb = 8 * dim
     npairs = (nnz - n) // 2
     return {
-        "node_pack": n * (8 * nc + pack),
-        # per pair: 4 ids, c_ij and c_ji, d written twice
-        "pair_viscosity": npairs * (16 + 2 * cb + 16) + n * pack,
-        "row_diagonal": nnz * (4 + cb + 8) + n * (pack + 8 + 8 + 8),
-        "row_low_order": nnz * (4 + cb + 8) + n * (pack + 8 + 8 + packb + rowb),
-        # per pair: 4 ids, d, m_ij, s written twice
-        "pair_limiter1": npairs * (16 + 8 + 8 + 16) + n * (packb + rowb + 8),
-        "row_pass1": nnz * (4 + 8 + 8 + 8) + n * (packb + rowb + 8 + 8 * nc),
-        "pair_limiter2": npairs * (16 + 8 + 8 + 8 + 16) + n * (packb + rowb + 8 + 8 * nc),
-        "row_pass2": nnz * (4 + 8 + 8 + 8 + 8) + n * (packb + 8 * nc + 8 + 3 * 8 * nc + 1),
+        # U read; pack A and pack L written (pack L's alpha by the diagonal sweep)
+        "node_pack": n * (8 * nc + packa + packl - 8),
+        # per pair: 4 ids, c_ij and c_ji, d written twice; U, p, c of the nodes
+        "pair_viscosity": npairs * (16 + 2 * cb + 16) + n * 8 * (nc + 2),
+        # per entry: column, c_ij, d_ij; per node: m_i read, d_ii, tau_i, alpha twice written
+        "row_diagonal": nnz * (4 + cb + 8) + n * (packa + 8 + 4 * 8),
+        # per node: alpha_i, m_i, lambda_i read; pack B and the row record written
+        "row_low_order": nnz * (4 + cb + 8) + n * (packl + 3 * 8 + packb + coef + rowb),
+        # per pair: 4 ids, d, m_ij, s written twice and once in pair order
+        "pair_limiter1": npairs * (16 + 8 + 8 + 16 + 8) + n * (packb + coef + rowb),
+        # per node: lambda_i, U^L read, the pass-1 state written
+        "row_pass1": nnz * (4 + 8 + 8 + 8) + n * (packb + 8 + 8 * nc + 8 * nc),
+        # per pair: 4 ids, d, m_ij, s1, s2 written twice; per node: bounds, pass-1 state
+        "pair_limiter2": npairs * (16 + 8 + 8 + 8 + 16) + n * (packb + coef + 24 + 8 * nc),
+        "row_pass2": nnz * (4 + 8 + 8 + 8 + 8) + n * (packb + 8 + 8 * nc + 3 * 8 * nc + 1),
     }
 
 
