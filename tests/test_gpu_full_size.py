@@ -119,7 +119,8 @@ DT_BIG = 1e-4   # below the stage-1 bound of the Mach 3 flow at h = 1/256
 def big(torch):
     announce(f"mach3_3d {N_BIG}^3 Morton: mesh, solver")
     mesh, U0 = inputs.workload("mach3_3d", n=N_BIG, order="morton")
-    s = solver(mesh)
+    # the launch configuration bench.py times: LDS staging, SELL window 64
+    s = solver(mesh, staging=True, sell_sigma=64)
     pe = inputs.PatchExtractor(mesh)
     rng = np.random.default_rng(11)
     samples = rng.choice(mesh.n_nodes, 10, replace=False)
