@@ -613,13 +613,16 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
     }
     if (!valid_) return;
     P.l1[ENTRY(P.diag_k[r_])] = 1.0;   // the diagonal's s1 (pass 2 reads it as 1)
-    // whole 64-byte records: a partly written line costs the memory a
-    // read-modify-write
+    // whole 64-byte records (a partly written line costs the memory a
+    // read-modify-write): the state, and the row's bounds beside it so that
+    // the pass-2 limiter gathers one record per row
     double *Up = P.upass + int64_t(i) * kRowU;
 #pragma unroll
     for (int r = 0; r < NC; ++r) Up[r] = V[r];
 #pragma unroll
-    for (int r = NC; r < kRowU; ++r) Up[r] = 0.0;
+    for (int q = 0; q < 3; ++q) Up[NC + q] = W[NC + q];
+#pragma unroll
+    for (int r = NC + 3; r < kRowU; ++r) Up[r] = 0.0;
 }
 
 // ------------------------------------------------------ pair limiter 2
@@ -652,40 +655,30 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
         Pij[r] = (1.0 - l) * Pij[r];
         Pji[r] = (1.0 - l) * Pji[r];
     }
-    // per side: the pass-1 state and the two chunks of the row record that
-    // hold the bounds (slots NC .. NC + 2 of U^L, bounds); in 2D the loads of
-    // both sides are in flight before the first passes through LDS
-    constexpr int B0 = 2 * (NC / 2), BO = NC - B0, NU = CH::upass;
+    // per side: the pass-1 state with the row's bounds (one record); in 2D
+    // the loads of both sides are in flight before the first passes
+    // through LDS
+    constexpr int NU = CH::upassb;
     double lij, lji;
     if constexpr (D == 2) {
         dchunk ui[GatherShape<NU>::LPR], uj[GatherShape<NU>::LPR];
-        dchunk wi[GatherShape<2>::LPR], wj[GatherShape<2>::LPR];
         gather_issue<NU>(P.upass, kRowU, i, ui);
-        gather_issue<2>(P.rowB + B0, kRowB, i, wi);
         gather_issue<NU>(P.upass, kRowU, j, uj);
-        gather_issue<2>(P.rowB + B0, kRowB, j, wj);
-        double Ui[2 * NU], Uj[2 * NU], Wbi[4], Wbj[4];
+        double Ui[2 * NU], Uj[2 * NU];
         gather_exchange<NU>(lw, ui, Ui);
-        gather_exchange<2>(lw, wi, Wbi);
         gather_exchange<NU>(lw, uj, Uj);
-        gather_exchange<2>(lw, wj, Wbj);
         if (!valid_) return;
-        lij = limiter<D>(Ui, Pij, Wbi[BO], Wbi[BO + 1], Wbi[BO + 2], P.gamma, P.newton_max,
-                         P.tol);
-        lji = limiter<D>(Uj, Pji, Wbj[BO], Wbj[BO + 1], Wbj[BO + 2], P.gamma, P.newton_max,
-                         P.tol);
+        lij = limiter<D>(Ui, Pij, Ui[NC], Ui[NC + 1], Ui[NC + 2], P.gamma, P.newton_max, P.tol);
+        lji = limiter<D>(Uj, Pji, Uj[NC], Uj[NC + 1], Uj[NC + 2], P.gamma, P.newton_max, P.tol);
     } else {
-        double U[2 * NU], Wb[4];
+        double U[2 * NU];
         gather<NU>(P.upass, kRowU, i, lw, U);
-        gather<2>(P.rowB + B0, kRowB, i, lw, Wb);
-        lij = valid_ ? limiter<D>(U, Pij, Wb[BO], Wb[BO + 1], Wb[BO + 2], P.gamma,
-                                  P.newton_max, P.tol)
+        lij = valid_ ? limiter<D>(U, Pij, U[NC], U[NC + 1], U[NC + 2], P.gamma, P.newton_max,
+                                  P.tol)
                      : 0.0;
         gather<NU>(P.upass, kRowU, j, lw, U);
-        gather<2>(P.rowB + B0, kRowB, j, lw, Wb);
         if (!valid_) return;
-        lji = limiter<D>(U, Pji, Wb[BO], Wb[BO + 1], Wb[BO + 2], P.gamma, P.newton_max,
-                         P.tol);
+        lji = limiter<D>(U, Pji, U[NC], U[NC + 1], U[NC + 2], P.gamma, P.newton_max, P.tol);
     }
     const double sv = lij < lji ? lij : lji;
     P.l2[e] = sv;

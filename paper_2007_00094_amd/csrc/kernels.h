@@ -16,7 +16,8 @@ constexpr int kPack = 16;     // doubles per node in the gather packs
 constexpr int kPackAlpha = 12;  // pack A slot of alpha_i (written by k_diag)
 constexpr int kPackCoef = 12;   // pack B slot of tau/(lambda_i m_i)
 constexpr int kRowB = 8;      // doubles per node: U^L (nc), bounds (3)
-constexpr int kRowU = 8;      // doubles per node: state after pass 1
+constexpr int kRowU = 8;      // doubles per node: state after pass 1 (nc), the
+                              // row's bounds (3)
 constexpr int kPackL = 8;     // doubles per node: the low-order sweep's neighbour
                               // record U (nc), p, phi, alpha [kPackLAlpha]
 constexpr int kPackLAlpha = 7;

@@ -492,6 +492,7 @@ template <int D> struct Chunks {
     static constexpr int packBrow = NC + 1;           // U, R, alpha, m
     static constexpr int rowB = (NC + 4) / 2;         // U^L, bounds
     static constexpr int upass = (NC + 1) / 2;        // pass-1 state
+    static constexpr int upassb = (NC + 4) / 2;       // pass-1 state and bounds
 };
 static_assert(Chunks<3>::packB <= kMaxChunks && Chunks<2>::packB <= kMaxChunks, "LDS tile");
 
