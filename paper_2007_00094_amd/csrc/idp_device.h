@@ -203,13 +203,18 @@ __host__ __device__ inline GasC make_gas(double g)
 
 // psi_branch(rho_i, p_i, c_i, p_max) + psi_branch(rho_j, p_j, c_j, p_max),
 // p_max = max(p_i, p_j): the same for both orientations of a pair (the sum
-// commutes), so a pair evaluates it once.
+// commutes), so a pair evaluates it once.  The state whose pressure is
+// p_max contributes exactly +0 (its shock branch has p - p_s = 0 over a
+// positive root), and x + 0 = x for the other term (never -0), so only the
+// other state's term is evaluated.
 template <int D>
 __device__ __forceinline__ double psi_sum(double rhoi, double pi, double ci, double rhoj,
                                           double pj, double cj, const GasC &G)
 {
-    const double pmax = pi > pj ? pi : pj;
-    return psi_branch<D>(rhoi, pi, ci, pmax, G.g) + psi_branch<D>(rhoj, pj, cj, pmax, G.g);
+    const bool jlow = pi > pj;
+    const double pmax = jlow ? pi : pj;
+    const double rho = jlow ? rhoj : rhoi, ps = jlow ? pj : pi, cs = jlow ? cj : ci;
+    return psi_branch<D>(rho, ps, cs, pmax, G.g);
 }
 
 // lambda_max with the two states' psi_branch sum S given.
