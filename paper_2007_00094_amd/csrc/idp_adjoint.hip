@@ -840,7 +840,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_alpha(StageArgs P, AdjArgs A)
     WAVE_ROW_SETUP(P, ROW_SLICE(P), P.nslices)
     (void)inst_;   // one instance: adjoints run on single meshes
     constexpr int NC = D + 2;
-    constexpr int NCH = (NC + 4 + D) / 2;   // U, p, c, eta/rho, v, phi
+    constexpr int NCH = kDiagChunks<D>;   // U, p, c, eta/rho (v recomputed)
     const double g = P.gamma;
     const int dk = valid_ ? P.diag_k[r_] : -1;
     NodeA<D> Ai;
@@ -873,7 +873,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_alpha(StageArgs P, AdjArgs A)
         gather<kNS / 2>(A.Nrec, kNS, act ? j : -1, lw, rn);
         if (!in) continue;
         NodeA<D> Aj;
-        unpack_a<D>(ra, Aj);
+        load_a_fwd<D>(ra, Aj);
         double c[D];
         load_c<D>(P, e, c);
         double mc = 0.0;
