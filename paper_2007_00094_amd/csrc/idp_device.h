@@ -217,7 +217,11 @@ __device__ __forceinline__ double psi_sum(double rhoi, double pi, double ci, dou
     return psi_branch<D>(rho, ps, cs, pmax, G.g);
 }
 
-// lambda_max with the two states' psi_branch sum S given.
+// The guaranteed upper bound on the maximum wave speed of the 1D Riemann
+// problem along n between U_i (left) and U_j (right) (Section 3.7): the
+// two-rarefaction pressure p~, taken as p* unless psi(p_max) >= 0 says
+// p* <= p_max, then the extreme wave speeds of the 1-wave and 3-wave.  S is
+// psi_sum of the pair (the psi(p_max) terms without u_j - u_i).
 template <int D>
 __device__ __forceinline__ double lambda_max_s(const double *n, const double *Ui, double pi,
                                                double ci, const double *Uj, double pj,
@@ -235,36 +239,6 @@ __device__ __forceinline__ double lambda_max_s(const double *n, const double *Ui
     const double ptilde = pj * fpow(pos_part(num) / den, G.e_p);
     const double pmax = pi > pj ? pi : pj;
     const double psi = S + uj - ui;
-    double pstar;
-    if (psi < 0.0)
-        pstar = ptilde;
-    else
-        pstar = pmax < ptilde ? pmax : ptilde;
-    const double lam1 = ui - ci * sqrt(1.0 + G.f * pos_part((pstar - pi) / pi));
-    const double lam3 = uj + cj * sqrt(1.0 + G.f * pos_part((pstar - pj) / pj));
-    const double a = neg_part(lam1), b = pos_part(lam3);
-    return a > b ? a : b;
-}
-
-template <int D>
-__device__ __forceinline__ double lambda_max(const double *n, const double *Ui,
-                                             double pi, double ci, const double *Uj,
-                                             double pj, double cj, const GasC &G)
-{
-    const double g = G.g;
-    double mti = 0.0, mtj = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) mti += n[k] * Ui[1 + k];
-#pragma unroll
-    for (int k = 0; k < D; ++k) mtj += n[k] * Uj[1 + k];
-    const double ui = mti / Ui[0];
-    const double uj = mtj / Uj[0];
-    const double num = ci + cj - G.half_gm1 * (uj - ui);
-    const double den = ci * fpow(pi / pj, G.e_den) + cj;
-    const double ptilde = pj * fpow(pos_part(num) / den, G.e_p);
-    const double pmax = pi > pj ? pi : pj;
-    const double psi = psi_branch<D>(Ui[0], pi, ci, pmax, g) +
-                       psi_branch<D>(Uj[0], pj, cj, pmax, g) + uj - ui;
     double pstar;
     if (psi < 0.0)
         pstar = ptilde;

@@ -357,20 +357,6 @@ struct GatherTailFetch {
     const int j = P.pair_j[pq_];
 
 template <int D>
-__device__ __forceinline__ void unpack_a(const double *o, NodeA<D> &A)
-{
-    constexpr int NC = D + 2;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) A.U[k] = o[k];
-    A.p = o[NC];
-    A.c = o[NC + 1];
-    A.er = o[NC + 2];
-#pragma unroll
-    for (int k = 0; k < D; ++k) A.v[k] = o[NC + 3 + k];
-    A.phi = o[NC + 3 + D];
-}
-
-template <int D>
 __device__ __forceinline__ void load_c(const StageArgs &P, int64_t e, double *c)
 {
     c[0] = P.c0[e];
