@@ -219,9 +219,10 @@ __device__ __forceinline__ double psi_sum(double rhoi, double pi, double ci, dou
 
 // The guaranteed upper bound on the maximum wave speed of the 1D Riemann
 // problem along n between U_i (left) and U_j (right) (Section 3.7): the
-// two-rarefaction pressure p~, taken as p* unless psi(p_max) >= 0 says
-// p* <= p_max, then the extreme wave speeds of the 1-wave and 3-wave.  S is
-// psi_sum of the pair (the psi(p_max) terms without u_j - u_i).
+// pressure bound is the two-rarefaction pressure p~, capped at p_max when
+// psi(p_max) >= 0 (then p* <= p_max); then the extreme speeds of the 1-wave
+// and 3-wave at that pressure.  S is psi_sum of the pair (psi(p_max)
+// without its u_j - u_i term).
 template <int D>
 __device__ __forceinline__ double lambda_max_s(const double *n, const double *Ui, double pi,
                                                double ci, const double *Uj, double pj,
