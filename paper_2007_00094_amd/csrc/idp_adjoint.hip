@@ -387,11 +387,11 @@ __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, do
     const bool c0 = tR < 0.0;
     if (c0) tR = 0.0;
     // Newton iterations: the brackets recorded, Psi recomputed backwards
-    constexpr bool kUnroll = NMAX <= 2;
+    constexpr int kUnroll = NMAX <= 2 ? NMAX : 1;   // loop unroll count
     double tLs[NMAX + 1], tRs[NMAX + 1];
     double tL = 0.0;
     int steps = 0, brk = 0;   // brk: 0 none, 1 psiR >= 0 (t = tR), 2 psiL <= tol (t = tL)
-#pragma unroll(kUnroll ? NMAX : 1)
+#pragma unroll kUnroll
     for (int it = 0; it < NMAX; ++it) {
         if (it >= newton_max) break;
         tLs[it] = tL;
@@ -408,7 +408,7 @@ __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, do
     // backwards: cotangents of (tL, tR) at the start of iteration `steps`
     double tLb = 0.0, tRb = 0.0, phib = 0.0;
     if (brk == 1) tRb = tb; else tLb = tb;
-#pragma unroll(kUnroll ? NMAX : 1)
+#pragma unroll kUnroll
     for (int it = NMAX - 1; it >= 0; --it) {
         if (it >= steps) continue;
         PsiPt<D> R, Lp;
