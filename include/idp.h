@@ -97,8 +97,9 @@ int idp_default_params(idp_params *p, int dim);
  * Builds the stencil graph I(i) (nodes sharing a cell, diagonal included),
  * m_ij and c_ij by 3-point Gauss quadrature per direction, m_i = sum_j m_ij,
  * and the device work buffers.  On success *out owns all of it; destroy
- * with idp_destroy.  Errors: IDP_EINVAL (sizes, ids out of range, bad
- * params), IDP_EMESH (an inverted or degenerate cell), IDP_ENOMEM, IDP_EHIP.*/
+ * with idp_destroy.  Errors: IDP_EINVAL (n_nodes or n_cells below 1, ids
+ * out of range, bad params; the first and the last before any device call),
+ * IDP_EMESH (an inverted or degenerate cell), IDP_ENOMEM, IDP_EHIP.      */
 int idp_create(idp_ctx **out, const idp_params *p, int64_t n_nodes,
                const double *coords, int64_t n_cells, const int64_t *cells,
                const uint8_t *dirichlet, void *hip_stream);

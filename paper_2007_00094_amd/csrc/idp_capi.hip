@@ -541,6 +541,7 @@ int idp_create(idp_ctx **out, const idp_params *prm, int64_t n_nodes,
     *out = nullptr;
     const int rc = check_params(*prm);
     if (rc != IDP_OK) return rc;
+    if (n_nodes < 1 || n_cells < 1) return IDP_EINVAL;   // an empty mesh has no step
     return create_impl(out, *prm, {MeshIn{n_nodes, n_cells, coords, cells, dirichlet}},
                        hip_stream);
 }

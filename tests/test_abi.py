@@ -60,6 +60,18 @@ def test_create_rejects_bad_params_before_any_device_call(field, value, code):
     assert L.idp_max_dt(None, None, None) == capi.IDP_EINVAL
 
 
+def test_create_rejects_an_empty_mesh_before_any_device_call():
+    L = capi.lib()
+    p = capi.idp_params()
+    L.idp_default_params(C.byref(p), 2)
+    h = C.c_void_p()
+    xy = (C.c_double * 8)()
+    cells = (C.c_int64 * 4)(0, 1, 2, 3)
+    assert L.idp_create(C.byref(h), C.byref(p), 0, xy, 1, cells, None, None) == capi.IDP_EINVAL
+    assert L.idp_create(C.byref(h), C.byref(p), 4, xy, 0, cells, None, None) == capi.IDP_EINVAL
+    assert not h.value
+
+
 def test_create_batch_rejects_bad_arguments_before_any_device_call():
     L = capi.lib()
     p = capi.idp_params()

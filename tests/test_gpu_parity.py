@@ -229,6 +229,33 @@ def test_sell_window_is_bitwise(torch, oracle_mod, dim, n, sigma):
     s.close()
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_single_cell_mesh(torch, oracle_mod, dim):
+    """The smallest mesh: one cell, every row the full stencil of 2^dim
+    nodes; three steps without boundary hold bitwise the oracle's, and with
+    the default hold (every node on the boundary) the state unchanged."""
+    announce(f"single-cell mesh dim={dim}")
+    from paper_2007_00094_amd.solver import Solver
+    mesh = inputs.q1_grid(2, dim, 0.2, seed=0, order="random")
+    U0 = inputs.ic_generic_smooth(mesh.coords)
+    free = np.zeros(mesh.n_nodes, np.uint8)
+    s = Solver(mesh, dirichlet=free)
+    o = oracle_mod.Oracle(mesh, dirichlet=free)
+    U = torch.tensor(U0, device="cuda")
+    Uo = U0.copy()
+    for _ in range(3):
+        dt, st = s.step(U)
+        Uo, dto, sto = o.step(Uo)
+        assert dt == dto and st == sto
+        assert np.array_equal(U.cpu().numpy(), Uo)
+    s.close()
+    s = Solver(mesh)
+    U = torch.tensor(U0, device="cuda")
+    s.step(U)
+    assert np.array_equal(U.cpu().numpy(), U0)
+    s.close()
+
+
 def test_determinism(torch):
     announce("determinism: two runs, sphere 3D 13^3")
     mesh = inputs.q1_grid(13, 3, 0.2, seed=0, order="random")
