@@ -241,8 +241,8 @@ def main():
     ap.add_argument("--sell-sigma", type=int, default=64,
                     help="SELL-C-sigma sorting window in rows (multiple of 64; 0: all rows)")
     ap.add_argument("--adjoint-steps", type=int, default=200)
-    ap.add_argument("--cpu-radius", type=int, default=16)
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-radius", type=int, default=24)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--newton-max", type=int, default=2,
                     help="Newton iterations of the limiter (the method's default is 2)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
