@@ -322,7 +322,7 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
     const double dd = t1 > t2 ? t1 : t2;
     P.d[e] = dd;
     P.d[t] = dd;
-    P.dp[p_] = dd;
+    if (P.sided) P.dp[p_] = dd;   // pair order: read by the stage adjoint only
     if (P.sided) P.sided[p_] = t1 > t2;
 }
 
@@ -514,7 +514,7 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
     if (failed(P)) return;
     constexpr int NC = D + 2;
     using CH = Chunks<D>;
-    const double dL = P.dp[pq_], m = P.mp[pq_];
+    const double dL = P.d[e], m = P.mp[pq_];   // d_ij at (i, j): the viscosity sweep's value
     // both directions first, so that the node packs are dead before the
     // rows' bounds are gathered.  2D: each phase has the loads of both rows
     // in flight before either passes through LDS; 3D (more registers per
@@ -554,7 +554,7 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
     const double sv = lij < lji ? lij : lji;
     P.l1[e] = sv;
     P.l1[t] = sv;
-    P.l1p[p_] = sv;
+    if (P.side1) P.l1p[p_] = sv;   // pair order: read by the stage adjoint only
     if (P.side1) P.side1[p_] = lij < lji;
 }
 
@@ -636,8 +636,8 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
     if (failed(P)) return;
     constexpr int NC = D + 2;
     using CH = Chunks<D>;
-    const double dL = P.dp[pq_], m = P.mp[pq_];
-    const double l = P.l1p[pq_];
+    const double dL = P.d[e], m = P.mp[pq_];   // d_ij at (i, j): the viscosity sweep's value
+    const double l = P.l1[e];
     double Pij[NC], Pji[NC];
     {
         NodeB<D> Bi, Bj;

@@ -52,7 +52,8 @@ struct StageArgs {
     int pper;                   // pair blocks per XCD
     const int32_t *pair_e, *pair_t, *pair_i, *pair_j;
     double *mp;                 // [npairs] m_ij in pair order
-    double *dp, *l1p;           // [npairs] d_ij, min(l_ij, l_ji) pass 1
+    double *dp, *l1p;           // [npairs] d_ij, min(l_ij, l_ji) pass 1; written
+                                // only for stages that keep adjoint records
     // matrices (SELL order); written by the precompute only
     double *c0, *c1, *c2, *mij;
     double *ct0, *ct1, *ct2;    // c_ji at the position of c_ij
