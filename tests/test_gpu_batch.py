@@ -165,3 +165,25 @@ def test_single_instance_calls_refuse_a_batch(torch):
     out = C.c_double()
     assert L.idp_step(bs._h, C.c_void_p(U.data_ptr()), 0.0, None) == capi.IDP_ENOTSUP
     assert L.idp_max_dt(bs._h, C.c_void_p(U.data_ptr()), C.byref(out)) == capi.IDP_ENOTSUP
+
+
+def test_full_batch_workload_sampled_instances(torch, oracle_mod):
+    """The benchmark's batch (64 2D meshes, sides 33-513, per-instance CFL
+    dt) for 3 steps under the launch schedule: the smallest, the largest
+    and two more instances bit for bit against the oracle run alone."""
+    announce("full 64-mesh batch workload, 3 steps, sampled instances vs oracle")
+    batch = inputs.batch_workload()
+    bs = make(batch)
+    U = torch.tensor(np.concatenate([u for _, u in batch]), device="cuda")
+    from paper_2007_00094_amd.solver import BatchSolver
+    used, _ = bs.steps(U, 3, schedule=BatchSolver.schedule("launches"))
+    Ug = U.cpu().numpy()
+    off = np.cumsum([0] + [m.n_nodes for m, _ in batch])
+    sizes = [m.n_nodes for m, _ in batch]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 40})
+    for k in picks:
+        m, u = batch[k]
+        uo, taus = oracle_run(oracle_mod, m, u, 3)
+        assert np.array_equal(used[:, k], taus), k
+        assert np.array_equal(Ug[off[k]:off[k + 1]], uo), k
+
