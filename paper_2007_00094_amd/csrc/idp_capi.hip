@@ -98,6 +98,10 @@ struct idp_ctx {
     int tape_steps = 0;
     std::vector<idp::StageArgs> tape;
     bool tape_last = false;          // holds the last segment of the forward
+    // the backward's recomputation stream (default priority) and its events:
+    // [0, 1] a bank of the tape recomputed, [2, 3] a bank's VJPs done, [4] start
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev[5] = {};
     // timing
     bool timing = false;
     std::vector<Pending> pending;
@@ -137,17 +141,23 @@ hipEvent_t get_event(idp_ctx *c)
 
 // Launch wrapper: brackets the launch with events when timing is on.
 template <class F>
-void timed(idp_ctx *c, int id, F &&launch)
+void timed_on(idp_ctx *c, hipStream_t st, int id, F &&launch)
 {
     if (!c->timing) {
         launch();
         return;
     }
     Pending p{id, get_event(c), get_event(c)};
-    if (p.a) (void)hipEventRecord(p.a, c->stream);
+    if (p.a) (void)hipEventRecord(p.a, st);
     launch();
-    if (p.b) (void)hipEventRecord(p.b, c->stream);
+    if (p.b) (void)hipEventRecord(p.b, st);
     c->pending.push_back(p);
+}
+
+template <class F>
+void timed(idp_ctx *c, int id, F &&launch)
+{
+    timed_on(c, c->stream, id, launch);
 }
 
 // After a stream synchronisation: fold event pairs into the totals.
@@ -210,19 +220,25 @@ int status_code(int st)
 //  P: the stage's arguments (the context's, or a set whose per-stage arrays
 //  live elsewhere, e.g. in the adjoint's tape).
 void stage_p(idp_ctx *c, const idp::StageArgs &P, const double *in, const double *U0,
+             double *out, int mode, int tau_mode, double dt_in, int check, int clear,
+             hipStream_t st)
+{
+    timed_on(c, st, K_BEGIN, [&] { idp::launch_begin(P, st, clear); });
+    timed_on(c, st, K_NODE, [&] { idp::launch_node(P, st, in, check); });
+    timed_on(c, st, K_DPAIR, [&] { idp::launch_dpair(P, st); });
+    timed_on(c, st, K_DIAG, [&] { idp::launch_diag(P, st, 1); });
+    timed_on(c, st, K_TAU, [&] { idp::launch_tau(P, st, dt_in, tau_mode); });
+    timed_on(c, st, K_LOW, [&] { idp::launch_low(P, st); });
+    timed_on(c, st, K_LIM1P, [&] { idp::launch_lim1p(P, st); });
+    timed_on(c, st, K_PASS1A, [&] { idp::launch_pass1a(P, st); });
+    if (P.passes >= 2) timed_on(c, st, K_LIM2P, [&] { idp::launch_lim2p(P, st); });
+    timed_on(c, st, K_PASS2, [&] { idp::launch_pass2(P, st, U0, out, mode); });
+}
+
+void stage_p(idp_ctx *c, const idp::StageArgs &P, const double *in, const double *U0,
              double *out, int mode, int tau_mode, double dt_in, int check, int clear)
 {
-    hipStream_t st = c->stream;
-    timed(c, K_BEGIN, [&] { idp::launch_begin(P, st, clear); });
-    timed(c, K_NODE, [&] { idp::launch_node(P, st, in, check); });
-    timed(c, K_DPAIR, [&] { idp::launch_dpair(P, st); });
-    timed(c, K_DIAG, [&] { idp::launch_diag(P, st, 1); });
-    timed(c, K_TAU, [&] { idp::launch_tau(P, st, dt_in, tau_mode); });
-    timed(c, K_LOW, [&] { idp::launch_low(P, st); });
-    timed(c, K_LIM1P, [&] { idp::launch_lim1p(P, st); });
-    timed(c, K_PASS1A, [&] { idp::launch_pass1a(P, st); });
-    if (P.passes >= 2) timed(c, K_LIM2P, [&] { idp::launch_lim2p(P, st); });
-    timed(c, K_PASS2, [&] { idp::launch_pass2(P, st, U0, out, mode); });
+    stage_p(c, P, in, U0, out, mode, tau_mode, dt_in, check, clear, c->stream);
 }
 
 void stage(idp_ctx *c, const double *in, const double *U0, double *out, int mode,
@@ -259,6 +275,12 @@ void idp_destroy(idp_ctx *c)
         if (p.b) (void)hipEventDestroy(p.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
+    if (c->stream2) {
+        (void)hipStreamSynchronize(c->stream2);
+        (void)hipStreamDestroy(c->stream2);
+    }
+    for (auto e : c->ev)
+        if (e) (void)hipEventDestroy(e);
     for (void *q : c->allocs) (void)hipFree(q);
     if (c->tape_mem) (void)hipFree(c->tape_mem);
     delete c;
@@ -908,12 +930,34 @@ int tape_reserve(idp_ctx *c, int steps)
 
 // One SSP-RK3 step in place on U whose three stages keep their arrays in
 // tape step `slot` (the same arithmetic as idp_step with a given dt).
-void tape_step(idp_ctx *c, int slot, double *U, double dt, int clear)
+void tape_step(idp_ctx *c, int slot, double *U, double dt, int clear, hipStream_t st)
 {
     const idp::StageArgs *T = c->tape.data() + 3 * slot;
-    stage_p(c, T[0], U, U, c->U1, 1, 1, dt, 1, clear);
-    stage_p(c, T[1], c->U1, U, c->U1, 2, 0, 0.0, 0, 0);
-    stage_p(c, T[2], c->U1, U, U, 3, 0, 0.0, 0, 0);
+    stage_p(c, T[0], U, U, c->U1, 1, 1, dt, 1, clear, st);
+    stage_p(c, T[1], c->U1, U, c->U1, 2, 0, 0.0, 0, 0, st);
+    stage_p(c, T[2], c->U1, U, U, 3, 0, 0.0, 0, 0, st);
+}
+
+void tape_step(idp_ctx *c, int slot, double *U, double dt, int clear)
+{
+    tape_step(c, slot, U, dt, clear, c->stream);
+}
+
+// The second stream and its events, created on first use.
+int ensure_stream2(idp_ctx *c)
+{
+    if (c->stream2) return IDP_OK;
+    if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        c->stream2 = nullptr;
+        return IDP_EHIP;
+    }
+    for (auto &e : c->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return IDP_EHIP;
+        }
+    return IDP_OK;
 }
 
 // ------------------------------------------------------------- backward
@@ -1056,7 +1100,9 @@ int idp_forward_checkpoints(idp_ctx *c, double *U, int n_steps, const double *dt
         if ((rc = dalloc(c, &c->ckpt, slots * state)) != IDP_OK) return rc;
         c->ckpt_slots = slots;
     }
-    if ((rc = tape_reserve(c, every)) != IDP_OK) return rc;
+    // two banks of `every` steps if memory allows: the backward recomputes a
+    // segment into one while it runs the VJPs of the other
+    if ((rc = tape_reserve(c, 2 * every)) != IDP_OK) return rc;
     c->ck_steps = -1;
     c->tape_last = false;
     // the last segment runs on the tape, which the backward then starts from
@@ -1107,6 +1153,50 @@ int idp_adjoint_checkpoints(idp_ctx *c, int n_steps, const double *dt, int every
         cur = nxt;
         nxt = tmp;
     };
+    if (T >= 2 * every && nck >= 2 && ensure_stream2(c) == IDP_OK) {
+        // Two tape banks: segment k lives in bank (nck - 1 - k) % 2 (the
+        // forward left the last one in bank 0).  While the VJPs of segment
+        // k run on the context stream, the second stream recomputes segment
+        // k - 1 into the other bank, after the VJPs that last read it.
+        hipStream_t s2 = c->stream2;
+        hipEvent_t *evR = c->ev, *evV = c->ev + 2;
+        auto bank = [&](int k) { return (nck - 1 - k) & 1; };
+        int first2 = 1;
+        auto recompute = [&](int k) {
+            const int s0 = k * every, s1 = s0 + every < n_steps ? s0 + every : n_steps;
+            (void)hipMemcpyAsync(seg, c->ckpt + int64_t(k) * state, state * 8,
+                                 hipMemcpyDeviceToDevice, s2);
+            for (int s = s0; s < s1; ++s) {
+                tape_step(c, bank(k) * every + (s - s0), seg, dt[s], first2, s2);
+                first2 = 0;
+            }
+            (void)hipEventRecord(evR[bank(k)], s2);
+        };
+        (void)hipEventRecord(c->ev[4], c->stream);   // everything before this call
+        (void)hipStreamWaitEvent(s2, c->ev[4], 0);
+        if (c->tape_last)
+            (void)hipEventRecord(evR[0], c->stream);
+        else
+            recompute(nck - 1);
+        for (int k = nck - 1; k >= 0; --k) {
+            const int b = bank(k), s0 = k * every;
+            const int s1 = s0 + every < n_steps ? s0 + every : n_steps;
+            (void)hipStreamWaitEvent(c->stream, evR[b], 0);
+            if (k > 0) {
+                if (k + 1 < nck) (void)hipStreamWaitEvent(s2, evV[1 - b], 0);
+                recompute(k - 1);
+            }
+            for (int s = s1 - 1; s >= s0; --s)
+                back([&](double *in, double *out) {
+                    step_vjp_tape(c, b * every + (s - s0), dt[s], in, out);
+                });
+            (void)hipEventRecord(evV[b], c->stream);
+        }
+        c->tape_last = false;
+        if (cur != Ubar0)
+            (void)hipMemcpyAsync(Ubar0, cur, state * 8, hipMemcpyDeviceToDevice, c->stream);
+        return finish(c);
+    }
     for (int k = nck - 1; k >= 0; --k) {
         const int s0 = k * every, s1 = s0 + every < n_steps ? s0 + every : n_steps;
         if (T >= s1 - s0) {

@@ -134,6 +134,9 @@ def test_checkpointed_adjoint_matches_reference_and_step_chain(torch, oracle_mod
     assert np.array_equal(Ud.cpu().numpy(), U)            # the forward is the oracle's, bitwise
     W = np.random.default_rng(8).normal(size=U0.shape)
     g = s.adjoint_checkpoints(dts, 3, torch.tensor(W, device="cuda")).cpu().numpy()
+    # again: now the last segment is recomputed too (the forward's tape is used up)
+    g2 = s.adjoint_checkpoints(dts, 3, torch.tensor(W, device="cuda")).cpu().numpy()
+    assert np.array_equal(g, g2)
     chain = torch.tensor(W, device="cuda")
     for k in range(6, -1, -1):
         chain = s.step_vjp(torch.tensor(states[k], device="cuda"), dts[k], chain)
