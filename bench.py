@@ -232,6 +232,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=257, help="nodes per side")
     ap.add_argument("--order", default="morton", choices=["morton", "random", "lex"])
+    ap.add_argument("--renumber", action="store_true",
+                    help="the library renumbers the nodes along a Morton curve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched measurement")
     ap.add_argument("--batch-steps", type=int, default=100)
@@ -281,7 +283,7 @@ def main():
     log(f"mesh {mesh.n_nodes} nodes, {mesh.n_cells} cells in {time.perf_counter() - t:.1f} s")
     t = time.perf_counter()
     s = Solver(mesh, asynchronous=True, newton_max=args.newton_max,
-               staging=not args.no_staging, sell_sigma=args.sell_sigma)
+               staging=not args.no_staging, sell_sigma=args.sell_sigma, renumber=args.renumber)
     torch.cuda.synchronize()
     log(f"solver created: nnz {s.nnz}, {s.device_bytes / 2**30:.1f} GiB device, "
         f"{time.perf_counter() - t:.1f} s")
@@ -365,7 +367,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"mach3_3d_{args.n}^3_{args.order}",
                    "newton_max_iter": args.newton_max, "lds_staging": not args.no_staging,
-                   "sell_sigma": args.sell_sigma,
+                   "sell_sigma": args.sell_sigma, "renumbered": args.renumber,
                    "nodes": mesh.n_nodes, "nnz": s.nnz, "stages": stages,
                    "parallelism": "single GPU"},
         "roofline": roofline,

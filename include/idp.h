@@ -56,6 +56,14 @@ extern "C" {
                                    from memory instead of staging each row
                                    block's neighbourhood in LDS (same results,
                                    bit for bit; for tests and measurement)  */
+#define IDP_FLAG_RENUMBER 4     /* the library numbers the nodes along a
+                                   Morton curve of their coordinates (every
+                                   row keeps the caller's column order, so
+                                   results are bit for bit those without);
+                                   U and every export stay in the caller's
+                                   order.  For meshes numbered without
+                                   locality.  Single meshes: idp_create_batch
+                                   and the adjoint return IDP_ENOTSUP       */
 
 /* Parameters of the scheme.  gamma: ratio of specific heats (Section 2);
  * cfl: c_cfl of Section 3.3 (0 < cfl <= 1); limiter_passes: 1 or 2

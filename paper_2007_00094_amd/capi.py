@@ -24,6 +24,7 @@ IDP_ENOTSUP = -7
 IDP_EWAIT = -8
 IDP_FLAG_ASYNC = 1
 IDP_FLAG_NO_STAGING = 2
+IDP_FLAG_RENUMBER = 4
 IDP_SCHED_LAUNCHES = 1
 IDP_SCHED_PERSISTENT = 2
 

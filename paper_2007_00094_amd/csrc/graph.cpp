@@ -9,8 +9,10 @@
 namespace idp {
 
 static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
-                 const int64_t *cells, int sigma)
+                 const int64_t *cells, int sigma, const int32_t *key)
 {
+    // column order within a row: ascending key (the node id by default)
+    auto before = [key](int32_t a, int32_t b) { return key ? key[a] < key[b] : a < b; };
     const int nv = 1 << dim;
     g.dim = dim;
     g.nv = nv;
@@ -51,7 +53,7 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
                 const int64_t c = g.nc_list[q];
                 for (int b = 0; b < nv; ++b) cand.push_back(int32_t(cells[c * nv + b]));
             }
-            std::sort(cand.begin(), cand.end());
+            std::sort(cand.begin(), cand.end(), before);
             const int len = int(std::unique(cand.begin(), cand.end()) - cand.begin());
             g.row_ptr[i + 1] = len;
             maxlen = std::max(maxlen, len);
@@ -71,7 +73,7 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
                 const int64_t c = g.nc_list[q];
                 for (int b = 0; b < nv; ++b) cand.push_back(int32_t(cells[c * nv + b]));
             }
-            std::sort(cand.begin(), cand.end());
+            std::sort(cand.begin(), cand.end(), before);
             auto end = std::unique(cand.begin(), cand.end());
             std::copy(cand.begin(), end, g.col.begin() + g.row_ptr[i]);
         }
@@ -84,7 +86,7 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
         for (int64_t q = g.row_ptr[i]; q < g.row_ptr[i + 1]; ++q) {
             const int32_t j = g.col[q];
             auto b = g.col.begin() + g.row_ptr[j], e = g.col.begin() + g.row_ptr[j + 1];
-            auto it = std::lower_bound(b, e, int32_t(i));
+            auto it = std::lower_bound(b, e, int32_t(i), before);
             if (it == e || *it != i) { bad = 1; continue; }
             g.tpos[q] = it - g.col.begin();
         }
@@ -200,10 +202,10 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
 }
 
 int build_graph(HostGraph &g, int dim, int64_t n, int64_t ncells,
-                const int64_t *cells, int sigma)
+                const int64_t *cells, int sigma, const int32_t *key)
 {
     try {
-        return build(g, dim, n, ncells, cells, sigma);
+        return build(g, dim, n, ncells, cells, sigma, key);
     } catch (const std::bad_alloc &) {
         return IDP_ENOMEM;
     }
@@ -378,6 +380,37 @@ int concat_graphs(const std::vector<HostGraph> &parts, HostGraph &g, BatchLayout
     } catch (const std::bad_alloc &) {
         return IDP_ENOMEM;
     }
+}
+
+// Morton code: the coordinates scaled to 2^(63/dim) steps of their bounding
+// box, bits interleaved (x lowest)
+void morton_order(int dim, int64_t n, const double *coords, std::vector<int32_t> &order)
+{
+    const int bits = dim == 3 ? 21 : 31;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) {
+        lo[d] = hi[d] = n > 0 ? coords[d] : 0.0;
+        for (int64_t i = 1; i < n; ++i) {
+            lo[d] = std::min(lo[d], coords[i * dim + d]);
+            hi[d] = std::max(hi[d], coords[i * dim + d]);
+        }
+    }
+    const double top = double((uint64_t(1) << bits) - 1);
+    std::vector<uint64_t> code(size_t(n), 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t c = 0;
+        for (int d = 0; d < dim; ++d) {
+            const double w = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0;
+            const uint64_t q = uint64_t((coords[i * dim + d] - lo[d]) / w * top + 0.5);
+            for (int b = 0; b < bits; ++b) c |= ((q >> b) & 1u) << (b * dim + d);
+        }
+        code[size_t(i)] = c;
+    }
+    order.resize(size_t(n));
+    for (int64_t i = 0; i < n; ++i) order[size_t(i)] = int32_t(i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return code[size_t(a)] < code[size_t(b)]; });
 }
 
 }  // namespace idp

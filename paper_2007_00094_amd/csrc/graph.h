@@ -54,8 +54,15 @@ struct HostGraph {
 // Returns 0 or a negative idp error code (IDP_EINVAL for ids out of range,
 // IDP_ENOMEM).  cells is [ncells][2^dim] (int64 node ids).  Rows are sorted
 // by length within windows of sigma rows (a multiple of 64; 0: all rows).
+// The columns of a row ascend by key[j] (the node id itself if key is
+// null): a renumbered mesh passes each node's original id, so that every
+// row keeps the original column order.
 int build_graph(HostGraph &g, int dim, int64_t n, int64_t ncells,
-                const int64_t *cells, int sigma = 0);
+                const int64_t *cells, int sigma = 0, const int32_t *key = nullptr);
+
+// A numbering of the nodes along a Morton curve of their coordinates
+// (coords [n][dim]): order[k] = the node placed k-th (ties: by node id).
+void morton_order(int dim, int64_t n, const double *coords, std::vector<int32_t> &order);
 
 // Neighbourhoods of row blocks, for staging in LDS.  Block b holds the rows
 // of slices 4b .. 4b+3; its halo is the ascending set of the columns of

@@ -66,6 +66,11 @@ struct idp_ctx {
     idp::StageArgs P{};
     char *scal = nullptr;           // device block, see Scalars
     double *U1 = nullptr;
+    // IDP_FLAG_RENUMBER: the library's node k is the caller's node order[k];
+    // pos is the inverse (host and device); the state lives in Uint
+    std::vector<int32_t> order, pos;
+    int32_t *pos_dev = nullptr;
+    double *Uint = nullptr;
     // batches
     int ninst = 1;
     idp::BatchLayout lay;           // instance offsets (single mesh: one instance)
@@ -214,6 +219,28 @@ int status_code(int st)
     return IDP_OK;
 }
 
+// States between the caller's numbering and the library's (renumbered
+// contexts): to_internal: out[pos[i]] = in[i]; else out[i] = in[pos[i]].
+__global__ void k_permute(int64_t n, int nc, const int32_t *__restrict__ pos,
+                          const double *__restrict__ in, double *__restrict__ out,
+                          int to_internal)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t k = pos[i];
+    if (to_internal)
+        for (int r = 0; r < nc; ++r) out[k * nc + r] = in[i * nc + r];
+    else
+        for (int r = 0; r < nc; ++r) out[i * nc + r] = in[k * nc + r];
+}
+
+void permute(idp_ctx *c, const double *in, double *out, int to_internal)
+{
+    const int nc = c->prm.dim + 2;
+    hipLaunchKernelGGL(k_permute, dim3(unsigned((c->n + 255) / 256)), dim3(256), 0, c->stream,
+                       c->n, nc, c->pos_dev, in, out, to_internal);
+}
+
 // One forward-Euler stage on the context stream.
 //  in: stage input state; U0: step-initial state; out: destination;
 //  tau_mode: 1 select tau (stage 1), 0 check the held tau, 2 use dt_in.
@@ -333,7 +360,40 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
     int64_t n_cells = meshes[0].n_cells;
     int rc = IDP_OK;
     try {
-        if (K == 1) {
+        if (K == 1 && (p.flags & IDP_FLAG_RENUMBER)) {
+            // nodes numbered along a Morton curve; rows keep the caller's
+            // column order (key = the caller's id), so the sums run as before
+            const int64_t n = meshes[0].n_nodes;
+            for (int64_t t = 0; t < n_cells * nv; ++t)
+                if (cells[t] < 0 || cells[t] >= n) rc = IDP_EINVAL;
+            if (rc == IDP_OK) {
+                idp::morton_order(dim, n, coords, c->order);
+                c->pos.assign(size_t(n), 0);
+                for (int64_t k = 0; k < n; ++k) c->pos[size_t(c->order[size_t(k)])] = int32_t(k);
+                cells_all.resize(size_t(n_cells) * nv);
+                for (int64_t t = 0; t < n_cells * nv; ++t)
+                    cells_all[size_t(t)] = c->pos[size_t(cells[t])];
+                coords_all.resize(size_t(n) * dim);
+                for (int64_t k = 0; k < n; ++k)
+                    for (int d = 0; d < dim; ++d)
+                        coords_all[size_t(k) * dim + d] = coords[int64_t(c->order[size_t(k)]) * dim + d];
+                if (dirichlet) {
+                    hold_all.resize(size_t(n));
+                    for (int64_t k = 0; k < n; ++k) hold_all[size_t(k)] = dirichlet[c->order[size_t(k)]];
+                    dirichlet = hold_all.data();
+                }
+                cells = cells_all.data();
+                coords = coords_all.data();
+                rc = idp::build_graph(g, dim, n, n_cells, cells, p.sell_sigma, c->order.data());
+            }
+            auto &L = c->lay;
+            L.node = {0, g.n};
+            L.cell = {0, g.ncells};
+            L.nnz = {0, g.nnz};
+            L.slice = {0, g.nslices};
+            L.sell = {0, g.sell_size};
+            L.pair = {0, g.npairs};
+        } else if (K == 1) {
             rc = idp::build_graph(g, dim, meshes[0].n_nodes, n_cells, cells, p.sell_sigma);
             auto &L = c->lay;
             L.node = {0, g.n};
@@ -541,10 +601,34 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
         }
         if (herr) { idp_destroy(c); return IDP_EMESH; }
     }
-    // keep what the CSR exports need, drop the rest of the host graph
-    c->row_ptr.swap(g.row_ptr);
-    c->col.swap(g.col);
-    c->sell_of_csr.swap(g.sell_of_csr);
+    // keep what the CSR exports need (in the caller's numbering), drop the
+    // rest of the host graph
+    if (!c->pos.empty()) {
+        const int64_t n = g.n;
+        c->row_ptr.assign(size_t(n) + 1, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t k = c->pos[size_t(i)];
+            c->row_ptr[size_t(i) + 1] = c->row_ptr[size_t(i)] + (g.row_ptr[k + 1] - g.row_ptr[k]);
+        }
+        c->col.resize(size_t(g.nnz));
+        c->sell_of_csr.resize(size_t(g.nnz));
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t k = c->pos[size_t(i)], q0 = c->row_ptr[size_t(i)];
+            for (int64_t q = g.row_ptr[k]; q < g.row_ptr[k + 1]; ++q) {
+                c->col[size_t(q0 + q - g.row_ptr[k])] = c->order[size_t(g.col[q])];
+                c->sell_of_csr[size_t(q0 + q - g.row_ptr[k])] = g.sell_of_csr[q];
+            }
+        }
+        TRY(dalloc(c, &c->pos_dev, n));
+        TRY(dalloc(c, &c->Uint, n * (dim + 2)));
+        HIPTRY(hipMemcpyAsync(c->pos_dev, c->pos.data(), size_t(n) * 4, hipMemcpyHostToDevice,
+                              c->stream));
+        HIPTRY(hipStreamSynchronize(c->stream));
+    } else {
+        c->row_ptr.swap(g.row_ptr);
+        c->col.swap(g.col);
+        c->sell_of_csr.swap(g.sell_of_csr);
+    }
 #undef TRY
 #undef HIPTRY
     *out = c;
@@ -578,6 +662,7 @@ int idp_create_batch(idp_ctx **out, const idp_params *prm, int n_inst,
     *out = nullptr;
     const int rc = check_params(*prm);
     if (rc != IDP_OK) return rc;
+    if (prm->flags & IDP_FLAG_RENUMBER) return IDP_ENOTSUP;   // single meshes only
     std::vector<MeshIn> meshes;
     try {
         meshes.resize(n_inst);
@@ -598,12 +683,18 @@ int idp_step(idp_ctx *c, double *U, double dt, double *dt_used)
     if (c->ninst != 1) return IDP_ENOTSUP;
     const bool async = (c->prm.flags & IDP_FLAG_ASYNC) != 0;
     double *U1 = c->U1;
+    double *const Uc = U;   // the caller's array
+    if (c->pos_dev) {
+        permute(c, Uc, c->Uint, 1);
+        U = c->Uint;
+    }
     // stage 1: U1 = E(U^n), tau selected (or checked) from the stage-1 bound
     stage(c, U, U, U1, 1, 1, dt, 1, async ? 0 : 1);
     // stage 2: U2 = U^n + 1/4 (E(U1) - U^n), written over U1
     stage(c, U1, U, U1, 2, 0, 0.0, 0, 0);
     // stage 3: U^{n+1} = U^n + 2/3 (E(U2) - U^n), written over U
     stage(c, U1, U, U, 3, 0, 0.0, 0, 0);
+    if (c->pos_dev) permute(c, U, Uc, 0);   // unchanged if the step refused
     if (hipGetLastError() != hipSuccess) return IDP_EHIP;
     if (async) return IDP_OK;
     Scalars h{};
@@ -619,7 +710,13 @@ int idp_euler_stage(idp_ctx *c, const double *U, double tau, double *Uout)
     if (!c || !U || !Uout || !(tau > 0.0) || !std::isfinite(tau) || U == Uout)
         return IDP_EINVAL;
     if (c->ninst != 1) return IDP_ENOTSUP;
-    stage(c, U, U, Uout, 0, 2, tau, 1, 1);
+    if (c->pos_dev) {
+        permute(c, U, c->Uint, 1);
+        stage(c, c->Uint, c->Uint, c->U1, 0, 2, tau, 1, 1);
+        permute(c, c->U1, Uout, 0);
+    } else {
+        stage(c, U, U, Uout, 0, 2, tau, 1, 1);
+    }
     Scalars h{};
     int rc = read_scalars(c, &h);
     if (rc != IDP_OK) return rc;
@@ -658,6 +755,10 @@ int idp_max_dt(idp_ctx *c, const double *U, double *dt_out)
 {
     if (!c || !U || !dt_out) return IDP_EINVAL;
     if (c->ninst != 1) return IDP_ENOTSUP;
+    if (c->pos_dev) {
+        permute(c, U, c->Uint, 1);
+        return max_dt_all(c, c->Uint, dt_out);
+    }
     return max_dt_all(c, U, dt_out);
 }
 
@@ -719,8 +820,10 @@ static int node_to_host(idp_ctx *c, const double *dev, int dev_stride, int off, 
         return IDP_EHIP;
     int rc = sync(c);
     if (rc != IDP_OK) return rc;
-    for (int64_t i = 0; i < c->n; ++i)
-        for (int k = 0; k < count; ++k) host[i * count + k] = tmp[i * dev_stride + off + k];
+    for (int64_t i = 0; i < c->n; ++i) {
+        const int64_t j = c->pos.empty() ? i : c->pos[size_t(i)];
+        for (int k = 0; k < count; ++k) host[i * count + k] = tmp[j * dev_stride + off + k];
+    }
     return IDP_OK;
 }
 
@@ -845,7 +948,7 @@ int adj_setup(idp_ctx *c)
 
 int adj_check(idp_ctx *c)
 {
-    if (c->ninst != 1 || c->prm.newton_max_iter > 8) return IDP_ENOTSUP;
+    if (c->ninst != 1 || c->prm.newton_max_iter > 8 || c->pos_dev) return IDP_ENOTSUP;
     return adj_setup(c);
 }
 

@@ -84,6 +84,9 @@ def test_create_batch_rejects_bad_arguments_before_any_device_call():
     nn = (C.c_int64 * 1)(4)
     nc = (C.c_int64 * 1)(1)
     assert L.idp_create_batch(C.byref(h), C.byref(p), 0, nn, co, nc, ce, None, None) == capi.IDP_EINVAL
+    p.flags = capi.IDP_FLAG_RENUMBER   # single meshes only
+    assert L.idp_create_batch(C.byref(h), C.byref(p), 1, nn, co, nc, ce, None, None) == capi.IDP_ENOTSUP
+    p.flags = 0
     assert L.idp_create_batch(None, C.byref(p), 1, nn, co, nc, ce, None, None) == capi.IDP_EINVAL
     assert L.idp_create_batch(C.byref(h), C.byref(p), 1, None, co, nc, ce, None, None) == capi.IDP_EINVAL
     bad = (C.c_int64 * 1)(0)

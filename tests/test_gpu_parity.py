@@ -256,6 +256,45 @@ def test_single_cell_mesh(torch, oracle_mod, dim):
     s.close()
 
 
+@pytest.mark.parametrize("dim,n", [(2, 33), (3, 17)])
+def test_renumbered_context_is_bitwise_the_plain_one(torch, oracle_mod, dim, n):
+    """IDP_FLAG_RENUMBER on a randomly numbered mesh: steps, max_dt, a stage,
+    every debug export and the matrices bit for bit those of the plain
+    context (and the oracle's), all in the caller's numbering."""
+    announce(f"renumbered context dim={dim} n={n} random order")
+    from paper_2007_00094_amd.solver import Solver
+    mesh = inputs.q1_grid(n, dim, 0.2, seed=5, order="random")
+    U0 = inputs.ic_four_quadrant(mesh.coords) if dim == 2 else inputs.ic_sphere(mesh.coords)
+    a, b = Solver(mesh), Solver(mesh, renumber=True)
+    assert a.nnz == b.nnz
+    assert a.max_dt(torch.tensor(U0, device="cuda")) == b.max_dt(torch.tensor(U0, device="cuda"))
+    Ma, Mb = a.matrices(), b.matrices()
+    for k in Ma:
+        assert np.array_equal(Ma[k], Mb[k]), k
+    tau = a.max_dt(torch.tensor(U0, device="cuda"))
+    Ea, _ = a.euler_stage(torch.tensor(U0, device="cuda"), tau)
+    Eb, _ = b.euler_stage(torch.tensor(U0, device="cuda"), tau)
+    assert np.array_equal(Ea.cpu().numpy(), Eb.cpu().numpy())
+    for what in (capi.IDP_DBG_D, capi.IDP_DBG_ALPHA, capi.IDP_DBG_R, capi.IDP_DBG_UL,
+                 capi.IDP_DBG_BOUNDS, capi.IDP_DBG_L1, capi.IDP_DBG_L2, capi.IDP_DBG_UPASS,
+                 capi.IDP_DBG_TAUI):
+        assert np.array_equal(a.debug(what), b.debug(what)), what
+    o = oracle_mod.Oracle(mesh, dirichlet=mesh.boundary)
+    Ua, Ub, Uo = torch.tensor(U0, device="cuda"), torch.tensor(U0, device="cuda"), U0.copy()
+    for _ in range(3):
+        dta, sta = a.step(Ua)
+        dtb, stb = b.step(Ub)
+        Uo, dto, sto = o.step(Uo)
+        assert dta == dtb == dto and sta == stb == sto
+        assert np.array_equal(Ub.cpu().numpy(), Uo)
+    assert np.array_equal(Ua.cpu().numpy(), Ub.cpu().numpy())
+    with pytest.raises(capi.IdpError) as ei:
+        b.euler_stage_vjp(Ub, tau, torch.zeros_like(Ub))
+    assert ei.value.code == capi.IDP_ENOTSUP
+    a.close()
+    b.close()
+
+
 def test_determinism(torch):
     announce("determinism: two runs, sphere 3D 13^3")
     mesh = inputs.q1_grid(13, 3, 0.2, seed=0, order="random")
