@@ -62,8 +62,8 @@ extern "C" {
                                    results are bit for bit those without);
                                    U and every export stay in the caller's
                                    order.  For meshes numbered without
-                                   locality.  Single meshes: idp_create_batch
-                                   and the adjoint return IDP_ENOTSUP       */
+                                   locality.  Single meshes only
+                                   (idp_create_batch returns IDP_ENOTSUP)  */
 
 /* Parameters of the scheme.  gamma: ratio of specific heats (Section 2);
  * cfl: c_cfl of Section 3.3 (0 < cfl <= 1); limiter_passes: 1 or 2

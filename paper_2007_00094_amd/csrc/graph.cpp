@@ -157,7 +157,8 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
                 g.stpos[e] = int32_t(e);
         }
     }
-    // pairs: the entries (i, j) with j > i, slice by slice in SELL order
+    // pairs: the entries (i, j) with j after i in the column order (j > i,
+    // or key[j] > key[i]), slice by slice in SELL order
     {
         std::vector<int64_t> cnt(g.nslices + 1, 0);
 #pragma omp parallel for schedule(static)
@@ -168,7 +169,7 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
                     const int64_t r = s * kSellC + lane;
                     const int32_t i = g.perm[r];
                     if (i < 0 || k >= g.row_len[r]) continue;
-                    if (g.scol[g.slice_off[s] + int64_t(k) * kSellC + lane] > i) ++c;
+                    if (before(i, g.scol[g.slice_off[s] + int64_t(k) * kSellC + lane])) ++c;
                 }
             cnt[s + 1] = c;
         }
@@ -189,7 +190,7 @@ static int build(HostGraph &g, int dim, int64_t n, int64_t ncells,
                     if (i < 0 || k >= g.row_len[r]) continue;
                     const int64_t e = g.slice_off[s] + int64_t(k) * kSellC + lane;
                     const int32_t j = g.scol[e];
-                    if (j <= i) continue;
+                    if (!before(i, j)) continue;
                     g.pair_e[p] = int32_t(e);
                     g.pair_t[p] = g.stpos[e];
                     g.pair_i[p] = i;

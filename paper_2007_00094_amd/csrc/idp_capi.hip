@@ -71,6 +71,7 @@ struct idp_ctx {
     std::vector<int32_t> order, pos;
     int32_t *pos_dev = nullptr;
     double *Uint = nullptr;
+    double *Pa = nullptr, *Pb = nullptr;   // the adjoint's caller arrays, renumbered
     // batches
     int ninst = 1;
     idp::BatchLayout lay;           // instance offsets (single mesh: one instance)
@@ -917,6 +918,10 @@ int adj_setup(idp_ctx *c)
     int e = IDP_OK;
 #define ADJ_ALLOC(ptr, count) if ((e = dalloc(c, &(ptr), (count))) != IDP_OK) return e
     ADJ_ALLOC(c->Ebp, n * idp::kEbS);
+    if (c->pos_dev) {
+        ADJ_ALLOC(c->Pa, n * nc);
+        ADJ_ALLOC(c->Pb, n * nc);
+    }
     ADJ_ALLOC(A.Upb, n * idp::kUpS);
     ADJ_ALLOC(A.Nrec, n * idp::kNS);
     ADJ_ALLOC(A.Irec, n * idp::kIS);
@@ -948,7 +953,7 @@ int adj_setup(idp_ctx *c)
 
 int adj_check(idp_ctx *c)
 {
-    if (c->ninst != 1 || c->prm.newton_max_iter > 8 || c->pos_dev) return IDP_ENOTSUP;
+    if (c->ninst != 1 || c->prm.newton_max_iter > 8) return IDP_ENOTSUP;
     return adj_setup(c);
 }
 
@@ -1146,6 +1151,14 @@ int idp_euler_stage_vjp(idp_ctx *c, const double *U, double tau, const double *E
         return IDP_EINVAL;
     int rc = adj_check(c);
     if (rc != IDP_OK) return rc;
+    if (c->pos_dev) {   // in the library's numbering, then back
+        permute(c, U, c->Uint, 1);
+        permute(c, Ebar, c->Pa, 1);
+        idp::launch_adj_pad(c->stream, c->n, c->prm.dim + 2, c->Pa, c->Ebp);
+        stage_vjp(c, c->Uint, tau, c->Ebp, c->Pb, 1);
+        permute(c, c->Pb, Ubar, 0);
+        return finish(c);
+    }
     idp::launch_adj_pad(c->stream, c->n, c->prm.dim + 2, Ebar, c->Ebp);
     stage_vjp(c, U, tau, c->Ebp, Ubar, 1);
     return finish(c);
@@ -1157,6 +1170,13 @@ int idp_step_vjp(idp_ctx *c, const double *U, double dt, const double *Ubar_next
         return IDP_EINVAL;
     int rc = adj_check(c);
     if (rc != IDP_OK) return rc;
+    if (c->pos_dev) {
+        permute(c, U, c->Uint, 1);
+        permute(c, Ubar_next, c->Pa, 1);
+        step_vjp(c, c->Uint, dt, c->Pa, c->Pb, 1);
+        permute(c, c->Pb, Ubar, 0);
+        return finish(c);
+    }
     step_vjp(c, U, dt, Ubar_next, Ubar, 1);
     return finish(c);
 }
@@ -1189,7 +1209,23 @@ int idp_debug_adjoint(idp_ctx *c, int what, double *out)
     }
 }
 
+static int forward_checkpoints(idp_ctx *c, double *U, int n_steps, const double *dt, int every);
+
 int idp_forward_checkpoints(idp_ctx *c, double *U, int n_steps, const double *dt, int every)
+{
+    if (!c || !U || !dt || n_steps < 1 || every < 1) return IDP_EINVAL;
+    if (!c->pos_dev) return forward_checkpoints(c, U, n_steps, dt, every);
+    int rc = adj_check(c);   // allocates nothing twice; the buffers below need it
+    if (rc != IDP_OK) return rc;
+    permute(c, U, c->Uint, 1);
+    rc = forward_checkpoints(c, c->Uint, n_steps, dt, every);
+    if (rc < 0) return rc;
+    permute(c, c->Uint, U, 0);
+    const int rc2 = finish(c);
+    return rc2 < 0 ? rc2 : rc;
+}
+
+static int forward_checkpoints(idp_ctx *c, double *U, int n_steps, const double *dt, int every)
 {
     if (!c || !U || !dt || n_steps < 1 || every < 1) return IDP_EINVAL;
     for (int s = 0; s < n_steps; ++s)
@@ -1233,8 +1269,25 @@ int idp_forward_checkpoints(idp_ctx *c, double *U, int n_steps, const double *dt
     return rc;
 }
 
+static int adjoint_checkpoints(idp_ctx *c, int n_steps, const double *dt, int every,
+                               const double *Ubar_final, double *Ubar0);
+
 int idp_adjoint_checkpoints(idp_ctx *c, int n_steps, const double *dt, int every,
                             const double *Ubar_final, double *Ubar0)
+{
+    if (!c || !dt || !Ubar_final || !Ubar0 || n_steps < 1 || every < 1) return IDP_EINVAL;
+    if (!c->pos_dev) return adjoint_checkpoints(c, n_steps, dt, every, Ubar_final, Ubar0);
+    if (!c->Pa) return IDP_EINVAL;   // no forward_checkpoints yet
+    permute(c, Ubar_final, c->Pa, 1);
+    const int rc = adjoint_checkpoints(c, n_steps, dt, every, c->Pa, c->Pb);
+    if (rc < 0) return rc;
+    permute(c, c->Pb, Ubar0, 0);
+    const int rc2 = finish(c);
+    return rc2 < 0 ? rc2 : rc;
+}
+
+static int adjoint_checkpoints(idp_ctx *c, int n_steps, const double *dt, int every,
+                               const double *Ubar_final, double *Ubar0)
 {
     if (!c || !dt || !Ubar_final || !Ubar0 || n_steps < 1 || every < 1) return IDP_EINVAL;
     if (n_steps != c->ck_steps || every != c->ck_every) return IDP_EINVAL;

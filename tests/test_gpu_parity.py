@@ -259,8 +259,9 @@ def test_single_cell_mesh(torch, oracle_mod, dim):
 @pytest.mark.parametrize("dim,n", [(2, 33), (3, 17)])
 def test_renumbered_context_is_bitwise_the_plain_one(torch, oracle_mod, dim, n):
     """IDP_FLAG_RENUMBER on a randomly numbered mesh: steps, max_dt, a stage,
-    every debug export and the matrices bit for bit those of the plain
-    context (and the oracle's), all in the caller's numbering."""
+    every debug export, the matrices and the adjoint entry points bit for
+    bit those of the plain context (and the oracle's), all in the caller's
+    numbering."""
     announce(f"renumbered context dim={dim} n={n} random order")
     from paper_2007_00094_amd.solver import Solver
     mesh = inputs.q1_grid(n, dim, 0.2, seed=5, order="random")
@@ -288,9 +289,19 @@ def test_renumbered_context_is_bitwise_the_plain_one(torch, oracle_mod, dim, n):
         assert dta == dtb == dto and sta == stb == sto
         assert np.array_equal(Ub.cpu().numpy(), Uo)
     assert np.array_equal(Ua.cpu().numpy(), Ub.cpu().numpy())
-    with pytest.raises(capi.IdpError) as ei:
-        b.euler_stage_vjp(Ub, tau, torch.zeros_like(Ub))
-    assert ei.value.code == capi.IDP_ENOTSUP
+    # the adjoint entry points in the caller's numbering, bit for bit
+    W = torch.tensor(np.random.default_rng(9).normal(size=U0.shape), device="cuda")
+    U = torch.tensor(U0, device="cuda")
+    assert np.array_equal(a.euler_stage_vjp(U, tau, W).cpu().numpy(),
+                          b.euler_stage_vjp(U, tau, W).cpu().numpy())
+    assert np.array_equal(a.step_vjp(U, tau, W).cpu().numpy(), b.step_vjp(U, tau, W).cpu().numpy())
+    dts = [0.5 * tau] * 5
+    Va, Vb = torch.tensor(U0, device="cuda"), torch.tensor(U0, device="cuda")
+    a.forward_checkpoints(Va, dts, 2)
+    b.forward_checkpoints(Vb, dts, 2)
+    assert np.array_equal(Va.cpu().numpy(), Vb.cpu().numpy())
+    assert np.array_equal(a.adjoint_checkpoints(dts, 2, W).cpu().numpy(),
+                          b.adjoint_checkpoints(dts, 2, W).cpu().numpy())
     a.close()
     b.close()
 
