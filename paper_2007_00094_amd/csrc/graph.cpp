@@ -404,7 +404,7 @@ void morton_order(int dim, int64_t n, const double *coords, std::vector<int32_t>
         for (int d = 0; d < dim; ++d) {
             const double w = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0;
             const double x = (coords[i * dim + d] - lo[d]) / w * top + 0.5;
-            const uint64_t q = x >= 0.0 && x <= top ? uint64_t(x) : 0;   // NaN: 0
+            const uint64_t q = x >= 0.0 ? (x < top ? uint64_t(x) : uint64_t(top)) : 0;  // NaN: 0
             for (int b = 0; b < bits; ++b) c |= ((q >> b) & 1u) << (b * dim + d);
         }
         code[size_t(i)] = c;
