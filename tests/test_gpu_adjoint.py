@@ -151,6 +151,10 @@ def test_checkpointed_adjoint_matches_reference_and_step_chain(torch, oracle_mod
 
 
 def test_adjoint_matches_central_differences_on_smooth_directions(torch):
+    """Along directions whose difference quotients agree between eps 1e-7
+    and 1e-8 to 1e-7 (no limiter or bound decision flips between the
+    +-eps runs) the adjoint matches them to 1e-6; along the others to 1e-6
+    plus twice that spread (spread above 1e-5: no check)."""
     announce("flow_blobs_3d_17, 5 steps: gradient of the box kinetic energy vs central "
              "differences of the GPU forward")
     from paper_2007_00094_amd.autograd import ssprk3
@@ -182,7 +186,7 @@ def test_adjoint_matches_central_differences_on_smooth_directions(torch):
 
     rng = np.random.default_rng(11)
     smooth = 0
-    for _ in range(4):
+    for _ in range(8):
         v = np.zeros(m.n_nodes)
         for _ in range(2):
             c = rng.uniform(0.3, 0.7, size=3)
@@ -193,10 +197,15 @@ def test_adjoint_matches_central_differences_on_smooth_directions(torch):
             return (Jrun(U0[:, 0] + eps * v) - Jrun(U0[:, 0] - eps * v)) / (2 * eps)
 
         f7, f8 = fd(1e-7), fd(1e-8)
-        if abs(f7 - f8) > 1e-5 * abs(f7):
-            continue
-        smooth += 1
-        assert abs(g @ v - f7) <= 2e-5 * abs(f7), (g @ v, f7)
+        rel, spread = abs(g @ v - f7) / abs(f7), abs(f7 - f8) / abs(f7)
+        print(f"  adjoint {g @ v:.12e} fd(1e-7) {f7:.12e} fd(1e-8) {f8:.12e} "
+              f"rel {rel:.2e} spread {spread:.2e}", flush=True)
+        if spread <= 1e-7:
+            # no decision flipped between the +-eps runs: the 1e-6 target
+            smooth += 1
+            assert rel <= 1e-6, (g @ v, f7)
+        elif spread <= 1e-5:
+            assert rel <= 1e-6 + 2 * spread, (g @ v, f7)
     assert smooth >= 2
 
 
