@@ -72,6 +72,10 @@ class Reference:
         self.To = where_off[torch.tensor(tpos)[eo]]      # transposed off-diagonal entry
         self.co = self.cij[eo]
         self.cto = self.cij[torch.tensor(tpos)[eo]]     # c_ji
+        # c_ij + c_ji is the boundary integral of phi_i phi_j n: zero up to
+        # rounding unless both nodes lie on the boundary
+        self.mirror = (torch.abs(self.co + self.cto).sum(1)
+                       <= 2.0 ** -36 * (torch.abs(self.co) + torch.abs(self.cto)).sum(1))
         self.mo = mij[eo]
         if dirichlet is None:
             dirichlet = np.zeros(o.n, dtype=bool)
@@ -206,7 +210,9 @@ class Reference:
         nji = self.cto / _safe(aji, aji > 0)[:, None]
         t1 = torch.where(aij > 0, self.lambda_max(nij, A, A, Io, Jo) * aij, torch.zeros_like(aij))
         t2 = torch.where(aji > 0, self.lambda_max(nji, A, A, Jo, Io) * aji, torch.zeros_like(aji))
-        d = torch.where(t1 > t2, t1, t2)
+        # where c_ji = -c_ij the two problems mirror each other: the pair's
+        # lower node id gives the one orientation evaluated
+        d = torch.where(self.mirror, torch.where(Io < Jo, t1, t2), torch.where(t1 > t2, t1, t2))
         # step 2: indicator over all j in I(i) (Section 3.8)
         mc = (A["m"][J] * self.cij).sum(1)
         a = torch.zeros(n, dtype=_T).index_add(0, I, (A["er"][J] - A["er"][I]) * mc)

@@ -587,12 +587,28 @@ ora_t *ora_create(int dim, double gamma, double cfl, int passes,
 }
 
 /* ------------------------------------------------- forward Euler stage */
+/* Whether a pair's coefficients are opposite: c_ij + c_ji is the boundary
+ * integral of phi_i phi_j n (zero whenever i or j is an interior node),
+ * so the test separates pairs where it vanishes, whose assembled sum is
+ * rounding noise, from boundary pairs, where it is of the size of c_ij:
+ * sum_k |c_ij,k + c_ji,k| <= 2^-36 sum_k (|c_ij,k| + |c_ji,k|).          */
+static int ora_mirror_pair(const double *cij, const double *cji, int dim)
+{
+    double s = 0.0, m = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        s += fabs(cij[k] + cji[k]);
+        m += fabs(cij[k]) + fabs(cji[k]);
+    }
+    return s <= 0x1p-36 * m;
+}
+
 static void stage_viscosity(ora_t *o, const double *U)
 {
     const int dim = o->dim, nc = o->nc;
     const double g = o->gamma;
     /* Steps 1 and 2 of Alg. 1: d_ij for j != i (both orientations, the
-     * larger wins), d_ii = -sum, alpha_i, tau_i = m_i/(-2 d_ii).          */
+     * larger wins; one where they mirror each other), d_ii = -sum,
+     * alpha_i, tau_i = m_i/(-2 d_ii).                                     */
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < o->n; ++i) {
         const double *Ui = U + i * nc;
@@ -608,15 +624,29 @@ static void stage_viscosity(ora_t *o, const double *U)
             for (int k = 0; k < dim; ++k) { aij += cij[k] * cij[k]; aji += cji[k] * cji[k]; }
             aij = sqrt(aij); aji = sqrt(aji);
             double t1 = 0.0, t2 = 0.0;
-            if (aij > 0.0) {
-                double inv = 1.0 / aij;
-                for (int k = 0; k < dim; ++k) nij[k] = cij[k] * inv;
-                t1 = ora_lambda_max(nij, Ui, Uj, dim, g, NULL) * aij;
-            }
-            if (aji > 0.0) {
-                double inv = 1.0 / aji;
-                for (int k = 0; k < dim; ++k) nji[k] = cji[k] * inv;
-                t2 = ora_lambda_max(nji, Uj, Ui, dim, g, NULL) * aji;
+            if (ora_mirror_pair(cij, cji, dim)) {
+                /* c_ji = -c_ij: the problem (n_ji, U_j, U_i) mirrors
+                 * (n_ij, U_i, U_j) and has the same bound; the pair's
+                 * lower node id gives the orientation evaluated.          */
+                const double *ca = i < j ? cij : cji;
+                const double *Ua = i < j ? Ui : Uj, *Ub = i < j ? Uj : Ui;
+                const double a = i < j ? aij : aji;
+                if (a > 0.0) {
+                    double inv = 1.0 / a;
+                    for (int k = 0; k < dim; ++k) nij[k] = ca[k] * inv;
+                    t1 = ora_lambda_max(nij, Ua, Ub, dim, g, NULL) * a;
+                }
+            } else {
+                if (aij > 0.0) {
+                    double inv = 1.0 / aij;
+                    for (int k = 0; k < dim; ++k) nij[k] = cij[k] * inv;
+                    t1 = ora_lambda_max(nij, Ui, Uj, dim, g, NULL) * aij;
+                }
+                if (aji > 0.0) {
+                    double inv = 1.0 / aji;
+                    for (int k = 0; k < dim; ++k) nji[k] = cji[k] * inv;
+                    t2 = ora_lambda_max(nji, Uj, Ui, dim, g, NULL) * aji;
+                }
             }
             double d = t1 > t2 ? t1 : t2;
             o->dij[q] = d;

@@ -3,7 +3,8 @@
 // One forward-Euler stage of Alg. 1 is a node kernel, four row sweeps over
 // the SELL-64 stencil layout and three sweeps over the unordered pairs:
 //   k_node    step 0   per node: p, c, eta/rho, v = m/rho, phi   (pack A)
-//   k_dpair   step 1   per pair: d_ij = d_ji (both orientations, the larger)
+//   k_dpair   step 1   per pair: d_ij = d_ji (both orientations, the larger;
+//                       one where c_ji = -c_ij makes them mirror images)
 //   k_diag    step 2   per row: d_ii, tau_i, min tau; indicator alpha_i
 //   k_low     step 3   per row: R_i, U^L_i, bounds rho_min, rho_max, phi_min
 //   k_lim1p   step 4   per pair: P_ij, P_ji (eq. def-p), l_ij, l_ji (Alg. 2),
@@ -300,6 +301,21 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
     }
     aij = sqrt(aij);
     aji = sqrt(aji);
+    // c_ij + c_ji integrates phi_i phi_j n over the boundary: it vanishes
+    // (up to rounding) unless both nodes are boundary nodes, and then the
+    // reversed problem (n_ji, U_j, U_i) mirrors (n_ij, U_i, U_j) and has
+    // the same bound; the pair's orientation (lower caller id first) is
+    // the one evaluated
+    bool mirror;
+    {
+        double s = 0.0, m = 0.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            s += fabs(c[q] + ct[q]);
+            m += fabs(c[q]) + fabs(ct[q]);
+        }
+        mirror = s <= 0x1p-36 * m;
+    }
     double t1 = 0.0, t2 = 0.0;
     // the psi_branch terms of the two states serve both orientations
     const double S = (aij > 0.0 || aji > 0.0)
@@ -312,7 +328,7 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
         for (int q = 0; q < D; ++q) nn[q] = c[q] * inv;
         t1 = lambda_max_s<D>(nn, Ai, Ai[NC], Ai[NC + 1], Aj, Aj[NC], Aj[NC + 1], S, P.gas) * aij;
     }
-    if (aji > 0.0) {
+    if (!mirror && aji > 0.0) {
         const double inv = 1.0 / aji;
         double nn[D];
 #pragma unroll
@@ -323,7 +339,7 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
     P.d[e] = dd;
     P.d[t] = dd;
     if (P.sided) P.dp[p_] = dd;   // pair order: read by the stage adjoint only
-    if (P.sided) P.sided[p_] = t1 > t2;
+    if (P.sided) P.sided[p_] = mirror || t1 > t2;
 }
 
 // --------------------------------------------------------- row diagonal

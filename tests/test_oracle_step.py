@@ -129,6 +129,46 @@ def _stage_setup(oracle_mod, name, n, order="lex", hold=False):
     return mesh, U, oracle_mod.Oracle(mesh, dirichlet=d)
 
 
+@pytest.mark.parametrize("name,n", [("four_quadrant", 11), ("mach3", 6)])
+def test_viscosity_is_the_larger_orientation(oracle_mod, name, n):
+    """d_ij = max(lambda(n_ij, U_i, U_j)|c_ij|, lambda(n_ji, U_j, U_i)|c_ji|)
+    (Section 3.3) on a jittered mesh in random order with a non-uniform
+    state, from the pointwise wave-speed bound.  Where c_ji = -c_ij (every
+    pair not sharing a boundary face) the two terms are mirror images and
+    one is evaluated: equal to rounding.  The test that finds those pairs,
+    |c_ij + c_ji|_1 <= 2^-36 (|c_ij|_1 + |c_ji|_1), must agree with the
+    geometry: the sum is rounding noise off the boundary faces and of the
+    size of c_ij on them."""
+    mesh, U, o = _stage_setup(oracle_mod, name, n, order="random")
+    o.max_dt(U)
+    rp, col, d, cij, tp = o.row_ptr(), o.col(), o.d_ij(), o.c_ij(), o.tpos()
+    ijk = mesh.grid_ijk()
+    dim = mesh.dim
+    lo_gap, hi_gap = 0.0, np.inf
+    for i in range(o.n):
+        for q in range(rp[i], rp[i + 1]):
+            j = col[q]
+            if j == i:
+                continue
+            cji = cij[tp[q]]
+            ratio = (np.abs(cij[q] + cji).sum()
+                     / (np.abs(cij[q]).sum() + np.abs(cji).sum()))
+            face = any(ijk[i, k] == ijk[j, k] and ijk[i, k] in (0, n - 1)
+                       for k in range(dim))
+            if face:
+                hi_gap = min(hi_gap, ratio)
+            else:
+                lo_gap = max(lo_gap, ratio)
+            best = 0.0
+            for cc, a, b in ((cij[q], U[i], U[j]), (cji, U[j], U[i])):
+                nrm = np.linalg.norm(cc)
+                if nrm > 0:
+                    lam, _ = oracle_mod.lambda_max(cc / nrm, a, b)
+                    best = max(best, lam * nrm)
+            assert abs(d[q] - best) <= 1e-13 * best, (i, j, d[q], best)
+    assert lo_gap <= 1e-13 and hi_gap >= 1e-3, (lo_gap, hi_gap)
+
+
 @pytest.mark.parametrize("name,n", [("four_quadrant", 21), ("sphere", 9), ("mach3", 9)])
 def test_stage_flux_balance(oracle_mod, name, n):
     """Conservation: with d, l symmetric and P skew, a stage changes the
