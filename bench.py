@@ -23,12 +23,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP64_PEAK_TFS = 78.6         # MI355X vector FP64, TFLOP/s
-# FP64 operations per unordered pair of the viscosity sweep (two wave-speed
-# bounds with their x^y series, divisions and square roots, the psi terms of
+# FP64 operations per unordered pair of the viscosity sweep at 257^3 (one
+# wave-speed bound for the mirror-image pairs, two for the 0.7% on boundary
+# faces, with their x^y series, divisions and square roots, the psi terms of
 # the two states once; FMA = 2): every operation of the formula runs exactly
 # once, so the count rocprofv3 measures for it
 # (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64) is its algorithmic count.
-VISCOSITY_FLOP_PER_PAIR = 783
+VISCOSITY_FLOP_PER_PAIR = 435
 KERNEL_SOURCES = ["paper_2007_00094_amd/csrc/idp_kernels.hip",
                   "paper_2007_00094_amd/csrc/idp_device.h",
                   "paper_2007_00094_amd/csrc/kernels.h",

@@ -299,6 +299,44 @@ static int concat(const std::vector<HostGraph> &parts, HostGraph &g, BatchLayout
     return IDP_OK;
 }
 
+// The pair ranges of the row blocks and the halo position of each pair's
+// row node (see Halos); left empty unless the pair entries ascend and every
+// pair's row diagonal holds its node i.
+static void pair_ranges(const HostGraph &g, int64_t nblocks, Halos &h)
+{
+    const int64_t np = g.npairs, nb = (g.nslices + 3) / 4;
+    for (int64_t p = 1; p < np; ++p)
+        if (g.pair_e[size_t(p)] <= g.pair_e[size_t(p - 1)]) return;
+    std::vector<int64_t> blk(size_t(nblocks + 1), np);
+    for (int64_t b = 0; b < nb; ++b)
+        blk[size_t(b)] = std::lower_bound(g.pair_e.begin(), g.pair_e.end(),
+                                          g.slice_off[size_t(4 * b)],
+                                          [](int32_t a, int64_t v) { return a < v; }) -
+                         g.pair_e.begin();
+    std::vector<uint16_t> li(size_t(np), 0);
+    bool bad = false;
+#pragma omp parallel for schedule(dynamic, 64) reduction(|| : bad)
+    for (int64_t b = 0; b < nb; ++b) {
+        if (h.cnt[size_t(b)] < 0) continue;
+        int64_t s = 4 * b;
+        for (int64_t p = blk[size_t(b)]; p < blk[size_t(b + 1)]; ++p) {
+            const int64_t e = g.pair_e[size_t(p)];
+            while (s + 1 < g.nslices && g.slice_off[size_t(s + 1)] <= e) ++s;
+            const int lane = int((e - g.slice_off[size_t(s)]) % kSellC);
+            const int64_t r = s * kSellC + lane;
+            const int64_t ed = g.slice_off[size_t(s)] + int64_t(g.diag_k[size_t(r)]) * kSellC + lane;
+            if (s >= 4 * b + 4 || g.scol[size_t(ed)] != g.pair_i[size_t(p)]) {
+                bad = true;
+                break;
+            }
+            li[size_t(p)] = h.loc[size_t(ed)];
+        }
+    }
+    if (bad) return;
+    h.pair_blk.swap(blk);
+    h.pair_li.swap(li);
+}
+
 int build_halos(const HostGraph &g, int64_t nblocks, int hmax, Halos &h)
 {
     try {
@@ -367,6 +405,7 @@ int build_halos(const HostGraph &g, int64_t nblocks, int hmax, Halos &h)
         for (int64_t b = 0; b < nb; ++b)
             std::copy(lists[size_t(b)].begin(), lists[size_t(b)].end(),
                       h.node.begin() + h.start[size_t(b)]);
+        pair_ranges(g, nblocks, h);
     } catch (const std::bad_alloc &) {
         return IDP_ENOMEM;
     }

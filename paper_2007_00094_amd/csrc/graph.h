@@ -69,11 +69,17 @@ void morton_order(int dim, int64_t n, const double *coords, std::vector<int32_t>
 // those rows.  cnt[b] = its size, or -1 if it exceeds hmax (the block then
 // gathers from memory); node[start[b] + q] is its q-th node and loc[e] the
 // halo position of entry e's column (entries of blocks with cnt < 0: 0).
+// The pairs of block b (those whose row i lies in it: pairs are ordered by
+// entry) are pair_blk[b] .. pair_blk[b+1]-1, and pair_li[p] is the halo
+// position of pair p's node i (its row's diagonal entry); pair_blk stays
+// empty if the pair entries are not ascending.
 struct Halos {
     std::vector<int64_t> start;   // [nblocks]
     std::vector<int32_t> cnt;     // [nblocks]
     std::vector<int32_t> node;
     std::vector<uint16_t> loc;    // [sell_size]
+    std::vector<int64_t> pair_blk;   // [nblocks + 1]
+    std::vector<uint16_t> pair_li;   // [npairs]
 };
 
 // nblocks >= ceil(nslices / 4) (blocks past the last slice: empty).

@@ -471,6 +471,7 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
     TRY(dalloc(c, &pi, g.npairs));
     TRY(dalloc(c, &pj, g.npairs));
     TRY(dalloc(c, &P.mp, g.npairs));
+    TRY(dalloc(c, &P.cpair, g.npairs * 2 * dim));
     TRY(dalloc(c, &P.dp, g.npairs));
     TRY(dalloc(c, &P.l1p, g.npairs));
     TRY(dalloc(c, &P.c0, S));
@@ -552,6 +553,19 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
             HIPTRY(hipMemcpyAsync(hn, h.node.data(), h.node.size() * 4, hipMemcpyHostToDevice,
                                   c->stream));
         HIPTRY(hipMemcpyAsync(hl, h.loc.data(), S * 2, hipMemcpyHostToDevice, c->stream));
+        if (!h.pair_blk.empty()) {
+            int64_t *pb;
+            uint16_t *pl;
+            TRY(dalloc(c, &pb, nblk + 1));
+            TRY(dalloc(c, &pl, std::max<int64_t>(g.npairs, 1)));
+            HIPTRY(hipMemcpyAsync(pb, h.pair_blk.data(), (nblk + 1) * 8, hipMemcpyHostToDevice,
+                                  c->stream));
+            if (g.npairs)
+                HIPTRY(hipMemcpyAsync(pl, h.pair_li.data(), g.npairs * 2,
+                                      hipMemcpyHostToDevice, c->stream));
+            P.pair_blk = pb;
+            P.pair_li = pl;
+        }
         // the host vectors die at the end of this scope: wait for the copies
         HIPTRY(hipStreamSynchronize(c->stream));
         P.halo_start = hs;

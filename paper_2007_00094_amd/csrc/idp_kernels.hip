@@ -177,6 +177,22 @@ __global__ void __launch_bounds__(kBlock) k_pair_mass(StageArgs P)
     P.mp[p] = P.mij[P.pair_e[p]];
 }
 
+// c_ij and c_ji in pair order
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_pair_c(StageArgs P)
+{
+    const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (p >= P.npairs) return;
+    const int64_t e = P.pair_e[p];
+    double *o = P.cpair + p * (2 * D);
+    o[0] = P.c0[e];
+    o[1] = P.c1[e];
+    if (D == 3) o[2] = P.c2[e];
+    o[D] = P.ct0[e];
+    o[D + 1] = P.ct1[e];
+    if (D == 3) o[D + 2] = P.ct2[e];
+}
+
 // ------------------------------------------------------------ helpers
 __global__ void k_begin(StageArgs P, int clear_status)
 {
@@ -269,30 +285,15 @@ __device__ __forceinline__ void node_sweep(const StageArgs &P, int64_t i, int64_
 
 // ------------------------------------------------------- pair viscosity
 // Step 1, once per unordered pair {i, j}: d_ij = d_ji = max of
-// lambda~(n_ij, U_i, U_j)|c_ij| and lambda~(n_ji, U_j, U_i)|c_ji|.
+// lambda~(n_ij, U_i, U_j)|c_ij| and lambda~(n_ji, U_j, U_i)|c_ji|, from
+// c_ij, c_ji (stored at the position of c_ij) and the two nodes' pack A
+// records (U, p, c); p_ is the pair's index, e and t its two entries.
 template <int D>
-__device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, int64_t pend,
-                                            double2 *lw)
+__device__ __forceinline__ void dpair_eval(const StageArgs &P, int64_t p_, int64_t e,
+                                           int64_t t, const double *c, const double *ct,
+                                           const double *Ai, const double *Aj)
 {
-    WAVE_PAIR_SETUP(P, pidx, pend)
-    if (failed(P)) return;
     constexpr int NC = D + 2;
-    constexpr int NCH = (NC + 3) / 2;   // U, p, c
-    double c[D], ct[D];   // c_ij, and c_ji stored at the position of c_ij
-    load_c<D>(P, e, c);
-    ct[0] = P.ct0[e];
-    ct[1] = P.ct1[e];
-    if (D == 3) ct[D - 1] = P.ct2[e];
-    double Ai[2 * NCH], Aj[2 * NCH];
-    {
-        // both records' loads in flight before either passes through LDS
-        dchunk vi[GatherShape<NCH>::LPR], vj[GatherShape<NCH>::LPR];
-        gather_issue<NCH>(P.packA, kPack, i, vi);
-        gather_issue<NCH>(P.packA, kPack, j, vj);
-        gather_exchange<NCH>(lw, vi, Ai);
-        gather_exchange<NCH>(lw, vj, Aj);
-    }
-    if (!valid_) return;
     double aij = 0.0, aji = 0.0;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
@@ -340,6 +341,48 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
     P.d[t] = dd;
     if (P.sided) P.dp[p_] = dd;   // pair order: read by the stage adjoint only
     if (P.sided) P.sided[p_] = mirror || t1 > t2;
+}
+
+// c_ij and c_ji of pair p (16-byte loads from the pair-order copy)
+template <int D>
+__device__ __forceinline__ void load_cp(const StageArgs &P, int64_t p, double *c, double *ct)
+{
+    const double2 *q = reinterpret_cast<const double2 *>(P.cpair + p * (2 * D));
+    double v[2 * D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double2 w = q[k];
+        v[2 * k] = w.x;
+        v[2 * k + 1] = w.y;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        c[k] = v[k];
+        ct[k] = v[D + k];
+    }
+}
+
+// the sweep over pairs pidx (one per lane) below pend, both records gathered
+template <int D>
+__device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, int64_t pend,
+                                            double2 *lw)
+{
+    WAVE_PAIR_SETUP(P, pidx, pend)
+    if (failed(P)) return;
+    constexpr int NCH = (D + 5) / 2;   // U, p, c
+    double c[D], ct[D];
+    load_cp<D>(P, pq_, c, ct);
+    double Ai[2 * NCH], Aj[2 * NCH];
+    {
+        // both records' loads in flight before either passes through LDS
+        dchunk vi[GatherShape<NCH>::LPR], vj[GatherShape<NCH>::LPR];
+        gather_issue<NCH>(P.packA, kPack, i, vi);
+        gather_issue<NCH>(P.packA, kPack, j, vj);
+        gather_exchange<NCH>(lw, vi, Ai);
+        gather_exchange<NCH>(lw, vj, Aj);
+    }
+    if (!valid_) return;
+    dpair_eval<D>(P, p_, e, t, c, ct, Ai, Aj);
 }
 
 // --------------------------------------------------------- row diagonal
@@ -806,6 +849,67 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
     dpair_sweep<D>(P, PAIR_INDEX(P), P.npairs, lw);
 }
 
+// Staged viscosity sweep: one block per row block takes the pairs of its
+// rows, whose two nodes are both in the block's halo; with the halo's
+// records in LDS every node record is read from memory once per block
+// instead of once per pair (a node has 2 x 13 pairs in 3D).  A block whose
+// halo did not fit gathers as above.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P)
+{
+    constexpr int NCH = (D + 5) / 2;
+    __shared__ double2 sh_[kHaloMaxD<D> * NCH];
+    const int64_t b = logical_block(P.per);
+    const int64_t p0 = P.pair_blk[b], p1 = P.pair_blk[b + 1];
+    if (stage_halo<NCH, NCH - 1, kPack>(P, b, P.packA, sh_)) {
+        if (failed(P)) return;
+        // the next pair's entries, halo positions and coefficients are
+        // loaded one pair ahead
+        int64_t p = p0 + threadIdx.x, en = 0, tn = 0;
+        int lin = 0, ljn = 0;
+        double cn[D], ctn[D];
+        if (p < p1) {
+            en = P.pair_e[p];
+            tn = P.pair_t[p];
+            lin = P.pair_li[p];
+            ljn = P.loc[en];
+            load_cp<D>(P, p, cn, ctn);
+        }
+        for (; p < p1; p += kBlock) {
+            const int64_t e = en, t = tn;
+            const int li = lin, lj = ljn;
+            double c[D], ct[D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                c[q] = cn[q];
+                ct[q] = ctn[q];
+            }
+            if (p + kBlock < p1) {
+                en = P.pair_e[p + kBlock];
+                tn = P.pair_t[p + kBlock];
+                lin = P.pair_li[p + kBlock];
+                ljn = P.loc[en];
+                load_cp<D>(P, p + kBlock, cn, ctn);
+            }
+            const double2 *ri = sh_ + li * NCH;
+            const double2 *rj = sh_ + lj * NCH;
+            double Ai[2 * NCH], Aj[2 * NCH];
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) {
+                const double2 a = ri[k], q = rj[k];
+                Ai[2 * k] = a.x;
+                Ai[2 * k + 1] = a.y;
+                Aj[2 * k] = q.x;
+                Aj[2 * k + 1] = q.y;
+            }
+            dpair_eval<D>(P, p, e, t, c, ct, Ai, Aj);
+        }
+    } else {
+        double2 *lw = sh_ + (threadIdx.x / kSlice) * NCH * kLdsRow;
+        for (int64_t q0 = p0; q0 < p1; q0 += kBlock) dpair_sweep<D>(P, q0 + threadIdx.x, p1, lw);
+    }
+}
+
 template <int D>
 __global__ void __launch_bounds__(kBlock, 4) k_diag(StageArgs P, int with_alpha)
 {
@@ -1074,9 +1178,14 @@ void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
         hipLaunchKernelGGL(k_transpose_c<2>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
     else
         hipLaunchKernelGGL(k_transpose_c<3>, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
-    if (P.npairs > 0)
-        hipLaunchKernelGGL(k_pair_mass, dim3(int((P.npairs + kBlock - 1) / kBlock)), dim3(kBlock),
-                           0, st, P);
+    if (P.npairs > 0) {
+        const dim3 gp(unsigned((P.npairs + kBlock - 1) / kBlock));
+        hipLaunchKernelGGL(k_pair_mass, gp, dim3(kBlock), 0, st, P);
+        if (P.dim == 2)
+            hipLaunchKernelGGL(k_pair_c<2>, gp, dim3(kBlock), 0, st, P);
+        else
+            hipLaunchKernelGGL(k_pair_c<3>, gp, dim3(kBlock), 0, st, P);
+    }
 }
 
 void launch_begin(const StageArgs &P, hipStream_t st, int clear_status)
@@ -1107,7 +1216,13 @@ static inline int grid_pairs(const StageArgs &P) { return P.pper * kXcd; }
             hipLaunchKernelGGL(K<3>, dim3(grid), dim3(kBlock), 0, st, __VA_ARGS__);     \
     } while (0)
 
-void launch_dpair(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_dpair, grid_pairs(P), P); }
+void launch_dpair(const StageArgs &P, hipStream_t st)
+{
+    if (P.halo_cnt && P.pair_blk)
+        LAUNCH_D(k_dpair_h, grid_rows(P), P);
+    else
+        LAUNCH_D(k_dpair, grid_pairs(P), P);
+}
 void launch_diag(const StageArgs &P, hipStream_t st, int with_alpha)
 {
     LAUNCH_D(k_diag, grid_rows(P), P, with_alpha);

@@ -77,6 +77,14 @@ struct StageArgs {
     const int64_t *halo_start;
     const int32_t *halo_cnt, *halo_node;
     const uint16_t *loc;
+    // [per * 8 + 1] the pairs of each row block (those of its rows), and
+    // [npairs] the halo position of each pair's node i, or null (the
+    // viscosity sweep then gathers both records)
+    const int64_t *pair_blk;
+    const uint16_t *pair_li;
+    // [npairs * 2 dim] c_ij then c_ji of each pair, in pair order (the
+    // viscosity sweep's coefficient stream)
+    double *cpair;
     // instances: a batch of independent meshes shares one context; their
     // slices, pairs and nodes are contiguous and never mixed
     int ninst;
