@@ -29,7 +29,7 @@ FP64_PEAK_TFS = 78.6         # MI355X vector FP64, TFLOP/s
 # the two states once; FMA = 2): every operation of the formula runs exactly
 # once, so the count rocprofv3 measures for it
 # (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64) is its algorithmic count.
-VISCOSITY_FLOP_PER_PAIR = 435
+VISCOSITY_FLOP_PER_PAIR = 438
 KERNEL_SOURCES = ["paper_2007_00094_amd/csrc/idp_kernels.hip",
                   "paper_2007_00094_amd/csrc/idp_device.h",
                   "paper_2007_00094_amd/csrc/kernels.h",
