@@ -854,14 +854,40 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
 // records in LDS every node record is read from memory once per block
 // instead of once per pair (a node has 2 x 13 pairs in 3D).  A block whose
 // halo did not fit gathers as above.
+// In 3D a staged record is the 48 bytes the sweep reads, rho, m, p, c (E
+// and eta/rho left out): 38 KB per block, four blocks per CU.
+__device__ __forceinline__ bool stage_halo_a3(const StageArgs &P, int64_t b, double2 *halo)
+{
+    constexpr int NC = 5;
+    const int cnt = P.halo_cnt[b];
+    if (cnt < 0) return false;
+    const int64_t h0 = P.halo_start[b];
+#pragma unroll 4
+    for (int q = int(threadIdx.x); q < 3 * cnt; q += kBlock) {
+        const int r = q / 3, c = q - 3 * r;
+        const double *a = P.packA + int64_t(P.halo_node[h0 + r]) * kPack;
+        halo[q] = c < 2 ? *reinterpret_cast<const double2 *>(a + 2 * c)
+                        : make_double2(a[NC], a[NC + 1]);
+    }
+    __syncthreads();
+    return true;
+}
+
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P)
 {
-    constexpr int NCH = (D + 5) / 2;
-    __shared__ double2 sh_[kHaloMaxD<D> * NCH];
+    constexpr int NCH = (D + 5) / 2;   // gathered chunks per record
+    constexpr int NS = D == 3 ? 3 : NCH;   // staged chunks per record
+    static_assert(kHaloMaxD<D> * NS >= (kBlock / kSlice) * NCH * kLdsRow, "gather tiles fit");
+    __shared__ double2 sh_[kHaloMaxD<D> * NS];
     const int64_t b = logical_block(P.per);
     const int64_t p0 = P.pair_blk[b], p1 = P.pair_blk[b + 1];
-    if (stage_halo<NCH, NCH - 1, kPack>(P, b, P.packA, sh_)) {
+    bool staged;
+    if constexpr (D == 3)
+        staged = stage_halo_a3(P, b, sh_);
+    else
+        staged = stage_halo<NCH, NCH - 1, kPack>(P, b, P.packA, sh_);
+    if (staged) {
         if (failed(P)) return;
         // the next pair's entries, halo positions and coefficients are
         // loaded one pair ahead
@@ -891,16 +917,37 @@ __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P)
                 ljn = P.loc[en];
                 load_cp<D>(P, p + kBlock, cn, ctn);
             }
-            const double2 *ri = sh_ + li * NCH;
-            const double2 *rj = sh_ + lj * NCH;
+            const double2 *ri = sh_ + li * NS;
+            const double2 *rj = sh_ + lj * NS;
             double Ai[2 * NCH], Aj[2 * NCH];
+            if constexpr (D == 3) {
+                // rho, m | p, c at the pack A slots (E and eta/rho unread)
 #pragma unroll
-            for (int k = 0; k < NCH; ++k) {
-                const double2 a = ri[k], q = rj[k];
-                Ai[2 * k] = a.x;
-                Ai[2 * k + 1] = a.y;
-                Aj[2 * k] = q.x;
-                Aj[2 * k + 1] = q.y;
+                for (int k = 0; k < 2; ++k) {
+                    const double2 a = ri[k], q = rj[k];
+                    Ai[2 * k] = a.x;
+                    Ai[2 * k + 1] = a.y;
+                    Aj[2 * k] = q.x;
+                    Aj[2 * k + 1] = q.y;
+                }
+                const double2 a = ri[2], q = rj[2];
+                Ai[4] = 0.0;
+                Aj[4] = 0.0;
+                Ai[5] = a.x;
+                Ai[6] = a.y;
+                Aj[5] = q.x;
+                Aj[6] = q.y;
+                Ai[7] = 0.0;
+                Aj[7] = 0.0;
+            } else {
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) {
+                    const double2 a = ri[k], q = rj[k];
+                    Ai[2 * k] = a.x;
+                    Ai[2 * k + 1] = a.y;
+                    Aj[2 * k] = q.x;
+                    Aj[2 * k + 1] = q.y;
+                }
             }
             dpair_eval<D>(P, p, e, t, c, ct, Ai, Aj);
         }
