@@ -184,8 +184,9 @@ STAGING_CASES = [
 
 @pytest.mark.parametrize("name,dim,n,order,ic", STAGING_CASES)
 def test_lds_staging_is_bitwise_the_gather_path(torch, oracle_mod, name, dim, n, order, ic):
-    """Row sweeps that stage their block's neighbourhood in LDS give the
-    same bits as the cooperative gathers, and both the oracle's."""
+    """Row sweeps and the viscosity sweep that stage their block's
+    neighbourhood in LDS give the same bits as the cooperative gathers, and
+    both the oracle's."""
     announce(f"LDS staging vs gathers: {name}")
     from paper_2007_00094_amd.solver import Solver
     mesh = inputs.q1_grid(n, dim, 0.2, seed=0, order=order, perm_seed=1)
