@@ -189,7 +189,9 @@ int idp_device_math(idp_ctx *ctx, int kind, int64_t n, const double *x_dev,
  * nodes [off[k], off[k+1]) of one concatenated state U_dev [N][nc]
  * (off from idp_batch_info); its results are bit-identical to a context
  * created for that mesh alone.  idp_step, idp_euler_stage and idp_max_dt
- * answer IDP_ENOTSUP on a context with more than one instance.           */
+ * answer IDP_ENOTSUP on a context with more than one instance; the batch
+ * calls below answer IDP_ENOTSUP on a context created with
+ * IDP_FLAG_RENUMBER (its state is in the caller's order: use idp_step).  */
 
 /* Build a batch context: n_inst meshes, each given like idp_create's
  * (host arrays n_nodes[k], coords[k], n_cells[k], cells[k], dirichlet[k]

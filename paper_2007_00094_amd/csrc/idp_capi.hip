@@ -780,6 +780,7 @@ int idp_max_dt(idp_ctx *c, const double *U, double *dt_out)
 int idp_batch_max_dt(idp_ctx *c, const double *U, double *dt_out)
 {
     if (!c || !U || !dt_out) return IDP_EINVAL;
+    if (c->pos_dev) return IDP_ENOTSUP;   // renumbered contexts: idp_max_dt
     return max_dt_all(c, U, dt_out);
 }
 
@@ -1594,6 +1595,7 @@ int idp_batch_steps(idp_ctx *c, double *U, int n_steps, const double *dt, double
                     const idp_schedule *sched)
 {
     if (!c || !U || n_steps < 0) return IDP_EINVAL;
+    if (c->pos_dev) return IDP_ENOTSUP;   // renumbered contexts: idp_step
     const idp_schedule sc = sched ? *sched : c->tuned;
     if (!valid_schedule(sc)) return IDP_EINVAL;
     if (n_steps == 0) return IDP_OK;
@@ -1604,6 +1606,7 @@ int idp_batch_tune(idp_ctx *c, const double *U, int n_steps, idp_schedule *best,
                    double *ms_out, int *n_candidates)
 {
     if (!c || !U || n_steps < 1) return IDP_EINVAL;
+    if (c->pos_dev) return IDP_ENOTSUP;
     const idp_schedule cand[] = {{IDP_SCHED_LAUNCHES, 0},    {IDP_SCHED_PERSISTENT, 4},
                                  {IDP_SCHED_PERSISTENT, 16},  {IDP_SCHED_PERSISTENT, 32},
                                  {IDP_SCHED_PERSISTENT, 64},  {IDP_SCHED_PERSISTENT, 128},

@@ -167,6 +167,27 @@ def test_single_instance_calls_refuse_a_batch(torch):
     assert L.idp_max_dt(bs._h, C.c_void_p(U.data_ptr()), C.byref(out)) == capi.IDP_ENOTSUP
 
 
+def test_batch_calls_refuse_a_renumbered_context(torch):
+    """A context built with IDP_FLAG_RENUMBER keeps its state in its own
+    numbering; the batch calls (which take the concatenated state as is)
+    answer IDP_ENOTSUP instead of stepping the caller's order wrongly."""
+    announce("2D renumbered single mesh: batch steps / max_dt / tune -> IDP_ENOTSUP")
+    import ctypes as C
+    from paper_2007_00094_amd.solver import Solver
+    m = inputs.q1_grid(9, 2, 0.2, seed=5, order="random")
+    u = inputs.ic_four_quadrant(m.coords, inputs.random_quadrant_states(5))
+    s = Solver(m, renumber=True)
+    U = torch.tensor(u, device="cuda")
+    L = capi.lib()
+    dt = (C.c_double * 1)()
+    p = C.c_void_p(U.data_ptr())
+    assert L.idp_batch_steps(s._h, p, 1, None, None, None) == capi.IDP_ENOTSUP
+    assert L.idp_batch_max_dt(s._h, p, dt) == capi.IDP_ENOTSUP
+    assert L.idp_batch_tune(s._h, p, 1, None, None, None) == capi.IDP_ENOTSUP
+    assert np.array_equal(U.cpu().numpy(), u)
+    s.close()
+
+
 def test_full_batch_workload_sampled_instances(torch, oracle_mod):
     """The benchmark's batch (64 2D meshes, sides 33-513, per-instance CFL
     dt) for 3 steps under the launch schedule: the smallest, the largest
