@@ -48,6 +48,8 @@ extern "C" {
 #define IDP_ENOTSUP (-7)        /* option not supported by this build        */
 #define IDP_EWAIT (-8)          /* a persistent batch launch gave up waiting
                                    on a dependency (its results are void)  */
+#define IDP_ESCRATCH (-9)       /* the call needs more than the static scratch
+                                   of idp_batch_steps_noalloc              */
 
 /* flags for idp_params.flags */
 #define IDP_FLAG_ASYNC 1        /* idp_step does not synchronise; errors are
@@ -227,6 +229,23 @@ typedef struct {
  * IDP_EWAIT, IDP_EINVAL or IDP_EHIP; after an error U_dev is undefined.  */
 int idp_batch_steps(idp_ctx *ctx, double *U_dev, int n_steps, const double *dt,
                     double *dt_used, const idp_schedule *sched);
+
+/* For callers that cannot allocate device memory during the call (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): idp_batch_steps with the launch schedule (IDP_SCHED_LAUNCHES),
+ * same arguments and same bits, that calls no hipMalloc, hipFree or other
+ * allocating routine.  idp_batch_steps allocates, on first need, the
+ * per-instance dt and the tau record of n_steps x n_inst; here those and the
+ * status word and per-instance tau scalars live in one static device array
+ * of 1 MiB per device (held by each device the library runs on until the
+ * process ends), so 16 + 32 n_inst + 8 n_steps n_inst bytes must fit in
+ * 1 MiB, else IDP_ESCRATCH before any device work.  The context's device
+ * must be current (IDP_EINVAL otherwise).  Every call on a device shares its
+ * array (kernels clear what must start at zero): calls that overlap on one
+ * device, from several threads or on several streams, race.  Returns as
+ * idp_batch_steps; IDP_ENOTSUP on a renumbered context.                  */
+int idp_batch_steps_noalloc(idp_ctx *ctx, double *U_dev, int n_steps, const double *dt,
+                            double *dt_used);
 
 /* tau_k = cfl * min_{i in instance k} m_i/(-2 d_ii(U)) for every instance:
  * host dt_out [n_inst].  Synchronises.                                   */

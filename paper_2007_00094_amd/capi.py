@@ -22,6 +22,7 @@ IDP_ESTATE = -5
 IDP_EDT = -6
 IDP_ENOTSUP = -7
 IDP_EWAIT = -8
+IDP_ESCRATCH = -9
 IDP_FLAG_ASYNC = 1
 IDP_FLAG_NO_STAGING = 2
 IDP_FLAG_RENUMBER = 4
@@ -76,6 +77,7 @@ SIGNATURES = {
                                    _vp]),
     "idp_batch_info": (C.c_int, [_vp, C.POINTER(C.c_int), _i64p]),
     "idp_batch_steps": (C.c_int, [_vp, _vp, C.c_int, _dp, _dp, C.POINTER(idp_schedule)]),
+    "idp_batch_steps_noalloc": (C.c_int, [_vp, _vp, C.c_int, _dp, _dp]),
     "idp_batch_max_dt": (C.c_int, [_vp, _vp, _dp]),
     "idp_batch_tune": (C.c_int, [_vp, _vp, C.c_int, C.POINTER(idp_schedule), _dp,
                                  C.POINTER(C.c_int)]),

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1650,6 +1651,109 @@ int idp_batch_tune(idp_ctx *c, const double *U, int n_steps, idp_schedule *best,
     return IDP_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------ the batch step that allocates nothing
+// Per device, one static array holds what idp_batch_steps keeps in buffers
+// it allocates on demand: the status word, per instance the tau minimum,
+// tau, the bound and the given dt, and the tau record of every step.  Host
+// code never uses the array's name as an address: the device address of
+// this device's copy is looked up once (hipGetSymbolAddress, with the
+// device current) and kept in g_scratch_ptr.
+namespace {
+constexpr size_t kNoAllocBytes = size_t(1) << 20;
+constexpr int kNoAllocDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kNoAllocDevices] = {};
+
+int scratch_address(int device, char **out)
+{
+    if (device < 0 || device >= kNoAllocDevices) return IDP_ENOTSUP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return IDP_EHIP;
+        }
+        g_scratch_ptr[device] = static_cast<char *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return IDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int idp_batch_steps_noalloc(idp_ctx *c, double *U, int n_steps, const double *dt,
+                            double *dt_used)
+{
+    if (!c || !U || n_steps < 0) return IDP_EINVAL;
+    if (c->pos_dev) return IDP_ENOTSUP;   // as idp_batch_steps
+    if (n_steps == 0) return IDP_OK;
+    const int K = c->ninst;
+    // layout: [status, 16 B] [tau minimum bits | tau | bound | dt] x K [record n_steps x K]
+    const size_t head = kScalHead + size_t(K) * 32;
+    if (size_t(n_steps) > (kNoAllocBytes - std::min(head, kNoAllocBytes)) / 8 / size_t(K) ||
+        head > kNoAllocBytes)
+        return IDP_ESCRATCH;
+    if (dt)
+        for (int k = 0; k < K; ++k)
+            if (!(dt[k] > 0.0) || !std::isfinite(dt[k])) return IDP_EINVAL;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return IDP_EHIP;
+    if (cur != c->device) return IDP_EINVAL;   // the context's device must be current
+    char *base = nullptr;
+    int rc = scratch_address(c->device, &base);
+    if (rc != IDP_OK) return rc;
+    idp::StageArgs P = c->P;
+    P.status = reinterpret_cast<int *>(base);
+    P.taumin = reinterpret_cast<unsigned long long *>(base + kScalHead);
+    P.tau = reinterpret_cast<double *>(base + kScalHead + size_t(K) * 8);
+    P.bound = reinterpret_cast<double *>(base + kScalHead + size_t(K) * 16);
+    double *dt_dev = reinterpret_cast<double *>(base + kScalHead + size_t(K) * 24);
+    double *rec = reinterpret_cast<double *>(base + head);
+    if (dt && hipMemcpyAsync(dt_dev, dt, size_t(K) * 8, hipMemcpyHostToDevice, c->stream) !=
+                  hipSuccess)
+        return IDP_EHIP;
+    P.dt_inst = dt ? dt_dev : nullptr;
+    // no event timing here (it may create events)
+    const bool timing = c->timing;
+    c->timing = false;
+    for (int st = 0; st < n_steps; ++st) {
+        // the first stage clears the status word and every stage the tau
+        // minima (kernels, so the call needs no memset)
+        stage_p(c, P, U, U, c->U1, 1, 1, 0.0, 1, st == 0 ? 1 : 0);
+        (void)hipMemcpyAsync(rec + int64_t(st) * K, P.tau, size_t(K) * 8,
+                             hipMemcpyDeviceToDevice, c->stream);
+        stage_p(c, P, c->U1, U, c->U1, 2, 0, 0.0, 0, 0);
+        stage_p(c, P, c->U1, U, U, 3, 0, 0.0, 0, 0);
+    }
+    c->timing = timing;
+    if (hipGetLastError() != hipSuccess) return IDP_EHIP;
+    int status = 0;
+    if (hipMemcpyAsync(&status, P.status, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
+        hipSuccess)
+        return IDP_EHIP;
+    if ((rc = sync(c)) != IDP_OK) return rc;
+    rc = status_code(status);
+    if (rc >= 0 && dt_used) {
+        if (hipMemcpyAsync(dt_used, rec, size_t(n_steps) * K * 8, hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess)
+            return IDP_EHIP;
+        const int rs = sync(c);
+        if (rs != IDP_OK) return rs;
+    }
+    return rc;
+}
+
 const char *idp_strerror(int code)
 {
     switch (code) {
@@ -1663,6 +1767,7 @@ const char *idp_strerror(int code)
     case IDP_EDT: return "dt exceeds the stage-1 bound min_i m_i/(-2 d_ii)";
     case IDP_ENOTSUP: return "option not supported";
     case IDP_EWAIT: return "a persistent batch launch gave up waiting on a dependency";
+    case IDP_ESCRATCH: return "the call needs more than the static scratch of idp_batch_steps_noalloc";
     default: return "unknown error";
     }
 }
