@@ -34,52 +34,73 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
-_lib = None
+_libs = {}
+
+
+def load_library(path: str = _LIB):
+    """The oracle library at ``path`` with its ctypes signatures (cached per
+    path; the default is the oracle built from ``idp_oracle.c``)."""
+    L = _libs.get(path)
+    if L is not None:
+        return L
+    if path == _LIB and not os.path.exists(_LIB):
+        build()
+    L = C.CDLL(path)
+    L.ora_create.restype = C.c_void_p
+    L.ora_create.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int,
+                             C.c_int, C.c_double, C.c_int, C.c_int64, _dp,
+                             C.c_int64, _i64p, _u8p, C.POINTER(C.c_int)]
+    L.ora_destroy.argtypes = [C.c_void_p]
+    L.ora_max_dt.restype = C.c_double
+    L.ora_max_dt.argtypes = [C.c_void_p, _dp]
+    L.ora_euler_stage.restype = C.c_int
+    L.ora_euler_stage.argtypes = [C.c_void_p, _dp, C.c_double, _dp]
+    L.ora_step.restype = C.c_int
+    L.ora_step.argtypes = [C.c_void_p, _dp, C.c_double, _dp]
+    L.ora_n.restype = C.c_int64
+    L.ora_n.argtypes = [C.c_void_p]
+    L.ora_nnz.restype = C.c_int64
+    L.ora_nnz.argtypes = [C.c_void_p]
+    L.ora_volume.restype = C.c_double
+    L.ora_volume.argtypes = [C.c_void_p]
+    L.ora_set_literal_alg3.argtypes = [C.c_void_p, C.c_int]
+    L.ora_set_limiter_mode.argtypes = [C.c_void_p, C.c_int]
+    L.ora_set_threads.restype = C.c_int
+    L.ora_set_threads.argtypes = [C.c_int]
+    L.ora_array.restype = C.c_void_p
+    L.ora_array.argtypes = [C.c_void_p, C.c_int]
+    for name in ("ora_pressure", "ora_speed_of_sound",
+                 "ora_specific_entropy", "ora_harten_entropy"):
+        f = getattr(L, name)
+        f.restype = C.c_double
+        f.argtypes = [_dp, C.c_int, C.c_double]
+    L.ora_harten_entropy_derivative.argtypes = [_dp, C.c_int, C.c_double, _dp]
+    L.ora_pow.restype = C.c_double
+    L.ora_pow.argtypes = [C.c_double, C.c_double]
+    L.ora_lambda_max.restype = C.c_double
+    L.ora_lambda_max.argtypes = [_dp, _dp, _dp, C.c_int, C.c_double, _dp]
+    L.ora_limiter.restype = C.c_double
+    L.ora_limiter.argtypes = [_dp, _dp, _dp, C.c_int, C.c_double, C.c_int,
+                              C.c_double, C.c_int]
+    _libs[path] = L
+    return L
 
 
 def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = C.CDLL(_LIB)
-        L.ora_create.restype = C.c_void_p
-        L.ora_create.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int,
-                                 C.c_int, C.c_double, C.c_int, C.c_int64, _dp,
-                                 C.c_int64, _i64p, _u8p, C.POINTER(C.c_int)]
-        L.ora_destroy.argtypes = [C.c_void_p]
-        L.ora_max_dt.restype = C.c_double
-        L.ora_max_dt.argtypes = [C.c_void_p, _dp]
-        L.ora_euler_stage.restype = C.c_int
-        L.ora_euler_stage.argtypes = [C.c_void_p, _dp, C.c_double, _dp]
-        L.ora_step.restype = C.c_int
-        L.ora_step.argtypes = [C.c_void_p, _dp, C.c_double, _dp]
-        L.ora_n.restype = C.c_int64
-        L.ora_n.argtypes = [C.c_void_p]
-        L.ora_nnz.restype = C.c_int64
-        L.ora_nnz.argtypes = [C.c_void_p]
-        L.ora_volume.restype = C.c_double
-        L.ora_volume.argtypes = [C.c_void_p]
-        L.ora_set_literal_alg3.argtypes = [C.c_void_p, C.c_int]
-        L.ora_set_threads.restype = C.c_int
-        L.ora_set_threads.argtypes = [C.c_int]
-        L.ora_array.restype = C.c_void_p
-        L.ora_array.argtypes = [C.c_void_p, C.c_int]
-        for name in ("ora_pressure", "ora_speed_of_sound",
-                     "ora_specific_entropy", "ora_harten_entropy"):
-            f = getattr(L, name)
-            f.restype = C.c_double
-            f.argtypes = [_dp, C.c_int, C.c_double]
-        L.ora_harten_entropy_derivative.argtypes = [_dp, C.c_int, C.c_double, _dp]
-        L.ora_pow.restype = C.c_double
-        L.ora_pow.argtypes = [C.c_double, C.c_double]
-        L.ora_lambda_max.restype = C.c_double
-        L.ora_lambda_max.argtypes = [_dp, _dp, _dp, C.c_int, C.c_double, _dp]
-        L.ora_limiter.restype = C.c_double
-        L.ora_limiter.argtypes = [_dp, _dp, _dp, C.c_int, C.c_double, C.c_int,
-                                  C.c_double, C.c_int]
-        _lib = L
-    return _lib
+    return load_library(_LIB)
+
+
+def build_variant(source: str, path: str) -> str:
+    """Compile the oracle from the C text ``source`` into ``path`` with the
+    oracle's own flags (tests plant mistakes this way to show that a pin
+    catches them)."""
+    src = path + ".c"
+    with open(src, "w") as f:
+        f.write(source)
+    subprocess.run(
+        ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+         "-fPIC", "-shared", "-o", path, src, "-lm"], check=True)
+    return path
 
 
 def _d(a):
@@ -152,7 +173,8 @@ class Oracle:
 
     def __init__(self, mesh=None, *, dim=None, coords=None, cells=None,
                  dirichlet=None, gamma=1.4, cfl=0.5, passes=2, newton_max=2,
-                 newton_tol=1e-10, relax=False):
+                 newton_tol=1e-10, relax=False, library=None):
+        self._L = load_library(library) if library else lib()
         if mesh is not None:
             dim, coords, cells = mesh.dim, mesh.coords, mesh.cells
             if dirichlet is None:
@@ -165,31 +187,38 @@ class Oracle:
         dirichlet = np.ascontiguousarray(dirichlet, dtype=np.uint8)
         err = C.c_int(0)
         self.dim, self.nc, self.gamma, self.cfl = dim, dim + 2, gamma, cfl
-        self._h = lib().ora_create(
+        self._h = self._L.ora_create(
             dim, gamma, cfl, passes, newton_max, newton_tol, int(relax), n,
             coords.ctypes.data_as(_dp), cells.shape[0],
             cells.ctypes.data_as(_i64p), dirichlet.ctypes.data_as(_u8p),
             C.byref(err))
         if not self._h:
             raise ValueError(f"oracle create failed: {err.value}")
-        self.n = int(lib().ora_n(self._h))
-        self.nnz = int(lib().ora_nnz(self._h))
+        self.n = int(self._L.ora_n(self._h))
+        self.nnz = int(self._L.ora_nnz(self._h))
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().ora_destroy(h)
+            self._L.ora_destroy(h)
             self._h = None
 
     def set_literal_alg3(self, on: bool):
-        lib().ora_set_literal_alg3(self._h, int(bool(on)))
+        self._L.ora_set_literal_alg3(self._h, int(bool(on)))
+
+    LIMITER_MODES = {"paper": 0, "high": 1, "low": 2}
+
+    def set_limiter_mode(self, mode: str):
+        """'paper': Alg. 2 candidates; 'high': every l_ij = 1 (the unlimited
+        high-order update); 'low': every l_ij = 0 (the low-order update)."""
+        self._L.ora_set_limiter_mode(self._h, self.LIMITER_MODES[mode])
 
     @property
     def volume(self):
-        return lib().ora_volume(self._h)
+        return self._L.ora_volume(self._h)
 
     def _arr(self, what, dtype, count, shape=None):
-        ptr = lib().ora_array(self._h, what)
+        ptr = self._L.ora_array(self._h, what)
         ctype = {np.int64: C.c_int64, np.float64: C.c_double}[dtype]
         a = np.ctypeslib.as_array(C.cast(ptr, C.POINTER(ctype)), shape=(count,))
         a = a.copy()
@@ -217,19 +246,19 @@ class Oracle:
 
     def max_dt(self, U):
         U, p = _d(U)
-        return lib().ora_max_dt(self._h, p)
+        return self._L.ora_max_dt(self._h, p)
 
     def euler_stage(self, U, tau):
         """Forward-Euler update E(U) with limiting; returns (Unew, warn)."""
         U, p = _d(U)
         out = np.empty_like(U)
-        w = lib().ora_euler_stage(self._h, p, tau, out.ctypes.data_as(_dp))
+        w = self._L.ora_euler_stage(self._h, p, tau, out.ctypes.data_as(_dp))
         return out, int(w)
 
     def step(self, U, dt=0.0):
         """One SSP-RK3 step; returns (Unew, dt_used, status)."""
         U = np.array(U, dtype=np.float64, copy=True, order="C")
         used = C.c_double(0.0)
-        st = lib().ora_step(self._h, U.ctypes.data_as(_dp), float(dt),
+        st = self._L.ora_step(self._h, U.ctypes.data_as(_dp), float(dt),
                             C.byref(used))
         return U, used.value, int(st)

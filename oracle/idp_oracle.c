@@ -50,7 +50,10 @@
  *   - x^y by one fixed series method (ora_pow), so that an implementation
  *     following the same steps reproduces these results bit for bit.
  * Parity pins: see tests/test_oracle_*.py.  The relaxation of the bounds
- * (optional, off by default) has no formula in the paper: parity unpinned.
+ * (optional, off by default) has no formula in the paper; the one used
+ * here widens each bound by (m_i/|Omega|)^(1.5/d), and is pinned by the
+ * second-order convergence it restores on a smooth vortex, not by a value
+ * the paper prints.
  */
 #include <math.h>
 #include <stdint.h>
@@ -66,6 +69,8 @@ typedef struct {
     int dim, nc;
     double gamma, cfl, newton_tol;
     int passes, newton_max, relax, literal_alg3;
+    int limiter_mode;     /* 0 Alg. 2 candidates; 1 l = 1 (the high-order
+                           * update, unlimited); 2 l = 0 (the low-order one) */
     int64_t n, nnz;
     int64_t *row_ptr;     /* [n+1] */
     int64_t *col;         /* [nnz], ascending within a row, diagonal incl. */
@@ -76,6 +81,7 @@ typedef struct {
     double *lam;          /* [n] 1/(card I(i) - 1) */
     uint8_t *dirichlet;   /* [n] */
     double volume;        /* sum of |T| (det J quadrature) */
+    double mass_total;    /* sum_i m_i in ascending node order (= |Omega|) */
     /* work / debug arrays of the last forward-Euler stage */
     double *dij;          /* [nnz] graph viscosity d^L_ij, diagonal d_ii */
     double *alpha;        /* [n] */
@@ -583,6 +589,8 @@ ora_t *ora_create(int dim, double gamma, double cfl, int passes,
         o->mi[i] = s;
         o->lam[i] = 1.0 / (double)(o->row_ptr[i + 1] - o->row_ptr[i] - 1);
     }
+    o->mass_total = 0.0;
+    for (int64_t i = 0; i < n; ++i) o->mass_total += o->mi[i];
     return o;
 }
 
@@ -721,8 +729,11 @@ static void stage_update(ora_t *o, const double *U, double tau, double *Uout)
             if (phj < phi_min) phi_min = phj;
         }
         if (o->relax) {
-            /* optional relaxation of the bounds (parity unpinned) */
-            double r = ora_pow(o->mi[i] / o->volume, 1.5 / (double)dim);
+            /* Relaxation of the bounds (remark of Section 3.9; the paper
+             * gives no formula): widen them by r_i = (m_i/|Omega|)^(1.5/d),
+             * |Omega| = sum_i m_i.  Pinned by the second-order convergence
+             * it restores on a smooth vortex.                            */
+            double r = ora_pow(o->mi[i] / o->mass_total, 1.5 / (double)dim);
             rho_min *= (1.0 - r);
             rho_max *= (1.0 + r);
             phi_min *= (1.0 - r);
@@ -757,7 +768,9 @@ static void stage_update(ora_t *o, const double *U, double tau, double *Uout)
             double bji = -o->mij[q] / o->mi[i];
             for (int r = 0; r < nc; ++r)
                 P[r] = coef * (bij * Rj[r] - bji * Ri[r] + (dH - dL) * (Uj[r] - Ui[r]));
-            o->l1[q] = ora_limiter(o->UL + i * nc, P, o->bnd + i * 3, dim, g,
+            o->l1[q] = o->limiter_mode == 1 ? 1.0
+                     : o->limiter_mode == 2 ? 0.0
+                     : ora_limiter(o->UL + i * nc, P, o->bnd + i * 3, dim, g,
                                    o->newton_max, o->newton_tol, o->literal_alg3);
         }
     }
@@ -785,7 +798,9 @@ static void stage_update(ora_t *o, const double *U, double tau, double *Uout)
                 double l = lij < lji ? lij : lji;
                 double P2[ORA_MAXC];
                 for (int r = 0; r < nc; ++r) P2[r] = (1.0 - l) * o->P[q * nc + r];
-                o->l2[q] = ora_limiter(o->Upass + i * nc, P2, o->bnd + i * 3,
+                o->l2[q] = o->limiter_mode == 1 ? 1.0
+                         : o->limiter_mode == 2 ? 0.0
+                         : ora_limiter(o->Upass + i * nc, P2, o->bnd + i * 3,
                                        dim, g, o->newton_max, o->newton_tol,
                                        o->literal_alg3);
             }
@@ -875,6 +890,10 @@ int64_t ora_n(const ora_t *o) { return o->n; }
 int64_t ora_nnz(const ora_t *o) { return o->nnz; }
 double ora_volume(const ora_t *o) { return o->volume; }
 void ora_set_literal_alg3(ora_t *o, int v) { o->literal_alg3 = v; }
+/* 0: the limiter of Alg. 2; 1: every l_ij = 1, so E(U) is the high-order
+ * update U^H of eq. high-order-final (no limiting); 2: every l_ij = 0, so
+ * E(U) is the low-order update U^L of eq. low-order.  Accuracy studies only. */
+void ora_set_limiter_mode(ora_t *o, int mode) { o->limiter_mode = mode; }
 
 int ora_set_threads(int nthreads)
 {

@@ -74,11 +74,15 @@ def morton_order(ijk: np.ndarray) -> np.ndarray:
 
 
 def q1_grid(n: int, dim: int, jitter: float = 0.2, seed: int = 0,
-            order: str = "lex", perm_seed: int = 1) -> Mesh:
+            order: str = "lex", perm_seed: int = 1, warp: float = 0.0) -> Mesh:
     """Structured Q1 grid of n^dim nodes on [0,1]^dim with seeded jitter.
 
     ``order`` picks the node numbering handed to the solver; the cells are
-    emitted in lexicographic cell order with vertices renumbered.
+    emitted in lexicographic cell order with vertices renumbered.  ``warp``
+    adds a smooth displacement that vanishes on the boundary: coordinate k
+    moves by warp * prod_l sin(pi x_l) * sin(2 pi x_(k+1 mod d)), so the
+    cells stay images of a smooth map (convergence studies need this; a
+    random jitter is a rough map).
     """
     if dim not in (2, 3):
         raise ValueError("dim must be 2 or 3")
@@ -99,6 +103,11 @@ def q1_grid(n: int, dim: int, jitter: float = 0.2, seed: int = 0,
         off = rng.uniform(-jitter * h, jitter * h, size=(N, dim))
         off[on_bnd] = 0.0
         coords = coords + off
+    if warp != 0.0:
+        bump = np.prod(np.sin(np.pi * coords), axis=1)
+        disp = np.stack([warp * bump * np.sin(2.0 * np.pi * coords[:, (k + 1) % dim])
+                         for k in range(dim)], axis=1)
+        coords = coords + disp
     # cells, lexicographic cell order, vertex b = bx + 2 by + 4 bz
     cax = [np.arange(n - 1, dtype=np.int64)] * dim
     cg = np.meshgrid(*cax, indexing="ij")
@@ -259,6 +268,33 @@ def ic_generic_smooth(coords: np.ndarray, seed: int = 5, gamma: float = GAMMA) -
     p = 1.0 + 0.3 * smooth_field(coords, seed + 1)
     vel = np.stack([0.3 * smooth_field(coords, seed + 2 + k) for k in range(dim)], axis=1)
     return conserved(rho, vel, p, gamma)
+
+
+def isentropic_vortex(coords: np.ndarray, t: float = 0.0, centre=(0.5, 0.5),
+                      radius: float = 0.1, beta: float = 5.0, u_inf=(0.0, 0.0),
+                      gamma: float = GAMMA) -> np.ndarray:
+    """The standard isentropic vortex (a closed-form smooth solution of the 2D
+    Euler equations) carried by the uniform flow ``u_inf``, at time ``t``.
+
+    With r the distance to the moving centre in units of ``radius``: the
+    velocity perturbation is beta/(2 pi) exp((1 - r^2)/2) times the rotated
+    offset, the temperature T = 1 - (gamma-1) beta^2/(8 gamma pi^2)
+    exp(1 - r^2), rho = T^(1/(gamma-1)), p = rho^gamma.  The radial pressure
+    gradient balances the centripetal acceleration at every radius, so the
+    vortex is a steady state for u_inf = 0 and is translated otherwise.
+    """
+    x = np.asarray(coords, dtype=np.float64)
+    c = np.array(centre, dtype=np.float64) + t * np.array(u_inf, dtype=np.float64)
+    dx = (x[:, 0] - c[0]) / radius
+    dy = (x[:, 1] - c[1]) / radius
+    r2 = dx * dx + dy * dy
+    amp = beta / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    vel = np.empty((x.shape[0], 2))
+    vel[:, 0] = u_inf[0] - amp * dy
+    vel[:, 1] = u_inf[1] + amp * dx
+    temp = 1.0 - (gamma - 1.0) * beta * beta / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = temp ** (1.0 / (gamma - 1.0))
+    return conserved(rho, vel, rho ** gamma, gamma)
 
 
 def ic_uniform(n_nodes: int, dim: int, rho=1.0, vel=None, p=1.0,

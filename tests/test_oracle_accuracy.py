@@ -1,0 +1,158 @@
+"""Accuracy pins of the oracle's high-order update (CPU).
+
+The high-order update of Sections 3.4-3.5 is formally second order: its
+Galerkin fluxes, the entropy-viscosity indicator of Section 3.8 that makes
+d^H_ij = d_ij (alpha_i + alpha_j)/2 vanish at O(h) on smooth data, and one
+Neumann step of the consistent mass matrix (b_ij = -m_ij/m_j).  These tests
+pin that part against the exact solution of the Euler equations (a
+translated isentropic vortex) and against the linear algebra of the
+consistent-mass system, and show, by planting mistakes in copies of the
+oracle, which mistakes the pins catch.
+
+Modes of the oracle's limiter used here: 'high' sets every l_ij = 1 (the
+unlimited high-order update), 'low' every l_ij = 0 (the low-order update),
+'paper' runs Alg. 2; ``relax`` widens the bounds by (m_i/|Omega|)^(1.5/d)
+(the remark of Section 3.9; the formula is this project's reading).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2007_00094_amd import inputs
+
+SIDES = (17, 33, 65)
+T_END = 0.1
+U_INF = (0.5, 0.25)
+RADIUS = 0.1
+
+
+def vortex_error(oracle_mod, n, mode, relax=False, library=None):
+    """Mass-weighted L1 density error of the translated isentropic vortex at
+    t = 0.1 on a smoothly warped n x n Q1 mesh of [0,1]^2, boundary held at
+    the initial state, measured within 0.25 of the moved centre (the held
+    boundary's influence does not reach there by t = 0.1)."""
+    mesh = inputs.q1_grid(n, 2, jitter=0.0, warp=0.05)
+    U = inputs.isentropic_vortex(mesh.coords, 0.0, radius=RADIUS, u_inf=U_INF)
+    o = oracle_mod.Oracle(mesh, relax=relax, library=library)
+    o.set_limiter_mode(mode)
+    t = 0.0
+    while t < T_END - 1e-14:
+        dt = min(o.max_dt(U), T_END - t)
+        U, used, st = o.step(U, dt=dt)
+        assert st in (0, 1)
+        t += used
+    exact = inputs.isentropic_vortex(mesh.coords, T_END, radius=RADIUS, u_inf=U_INF)
+    centre = 0.5 + np.array(U_INF) * T_END
+    near = np.sum((mesh.coords - centre) ** 2, axis=1) < 0.25 ** 2
+    m = o.m_i()[near]
+    return float(np.sum(m * np.abs(U[near, 0] - exact[near, 0])) / np.sum(m))
+
+
+def orders(errs):
+    """Observed orders between successive refinements (h halves)."""
+    return [float(np.log2(errs[k] / errs[k + 1])) for k in range(len(errs) - 1)]
+
+
+def test_vortex_high_order_update_is_second_order(oracle_mod):
+    """Unlimited high-order update (l = 1): order >= 1.8 on every refinement
+    (measured 2.65, 2.94); the low-order update (l = 0) stays near first
+    order (0.33, 0.56 on these coarse meshes) and is >= 10x less accurate."""
+    high = [vortex_error(oracle_mod, n, "high") for n in SIDES]
+    low = [vortex_error(oracle_mod, n, "low") for n in SIDES]
+    print("vortex L1(rho) high", high, orders(high), "low", low, orders(low))
+    assert min(orders(high)) >= 1.8, (high, orders(high))
+    assert max(orders(low)) <= 1.2, (low, orders(low))
+    assert low[-1] >= 10.0 * high[-1]
+
+
+def test_vortex_limited_update_order_with_and_without_relaxation(oracle_mod):
+    """With the bounds relaxed, the limited scheme keeps second order (>= 1.8,
+    measured 2.65, 2.94); with the paper's strict bounds the limiter clips the
+    smooth extremum of the entropy-uniform vortex and the order falls
+    (measured 1.95, 1.27; reported, asserted only to be below the relaxed
+    scheme's accuracy)."""
+    relaxed = [vortex_error(oracle_mod, n, "paper", relax=True) for n in SIDES]
+    strict = [vortex_error(oracle_mod, n, "paper") for n in SIDES]
+    print("vortex L1(rho) relaxed", relaxed, orders(relaxed),
+          "strict bounds", strict, orders(strict))
+    assert min(orders(relaxed)) >= 1.8, (relaxed, orders(relaxed))
+    assert strict[-1] > 2.0 * relaxed[-1]
+
+
+# Mistakes planted in copies of the oracle (text replacements of its C
+# source).  Each must make the second-order pin fail.
+_DH = "double dH = dL * (o->alpha[i] + o->alpha[j]) / 2.0;"
+_N = "double N = fabs(a - etab + er_i * b[0]);"
+_P = "P[r] = coef * (bij * Rj[r] - bji * Ri[r] + (dH - dL) * (Uj[r] - Ui[r]));"
+MUTANTS = {
+    # the indicator ignored: high-order viscosity equal to the low-order one
+    "dH_is_dL": [(_DH, "double dH = dL;")],
+    # a dropped term of the indicator's numerator N_i (Section 3.8)
+    "N_drops_term": [(_N, "double N = fabs(a - etab);")],
+    # a wrong sign inside N_i
+    "N_wrong_sign": [(_N, "double N = fabs(a + etab + er_i * b[0]);")],
+    # the consistent-mass correction with the wrong sign
+    "b_wrong_sign": [(_P, "P[r] = coef * (-bij * Rj[r] + bji * Ri[r] + (dH - dL) * (Uj[r] - Ui[r]));")],
+}
+
+
+def _mutant(oracle_mod, tmp_path_factory, name, edits):
+    src = open(oracle_mod._SRC).read()
+    for old, new in edits:
+        assert src.count(old) >= 1, (name, old)
+        src = src.replace(old, new)
+    path = str(tmp_path_factory.mktemp("mutant") / f"libora_{name}.so")
+    return oracle_mod.build_variant(src, path)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_vortex_order_catches_planted_mistake(oracle_mod, tmp_path_factory, name):
+    lib = _mutant(oracle_mod, tmp_path_factory, name, MUTANTS[name])
+    errs = [vortex_error(oracle_mod, n, "high", library=lib) for n in SIDES]
+    assert min(orders(errs)) < 1.8, (name, errs, orders(errs))
+
+
+def _neumann_residual_error(oracle_mod, dim, n, library=None):
+    mesh = inputs.q1_grid(n, dim, jitter=0.2, seed=4, order="random")
+    U = inputs.ic_generic_smooth(mesh.coords, seed=6)
+    o = oracle_mod.Oracle(mesh, dirichlet=np.zeros(mesh.n_nodes, np.uint8),
+                          library=library)
+    o.set_limiter_mode("high")
+    tau = o.max_dt(U)
+    V, _ = o.euler_stage(U, tau)
+    R, mi = o.R(), o.m_i()
+    rp, col, mij = o.row_ptr(), o.col(), o.m_ij()
+    Mc = sp.csr_matrix((mij, col, rp), shape=(o.n, o.n))
+    Minv = sp.diags(1.0 / mi)
+    E = sp.diags(mi) - Mc
+    delta = (V - U) / tau
+    resid = Mc @ delta - R
+    expect = -(E @ (Minv @ (E @ (Minv @ R))))
+    scale = np.max(np.abs(R), axis=0)
+    return float(np.max(np.abs(resid - expect) / scale))
+
+
+@pytest.mark.parametrize("dim,n", [(2, 17), (3, 7)])
+def test_high_order_stage_is_one_neumann_step_of_the_consistent_mass_system(oracle_mod, dim, n):
+    """With l = 1 a stage is U^H.  The high-order system is
+    M_c (U^H - U)/tau = R with the consistent mass matrix M_c; the scheme
+    solves it with one Neumann step around the lumped matrix M_L, whose
+    residual is exactly M_c (U^H - U)/tau - R = -(E M_L^-1)^2 R with
+    E = M_L - M_c.  Checked with the exported m_ij, m_i (pinned by closed
+    forms elsewhere) on a jittered mesh where the m_i differ."""
+    assert _neumann_residual_error(oracle_mod, dim, n) <= 1e-11
+
+
+NEUMANN_MUTANTS = {
+    # b_ij and b_ji with m_i and m_j exchanged
+    "b_masses_exchanged": [("double bij = -o->mij[q] / o->mi[j];\n            double bji = -o->mij[q] / o->mi[i];",
+                            "double bij = -o->mij[q] / o->mi[i];\n            double bji = -o->mij[q] / o->mi[j];")],
+    # the lumped-mass update (no consistent-mass correction)
+    "b_dropped": [(_P, "P[r] = coef * ((dH - dL) * (Uj[r] - Ui[r]));")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(NEUMANN_MUTANTS))
+def test_neumann_identity_catches_planted_mistake(oracle_mod, tmp_path_factory, name):
+    lib = _mutant(oracle_mod, tmp_path_factory, name, NEUMANN_MUTANTS[name])
+    assert _neumann_residual_error(oracle_mod, 2, 17, library=lib) > 1e-6
