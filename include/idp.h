@@ -71,8 +71,14 @@ extern "C" {
  * cfl: c_cfl of Section 3.3 (0 < cfl <= 1); limiter_passes: 1 or 2
  * (Section 3.5 asks for at least two); newton_max_iter, newton_tol: the
  * iteration cap and the tolerance TOL of Alg. 2 (the paper gives no
- * values; defaults 2 and 1e-10); relax_bounds must be 0 (the relaxation
- * of the remark in Section 3.9 is not part of this build).  sell_sigma:
+ * values; defaults 2 and 1e-10); relax_bounds: 0 (default) keeps the
+ * bounds of Section 3.9, 1 widens them as the remark of Section 3.9
+ * suggests, by r_i = (m_i/|Omega|)^(1.5/d) with |Omega| = sum_i m_i:
+ * rho_min (1 - r_i), rho_max (1 + r_i), phi_min (1 - r_i) (the paper gives
+ * no formula; this one restores second order at smooth extrema); single
+ * meshes only (idp_create_batch returns IDP_ENOTSUP) and no adjoint (the
+ * adjoint entry points return IDP_ENOTSUP); other values: IDP_EINVAL.
+ * sell_sigma:
  * the sorting window sigma of the SELL-C-sigma row layout (Section 4.3;
  * C = 64): rows are sorted by length, longest first and stable, within
  * consecutive windows of sell_sigma rows (a positive multiple of 64), or
@@ -158,7 +164,15 @@ int idp_export_matrices(const idp_ctx *ctx, int64_t *row_ptr, int32_t *col,
  *  IDP_DBG_L2     min(l_ij, l_ji) of pass 2 [nnz]  (diagonal: 1)
  *  IDP_DBG_UPASS  state after pass 1 [n][nc]
  *  IDP_DBG_TAUI   m_i/(-2 d_ii) [n]
- * Synchronises.                                                          */
+ *  IDP_DBG_P      P_ij of eq. def-p, before pass 1 [nnz][nc] (diagonal: 0)
+ *  IDP_DBG_L1RAW  row candidate l_ij of pass 1 (Alg. 2 on U^L_i, P_ij and
+ *                 the bounds of row i) [nnz]  (diagonal: 1)
+ *  IDP_DBG_L2RAW  row candidate of pass 2 (on the pass-1 state of i and
+ *                 (1 - min(l_ij, l_ji)) P_ij) [nnz]  (diagonal: 1)
+ * The last three are recomputed from the stage's buffers with the sweeps'
+ * own device functions (the sweeps keep only the pair minima); they
+ * allocate a temporary device array of one double per entry (IDP_ENOMEM if
+ * that fails).  Synchronises.  IDP_EINVAL for an unknown code.           */
 #define IDP_DBG_D 0
 #define IDP_DBG_ALPHA 1
 #define IDP_DBG_R 2
@@ -168,6 +182,9 @@ int idp_export_matrices(const idp_ctx *ctx, int64_t *row_ptr, int32_t *col,
 #define IDP_DBG_L2 6
 #define IDP_DBG_UPASS 7
 #define IDP_DBG_TAUI 8
+#define IDP_DBG_P 9
+#define IDP_DBG_L1RAW 10
+#define IDP_DBG_L2RAW 11
 int idp_debug_export(idp_ctx *ctx, int what, double *host_out);
 
 /* Per-kernel timing with HIP events on the context's stream: on = 1 starts
@@ -262,8 +279,8 @@ int idp_batch_tune(idp_ctx *ctx, const double *U_dev, int n_steps, idp_schedule 
 
 /* ------------------------------------------------------------ adjoint
  * Reverse mode of the scheme with a fixed time step (the tau of every stage
- * given), for one mesh (IDP_ENOTSUP on a batch context or with
- * newton_max_iter > 8).  Every max, min, clamp and branch of the forward is
+ * given), for one mesh (IDP_ENOTSUP on a batch context, with
+ * newton_max_iter > 8 or with relaxed bounds).  Every max, min, clamp and branch of the forward is
  * differentiated on the branch the forward took (at an exact tie, the
  * branch its comparison picks); the limiter's Newton iterations (Alg. 2/3)
  * are differentiated as unrolled.  Cotangent arrays are device [n][nc],

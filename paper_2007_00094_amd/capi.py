@@ -38,6 +38,9 @@ IDP_DBG_L1 = 5
 IDP_DBG_L2 = 6
 IDP_DBG_UPASS = 7
 IDP_DBG_TAUI = 8
+IDP_DBG_P = 9
+IDP_DBG_L1RAW = 10
+IDP_DBG_L2RAW = 11
 
 
 class idp_params(C.Structure):

@@ -333,7 +333,7 @@ int check_params(const idp_params &p)
         p.newton_max_iter < 0 || p.newton_max_iter > 64 || !(p.newton_tol >= 0.0) ||
         p.sell_sigma < 0 || p.sell_sigma % idp::kSellC != 0)
         return IDP_EINVAL;
-    if (p.relax_bounds) return IDP_ENOTSUP;
+    if (p.relax_bounds != 0 && p.relax_bounds != 1) return IDP_EINVAL;
     return IDP_OK;
 }
 
@@ -617,6 +617,25 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
         }
         if (herr) { idp_destroy(c); return IDP_EMESH; }
     }
+    if (p.relax_bounds) {
+        // |Omega| = sum_i m_i, summed in the caller's node order
+        std::vector<double> mi_host;
+        try {
+            mi_host.resize(size_t(g.n));
+        } catch (const std::bad_alloc &) {
+            idp_destroy(c);
+            return IDP_ENOMEM;
+        }
+        TRY(dalloc(c, &P.relax_r, g.n));
+        HIPTRY(hipMemcpyAsync(mi_host.data(), P.mi, size_t(g.n) * 8, hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPTRY(hipStreamSynchronize(c->stream));
+        double mass_total = 0.0;
+        for (int64_t i = 0; i < g.n; ++i)
+            mass_total += mi_host[c->pos.empty() ? size_t(i) : size_t(c->pos[size_t(i)])];
+        idp::launch_relax(P, c->stream, mass_total);
+        HIPTRY(hipGetLastError());
+    }
     // keep what the CSR exports need (in the caller's numbering), drop the
     // rest of the host graph
     if (!c->pos.empty()) {
@@ -679,6 +698,7 @@ int idp_create_batch(idp_ctx **out, const idp_params *prm, int n_inst,
     const int rc = check_params(*prm);
     if (rc != IDP_OK) return rc;
     if (prm->flags & IDP_FLAG_RENUMBER) return IDP_ENOTSUP;   // single meshes only
+    if (prm->relax_bounds) return IDP_ENOTSUP;                 // single meshes only
     std::vector<MeshIn> meshes;
     try {
         meshes.resize(n_inst);
@@ -877,6 +897,26 @@ int idp_debug_export(idp_ctx *c, int what, double *out)
     case IDP_DBG_UL: return node_to_host(c, c->P.rowB, idp::kRowB, 0, nc, out);
     case IDP_DBG_BOUNDS: return node_to_host(c, c->P.rowB, idp::kRowB, nc, 3, out);
     case IDP_DBG_UPASS: return node_to_host(c, c->P.upass, idp::kRowU, 0, nc, out);
+    case IDP_DBG_P:
+    case IDP_DBG_L1RAW:
+    case IDP_DBG_L2RAW: {
+        // recomputed from the last stage's buffers into a temporary array
+        double *tmp = nullptr;
+        if (hipMalloc(&tmp, size_t(c->sell_size) * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return IDP_ENOMEM;
+        }
+        int rc = IDP_OK;
+        const int kind = what == IDP_DBG_P ? 0 : what == IDP_DBG_L1RAW ? 1 : 2;
+        const int ncomp = kind == 0 ? nc : 1;
+        for (int q = 0; q < ncomp && rc == IDP_OK; ++q) {
+            idp::launch_debug_entries(c->P, c->stream, kind, q, tmp);
+            if (hipGetLastError() != hipSuccess) rc = IDP_EHIP;
+            else rc = sell_to_csr(c, tmp, out, ncomp, q);
+        }
+        (void)hipFree(tmp);
+        return rc;
+    }
     default: return IDP_EINVAL;
     }
 }
@@ -969,7 +1009,8 @@ int adj_setup(idp_ctx *c)
 
 int adj_check(idp_ctx *c)
 {
-    if (c->ninst != 1 || c->prm.newton_max_iter > 8) return IDP_ENOTSUP;
+    // the adjoint differentiates the paper's bounds (no relaxation)
+    if (c->ninst != 1 || c->prm.newton_max_iter > 8 || c->prm.relax_bounds) return IDP_ENOTSUP;
     return adj_setup(c);
 }
 

@@ -554,6 +554,13 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
     B[kPackCoef] = tau / (P.lam[i] * mi);   // tau/(lambda_i m_i) of eq. def-p
 #pragma unroll
     for (int r = kPackCoef + 1; r < kPack; ++r) B[r] = 0.0;
+    if (P.relax_r) {
+        // widened bounds (remark of Section 3.9), r_i fixed by the mesh
+        const double rr = P.relax_r[i];
+        rho_min *= (1.0 - rr);
+        rho_max *= (1.0 + rr);
+        phi_min *= (1.0 - rr);
+    }
     W[NC + 0] = rho_min;
     W[NC + 1] = rho_max;
     W[NC + 2] = phi_min;
@@ -1206,6 +1213,60 @@ __global__ void k_math(int kind, int64_t n, const double *x, const double *y, do
     else out[i] = x[i] / y[i];
 }
 
+// Debug export of per-entry quantities the pair sweeps compute and do not
+// keep, from the buffers of the last stage, with the sweeps' own device
+// functions: what 0: component `comp` of P_ij (eq. def-p); 1: the pass-1
+// candidate l_ij (Alg. 2 on U^L_i, P_ij, bounds_i); 2: the pass-2 candidate
+// on (pass-1 state of i, (1 - s1_ij) P_ij, bounds_i).  Diagonal: P_ii = 0,
+// candidates 1.  One thread per row, SELL positions.
+template <int D>
+__global__ void k_debug_entries(StageArgs P, int what, int comp, double *out)
+{
+    constexpr int NC = D + 2;
+    const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (r >= P.nslices * kSlice) return;
+    const int i = P.perm[r];
+    if (i < 0) return;
+    const int L = P.row_len[r];
+    const int64_t off = P.slice_off[r / kSlice] + r % kSlice;
+    NodeB<D> Bi;
+    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
+    const double *W = P.rowB + int64_t(i) * kRowB;
+    const double *Up = P.upass + int64_t(i) * kRowU;
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = off + int64_t(k) * kSlice;
+        const int j = P.scol[e];
+        if (j == i) {
+            out[e] = what == 0 ? 0.0 : 1.0;
+            continue;
+        }
+        NodeB<D> Bj;
+        load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+        double Pd[NC];
+        direction<D>(Bi, Bj, Bi.coef, P.d[e], P.mij[e], Pd);
+        if (what == 0) {
+            out[e] = Pd[comp];
+        } else if (what == 1) {
+            out[e] = row_limiter<D>(W, W, Pd, P);
+        } else {
+            const double l = P.l1[e];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) Pd[q] = (1.0 - l) * Pd[q];
+            out[e] = limiter<D>(Up, Pd, Up[NC], Up[NC + 1], Up[NC + 2], P.gamma, P.newton_max,
+                                P.tol);
+        }
+    }
+}
+
+// Widening of the bounds: r_i = (m_i/|Omega|)^(1.5/d), |Omega| = sum_i m_i
+// (summed on the host in the caller's node order).
+__global__ void k_relax(StageArgs P, double mass_total, double expo)
+{
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= P.n) return;
+    P.relax_r[i] = fpow(P.mi[i] / mass_total, expo);
+}
+
 // ------------------------------------------------------------ launches
 static inline int grid_rows(const StageArgs &P) { return P.per * kXcd; }
 static inline int grid_nodes(int64_t n) { return int((n + kBlock - 1) / kBlock); }
@@ -1233,6 +1294,21 @@ void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
         else
             hipLaunchKernelGGL(k_pair_c<3>, gp, dim3(kBlock), 0, st, P);
     }
+}
+
+void launch_debug_entries(const StageArgs &P, hipStream_t st, int what, int comp, double *out)
+{
+    const dim3 g(unsigned((P.nslices * kSlice + kBlock - 1) / kBlock));
+    if (P.dim == 2)
+        hipLaunchKernelGGL(k_debug_entries<2>, g, dim3(kBlock), 0, st, P, what, comp, out);
+    else
+        hipLaunchKernelGGL(k_debug_entries<3>, g, dim3(kBlock), 0, st, P, what, comp, out);
+}
+
+void launch_relax(const StageArgs &P, hipStream_t st, double mass_total)
+{
+    hipLaunchKernelGGL(k_relax, dim3(grid_nodes(P.n)), dim3(kBlock), 0, st, P, mass_total,
+                       1.5 / double(P.dim));
 }
 
 void launch_begin(const StageArgs &P, hipStream_t st, int clear_status)

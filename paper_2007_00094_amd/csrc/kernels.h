@@ -58,6 +58,9 @@ struct StageArgs {
     double *c0, *c1, *c2, *mij;
     double *ct0, *ct1, *ct2;    // c_ji at the position of c_ij
     double *mi, *lam;
+    // [n] widening r_i = (m_i/|Omega|)^(1.5/d) of the bounds (remark of
+    // Section 3.9), or null: the bounds of the paper, unrelaxed
+    double *relax_r;
     const uint8_t *hold;
     // per-stage work
     double *d;                  // [sell] d_ij, diagonal d_ii
@@ -119,6 +122,10 @@ struct BatchArgs {
     double *dt_rec;             // [nsteps][ninst] tau of every step
 };
 
+// per-entry P_ij component / pass-1 / pass-2 candidates into out [sell]
+void launch_debug_entries(const StageArgs &P, hipStream_t st, int what, int comp, double *out);
+// r_i = (m_i / mass_total)^(1.5/d) into P.relax_r
+void launch_relax(const StageArgs &P, hipStream_t st, double mass_total);
 void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
                      const int32_t *cells, const int64_t *nc_ptr,
                      const int32_t *nc_list, const double gx[3], int *err);

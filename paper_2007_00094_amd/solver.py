@@ -25,7 +25,7 @@ class Solver:
     def __init__(self, mesh=None, *, dim=None, coords=None, cells=None,
                  dirichlet=None, gamma=1.4, cfl=0.5, passes=2, newton_max=2,
                  newton_tol=1e-10, asynchronous=False, stream=None, staging=True,
-                 sell_sigma=0, renumber=False):
+                 sell_sigma=0, renumber=False, relax=False):
         torch = _require_torch_gpu()
         if mesh is not None:
             dim, coords, cells = mesh.dim, mesh.coords, mesh.cells
@@ -46,6 +46,7 @@ class Solver:
             (0 if staging else capi.IDP_FLAG_NO_STAGING) | \
             (capi.IDP_FLAG_RENUMBER if renumber else 0)
         p.sell_sigma = int(sell_sigma)
+        p.relax_bounds = 1 if relax else 0
         self.params = p
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         hd = None
@@ -161,12 +162,13 @@ class Solver:
         capi.IDP_DBG_D: "z", capi.IDP_DBG_L1: "z", capi.IDP_DBG_L2: "z",
         capi.IDP_DBG_ALPHA: "n", capi.IDP_DBG_TAUI: "n", capi.IDP_DBG_R: "nc",
         capi.IDP_DBG_UL: "nc", capi.IDP_DBG_UPASS: "nc", capi.IDP_DBG_BOUNDS: "n3",
+        capi.IDP_DBG_P: "zc", capi.IDP_DBG_L1RAW: "z", capi.IDP_DBG_L2RAW: "z",
     }
 
     def debug(self, what: int) -> np.ndarray:
         kind = self._DBG_SHAPE[what]
         shape = {"z": (self.nnz,), "n": (self.n,), "nc": (self.n, self.nc),
-                 "n3": (self.n, 3)}[kind]
+                 "n3": (self.n, 3), "zc": (self.nnz, self.nc)}[kind]
         out = np.empty(shape)
         capi.check("idp_debug_export", capi.lib().idp_debug_export(
             self._h, int(what), out.ctypes.data_as(capi._dp)))

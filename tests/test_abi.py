@@ -45,7 +45,7 @@ def test_strerror_and_defaults_on_host():
 @pytest.mark.parametrize("field,value,code", [
     ("dim", 4, capi.IDP_EINVAL), ("cfl", 1.5, capi.IDP_EINVAL),
     ("gamma", 1.0, capi.IDP_EINVAL), ("limiter_passes", 3, capi.IDP_EINVAL),
-    ("relax_bounds", 1, capi.IDP_ENOTSUP)])
+    ("relax_bounds", 2, capi.IDP_EINVAL)])
 def test_create_rejects_bad_params_before_any_device_call(field, value, code):
     L = capi.lib()
     p = capi.idp_params()
@@ -97,3 +97,20 @@ def test_create_batch_rejects_bad_arguments_before_any_device_call():
     assert L.idp_batch_tune(None, None, 1, None, None, None) == capi.IDP_EINVAL
     assert L.idp_batch_max_dt(None, None, None) == capi.IDP_EINVAL
     assert L.idp_batch_info(None, None, None) == capi.IDP_EINVAL
+
+
+def test_batch_create_refuses_relaxed_bounds_before_any_device_call():
+    """The relaxation of the bounds is for single meshes only."""
+    L = capi.lib()
+    p = capi.idp_params()
+    L.idp_default_params(C.byref(p), 2)
+    p.relax_bounds = 1
+    h = C.c_void_p()
+    xy = (C.c_double * 8)(0, 0, 1, 0, 0, 1, 1, 1)
+    cells = (C.c_int64 * 4)(0, 1, 2, 3)
+    nn = (C.c_int64 * 1)(4)
+    nc = (C.c_int64 * 1)(1)
+    co = (C.POINTER(C.c_double) * 1)(C.cast(xy, C.POINTER(C.c_double)))
+    ce = (C.POINTER(C.c_int64) * 1)(C.cast(cells, C.POINTER(C.c_int64)))
+    assert L.idp_create_batch(C.byref(h), C.byref(p), 1, nn, co, nc, ce, None, None) == \
+        capi.IDP_ENOTSUP

@@ -112,16 +112,21 @@ def test_stage_intermediates_bitwise(torch, oracle_mod, name, dim, n, order):
              ("tau_i", g(capi.IDP_DBG_TAUI), o.tau_i()), ("R", g(capi.IDP_DBG_R), o.R()),
              ("U^L", g(capi.IDP_DBG_UL), o.U_low()), ("bounds", g(capi.IDP_DBG_BOUNDS), o.bounds()),
              ("min l1", g(capi.IDP_DBG_L1), sym(o.l1())), ("min l2", g(capi.IDP_DBG_L2), sym(o.l2())),
-             ("U pass 1", g(capi.IDP_DBG_UPASS), o.U_pass1()), ("E(U)", E.cpu().numpy(), E_ref)]
+             ("U pass 1", g(capi.IDP_DBG_UPASS), o.U_pass1()), ("E(U)", E.cpu().numpy(), E_ref),
+             ("P", g(capi.IDP_DBG_P), o.P()), ("l1 raw", g(capi.IDP_DBG_L1RAW), o.l1()),
+             ("l2 raw", g(capi.IDP_DBG_L2RAW), o.l2())]
     for nm, a, b in pairs:
         assert np.array_equal(a, b), (nm, np.max(rel_diff(a, b)))
+    # the recomputed candidates are the ones the pair sweeps took the minima of
+    assert np.array_equal(sym(g(capi.IDP_DBG_L1RAW)), g(capi.IDP_DBG_L1))
+    assert np.array_equal(sym(g(capi.IDP_DBG_L2RAW)), g(capi.IDP_DBG_L2))
     assert w == w_ref
     s.close()
 
 
-def _run_steps(torch, oracle_mod, mesh, U0, steps, every_step=True):
-    o = oracle_mod.Oracle(mesh)
-    s = solver(mesh)
+def _run_steps(torch, oracle_mod, mesh, U0, steps, every_step=True, relax=False, **kw):
+    o = oracle_mod.Oracle(mesh, relax=relax)
+    s = solver(mesh, relax=relax, **kw)
     U = torch.tensor(U0, device="cuda")
     Uo = U0.copy()
     worst = 0.0
@@ -143,6 +148,32 @@ def test_step_parity_four_quadrant_50_steps(torch, oracle_mod):
     announce("four-quadrant 2D 33^2, 50 steps")
     mesh, U0 = inputs.workload("four_quadrant_2d")
     assert _run_steps(torch, oracle_mod, mesh, U0, 50) == 0.0
+
+
+@pytest.mark.parametrize("relax,renumber", [(False, False), (True, False), (True, True)])
+def test_step_parity_vortex_relaxed_bounds(torch, oracle_mod, relax, renumber):
+    """Translated isentropic vortex on a smoothly warped 2D 33^2 mesh in
+    random node order, 30 steps, with the paper's bounds and with the
+    bounds widened by (m_i/|Omega|)^(1.5/d) (remark of Section 3.9; |Omega|
+    summed in the caller's node order, also when the library renumbers)."""
+    announce(f"vortex 2D 33^2 warped random order, relax={relax} renumber={renumber}, 30 steps")
+    mesh = inputs.q1_grid(33, 2, jitter=0.0, warp=0.05, order="random")
+    U0 = inputs.isentropic_vortex(mesh.coords, radius=0.1, u_inf=(0.5, 0.25))
+    assert _run_steps(torch, oracle_mod, mesh, U0, 30, relax=relax, renumber=renumber) == 0.0
+
+
+def test_step_parity_relaxed_bounds_3d(torch, oracle_mod):
+    """3D 13^3 Mach 3 blobs, Morton order, relaxed bounds: 5 steps bitwise;
+    the adjoint refuses a relaxed context."""
+    announce("relaxed bounds 3D 13^3 Morton, 5 steps")
+    mesh = inputs.q1_grid(13, 3, 0.2, seed=0, order="morton")
+    U0 = inputs.ic_mach3_blobs(mesh.coords)
+    assert _run_steps(torch, oracle_mod, mesh, U0, 5, relax=True) == 0.0
+    s = solver(mesh, relax=True)
+    U = torch.tensor(U0, device="cuda")
+    with pytest.raises(RuntimeError, match="not supported"):
+        s.forward_checkpoints(U, [1e-4], every=1)
+    s.close()
 
 
 def test_step_parity_sphere_3d(torch, oracle_mod):
