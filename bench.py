@@ -95,9 +95,22 @@ def measured_traffic(kernel):
     return None
 
 
-def cpu_baseline(mesh, U0, radius, steps):
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(mesh, U0, radius, steps, single_steps):
     """The oracle, as it stands, on a patch of the same mesh and state:
-    nodes within graph distance ``radius`` of the mesh centre."""
+    nodes within graph distance ``radius`` of the mesh centre; ``steps``
+    steps with every host thread, then ``single_steps`` on one thread."""
     import oracle
     from paper_2007_00094_amd import inputs
     centre = int(np.argmin(np.sum((mesh.coords - 0.5) ** 2, axis=1)))
@@ -110,11 +123,51 @@ def cpu_baseline(mesh, U0, radius, steps):
     for _ in range(steps):
         U, _, _ = o.step(U, dt=dt)
     t = time.perf_counter() - t0
+    single = None
+    if single_steps > 0:
+        oracle.set_threads(1)
+        t1 = time.perf_counter()
+        for _ in range(single_steps):
+            U, _, _ = o.step(U, dt=dt)
+        t1 = time.perf_counter() - t1
+        oracle.set_threads(threads)
+        single = sub.n_nodes * 3 * single_steps / t1
     return {"value": sub.n_nodes * 3 * steps / t, "unit": "node-updates/s",
             "cores": threads, "kind": "oracle",
+            "single_thread_value": single, "cpu_model": cpu_model(),
+            "host_threads": os.cpu_count(),
             "sample": f"{steps} SSP-RK3 step(s) on a {sub.n_nodes}-node patch "
                       f"(graph radius {radius} around the centre) of the same mesh "
-                      f"and state, fixed dt, {threads} OpenMP threads, {t:.1f} s"}
+                      f"and state, fixed dt, {threads} OpenMP threads, {t:.1f} s; "
+                      f"then {single_steps} step(s) on 1 thread"}
+
+
+def hbm_copy_bandwidth(gib=4.0, reps=3):
+    """Achievable HBM bandwidth: the best of ``reps`` timed device copies of
+    ``gib`` GiB (bytes read + written) and triads a = b + s c (2 read, 1
+    written), in GB/s."""
+    import torch
+    n = int(gib * 2**30 // 8)
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    z = torch.full_like(x, 2.0)
+    best_copy = best_triad = 0.0
+    for _ in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        best_copy = max(best_copy, 16.0 * n / (a.elapsed_time(b) * 1e-3) / 1e9)
+        a.record()
+        torch.add(x, z, alpha=0.5, out=y)
+        b.record()
+        b.synchronize()
+        best_triad = max(best_triad, 24.0 * n / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del x, y, z
+    torch.cuda.empty_cache()
+    return {"copy_GB_per_s": round(best_copy, 1), "triad_GB_per_s": round(best_triad, 1),
+            "bytes_per_array": 8 * n}
 
 
 def batched_bench(steps):
@@ -144,7 +197,7 @@ def batched_bench(steps):
             so.step(u)
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
-    assert all(so.status() in (0, 1) for so in sols)
+    assert all(so.status() == 0 for so in sols), "a batch instance's step failed or warned"
     for so in sols:
         so.close()
     n = int(bs.n)
@@ -176,7 +229,7 @@ def adjoint_bench(steps, every):
     dts = []
     for _ in range(steps):
         dt, st = s.step(U)
-        assert st in (0, 1), f"base run failed: {st}"
+        assert st == 0, f"base run failed or warned: {st}"
         dts.append(dt)
     # cotangent of J = sum_{x_i in box} m_i |m_i|^2 / (2 rho_i) at the final state
     box = torch.tensor(np.all((mesh.coords >= 0.4) & (mesh.coords <= 0.6), axis=1), device="cuda")
@@ -248,6 +301,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--cpu-radius", type=int, default=24)
     ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-single-steps", type=int, default=2,
+                    help="steps of the oracle on one thread (0: skip)")
     ap.add_argument("--newton-max", type=int, default=2,
                     help="Newton iterations of the limiter (the method's default is 2)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
@@ -293,6 +348,8 @@ def main():
         s.step(U)
     torch.cuda.synchronize()
     assert s.status() in (0, 1), "warm-up steps failed"
+    if s.status() == 1:
+        log("WARNING: a warm-up step exceeded a stage-2/3 CFL bound")
     log(f"{args.warmup} warm-up steps done")
 
     s.set_timing(True)
@@ -304,6 +361,9 @@ def main():
     elapsed = time.perf_counter() - t0
     st = s.status()
     assert st in (0, 1), f"timed steps failed: {st}"
+    if st == 1:
+        log("WARNING: a timed step exceeded a stage-2/3 CFL bound (invariant domain not "
+            "guaranteed for it)")
     times = s.kernel_times()
     s.set_timing(False)
     log(f"{args.steps} timed steps in {elapsed:.3f} s")
@@ -337,6 +397,11 @@ def main():
                     "algorithmic_bytes_per_launch": algo[dom]}
 
     s.close()
+    log("achievable HBM bandwidth: 4 GiB copy and triad")
+    roofline["measured_hbm"] = hbm_copy_bandwidth()
+    roofline["frac_of_measured_copy"] = round(
+        roofline["achieved"] / roofline["measured_hbm"]["copy_GB_per_s"], 4) \
+        if roofline["unit"] == "GB/s" else None
     batched = None
     if not args.no_batch:
         log("batched: 64 meshes, tuned schedule vs per-instance loop")
@@ -352,7 +417,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a patch)")
-        cpu = cpu_baseline(mesh, U0, args.cpu_radius, args.cpu_steps)
+        cpu = cpu_baseline(mesh, U0, args.cpu_radius, args.cpu_steps, args.cpu_single_steps)
     out = {
         "metric": "Q1 node-updates/s per RK stage FP64; HBM GB/s; adjoint/forward time ratio",
         "value": value,
@@ -371,6 +436,7 @@ def main():
                    "sell_sigma": args.sell_sigma, "renumbered": args.renumber,
                    "nodes": mesh.n_nodes, "nnz": s.nnz, "stages": stages,
                    "parallelism": "single GPU"},
+        "cfl_warning": st == 1,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

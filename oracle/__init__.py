@@ -15,7 +15,13 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "idp_oracle.c")
-_LIB = os.path.join(_HERE, "libidp_oracle.so")
+# IDP_ORACLE_SANITIZE=1 builds and loads a copy instrumented with the
+# address and undefined-behaviour sanitizers (the host process must then
+# preload the sanitizer runtimes; see the design notes for the command)
+_SANITIZE = os.environ.get("IDP_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libidp_oracle_san.so" if _SANITIZE else "libidp_oracle.so")
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+              "-fno-omit-frame-pointer", "-g"]
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -28,7 +34,8 @@ def build(force: bool = True) -> str:
         tmp = _LIB + ".tmp"
         subprocess.run(
             ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-             "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"],
+             "-fPIC", "-shared", "-Wall", *(_SAN_FLAGS if _SANITIZE else []),
+             "-o", tmp, _SRC, "-lm"],
             check=True)
         os.replace(tmp, _LIB)
     return _LIB

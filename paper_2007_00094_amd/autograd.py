@@ -6,6 +6,12 @@ library's reverse sweep (idp_adjoint_checkpoints): each segment of
 ``every`` steps is recomputed from a checkpoint and stepped backwards, so
 the graph viscosity, the bounds and the limiter coefficients are
 recomputed in the backward, never stored for the whole run.
+
+The solver keeps the checkpoints of its latest forward_checkpoints run only.
+Each forward records which run it was (the solver's checkpoint generation)
+and its initial state; a backward whose run is no longer the latest (another
+ssprk3 or forward_checkpoints on the same solver came between) first redoes
+its own forward from that state, so it never differentiates another run.
 """
 from __future__ import annotations
 
@@ -16,14 +22,22 @@ import torch
 class _SSPRK3Steps(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U0, solver, dts, every):
-        U = U0.detach().clone().contiguous()
+        start = U0.detach().clone().contiguous()
+        U = start.clone()
         solver.forward_checkpoints(U, dts, every)
         ctx.solver, ctx.dts, ctx.every = solver, dts, every
+        ctx.start, ctx.generation = start, solver.checkpoint_generation
         return U
 
     @staticmethod
     def backward(ctx, Ubar):
-        g = ctx.solver.adjoint_checkpoints(ctx.dts, ctx.every, Ubar.contiguous())
+        s = ctx.solver
+        if s.checkpoint_generation != ctx.generation:
+            # another run replaced this one's checkpoints: recompute them
+            U = ctx.start.clone()
+            s.forward_checkpoints(U, ctx.dts, ctx.every)
+            ctx.generation = s.checkpoint_generation
+        g = s.adjoint_checkpoints(ctx.dts, ctx.every, Ubar.contiguous())
         return g, None, None, None
 
 

@@ -128,9 +128,14 @@ class Solver:
             self._h, self._u(U), float(dt), self._u(Ubar_next), self._u(out)))
         return out
 
+    checkpoint_generation = 0
+
     def forward_checkpoints(self, U, dts, every: int):
-        """len(dts) steps in place with the given steps, checkpoints kept."""
+        """len(dts) steps in place with the given steps, checkpoints kept
+        (replacing those of the previous run; checkpoint_generation counts
+        the runs)."""
         d = np.ascontiguousarray(dts, dtype=np.float64)
+        self.checkpoint_generation += 1
         return capi.check("idp_forward_checkpoints", capi.lib().idp_forward_checkpoints(
             self._h, self._u(U), len(d), d.ctypes.data_as(capi._dp), int(every)))
 

@@ -95,7 +95,7 @@ def test_sphere_65_100_steps_against_oracle_reference(torch):
     dts = []
     for k in range(1, g["steps"] + 1):
         dt, st = s.step(U)
-        assert st in (0, 1)
+        assert st == 0
         dts.append(dt)
         if k in g["sha"]:
             Ug = U.cpu().numpy()
@@ -168,6 +168,29 @@ def test_mach3_257_stage_sampled(torch, oracle_mod, big):
         assert np.array_equal(drg, dro)
 
 
+def check_step_patches(oracle_mod, pe, samples, Uin, Uout, dt):
+    """Nodes within distance 1 of each sample after one SSP-RK3 step with
+    step dt from Uin: against the oracle on radius-12 patches (held nodes
+    are the mesh's boundary nodes in the patch)."""
+    for c in samples:
+        sub, nodes, dist = pe.extract([int(c)], 12)
+        o = oracle_mod.Oracle(sub, dirichlet=np.zeros(sub.n_nodes, np.uint8))
+        hold = sub.boundary.astype(bool)
+        u0 = Uin[nodes]
+        e1, _ = o.euler_stage(u0, dt)
+        u1 = e1.copy()
+        u1[hold] = u0[hold]
+        e2, _ = o.euler_stage(u1, dt)
+        u2 = u0 + 0.25 * (e2 - u0)
+        u2[hold] = u0[hold]
+        e3, _ = o.euler_stage(u2, dt)
+        u3 = u0 + (2.0 / 3.0) * (e3 - u0)
+        u3[hold] = u0[hold]
+        exact = dist <= 1
+        assert np.max(rel_err(Uout[nodes[exact]], u3[exact])) <= 1e-12
+        assert np.array_equal(Uout[nodes[exact]], u3[exact]), int(c)
+
+
 def test_mach3_257_step_sampled(torch, oracle_mod, big):
     """One SSP-RK3 step with fixed dt on the whole mesh; nodes within
     distance 1 of each sample against radius-12 oracle patches."""
@@ -175,25 +198,89 @@ def test_mach3_257_step_sampled(torch, oracle_mod, big):
     announce(f"mach3_3d {N_BIG}^3: SSP-RK3 step, {len(samples)} sampled patches")
     U = torch.tensor(U0, device="cuda")
     used, st = s.step(U, dt=DT_BIG)
-    assert used == DT_BIG and st in (0, 1)
-    Ug = U.cpu().numpy()
-    for c in samples:
-        sub, nodes, dist = pe.extract([int(c)], 12)
-        o = oracle_mod.Oracle(sub, dirichlet=np.zeros(sub.n_nodes, np.uint8))
-        hold = sub.boundary.astype(bool)
-        u0 = U0[nodes]
-        e1, _ = o.euler_stage(u0, DT_BIG)
-        u1 = e1.copy()
-        u1[hold] = u0[hold]
-        e2, _ = o.euler_stage(u1, DT_BIG)
-        u2 = u0 + 0.25 * (e2 - u0)
-        u2[hold] = u0[hold]
-        e3, _ = o.euler_stage(u2, DT_BIG)
-        u3 = u0 + (2.0 / 3.0) * (e3 - u0)
-        u3[hold] = u0[hold]
-        exact = dist <= 1
-        assert np.max(rel_err(Ug[nodes[exact]], u3[exact])) <= 1e-12
-        assert np.array_equal(Ug[nodes[exact]], u3[exact])
+    assert used == DT_BIG and st == 0
+    check_step_patches(oracle_mod, pe, samples, U0, U.cpu().numpy(), DT_BIG)
+
+
+def test_mach3_257_cfl_step_sampled_after_three_steps(torch, oracle_mod, big):
+    """The benchmark's stepping (CFL 0.5 dt from stage 1): after 3 steps on
+    the whole mesh, the 4th step's output on sampled patches against the
+    oracle stepping the GPU's state with the GPU's dt (the global minimum,
+    which is below every patch's own bound)."""
+    mesh, U0, s, pe, samples = big
+    announce(f"mach3_3d {N_BIG}^3: 3 CFL steps, then the 4th on {len(samples)} sampled patches")
+    U = torch.tensor(U0, device="cuda")
+    for _ in range(3):
+        _, st = s.step(U)
+        assert st == 0
+    U3 = U.cpu().numpy()
+    dt, st = s.step(U)
+    assert st == 0 and dt > DT_BIG
+    check_step_patches(oracle_mod, pe, samples, U3, U.cpu().numpy(), dt)
+
+
+G = 1.4
+
+
+def check_invariants(E, bounds, phi_in, slack=1e-12):
+    """Strict positivity of density and internal energy, the stage's local
+    density bounds and entropy lower bound (rounding slack 1e-12 relative),
+    on every node, and the minimum principle of the specific entropy: its
+    minimum over the mesh is not below the stage input's (phi_in)."""
+    rho = E[:, 0]
+    rho_eps = E[:, -1] - 0.5 * np.sum(E[:, 1:-1] ** 2, axis=1) / rho
+    assert np.all(rho > 0) and np.all(rho_eps > 0)
+    assert np.all(rho >= bounds[:, 0] * (1 - slack))
+    assert np.all(rho <= bounds[:, 1] * (1 + slack))
+    phi = rho_eps * rho ** (-G)
+    assert np.all(phi >= bounds[:, 2] * (1 - slack))
+    assert phi.min() >= phi_in * (1 - slack), (phi.min(), phi_in)
+
+
+def phi_min(U):
+    """Minimum over the nodes of the specific entropy of a device state."""
+    rho = U[:, 0]
+    rho_eps = U[:, -1] - 0.5 * (U[:, 1:-1] ** 2).sum(1) / rho
+    return float((rho_eps * rho ** (-G)).min())
+
+
+def test_mach3_257_invariants_every_stage_20_cfl_steps(torch, big):
+    """The benchmark's 20 CFL steps, composed from the library's stages
+    (bit for bit its own step, checked against idp_step after every step):
+    after every stage, on all nodes, rho > 0 and rho eps > 0 strictly, the
+    density bounds and the entropy lower bound of that stage hold to 1e-12
+    relative, min phi over the mesh is not below the stage input's, nor below
+    the previous step's; no stage exceeds its CFL bound."""
+    mesh, U0, s, pe, samples = big
+    announce(f"mach3_3d {N_BIG}^3 Morton: 20 CFL steps, invariants after every stage")
+    hold = torch.tensor(mesh.boundary.astype(bool), device="cuda")[:, None]
+    U = torch.tensor(U0, device="cuda")
+    ref = U.clone()
+    for k in range(20):
+        dt = s.max_dt(U)
+        warn = []
+        phi_step = phi_min(U)
+        E1, w = s.euler_stage(U, dt)
+        warn.append(w)
+        check_invariants(E1.cpu().numpy(), s.debug(capi.IDP_DBG_BOUNDS), phi_step)
+        U1 = torch.where(hold, U, E1)
+        E2, w = s.euler_stage(U1, dt)
+        warn.append(w)
+        check_invariants(E2.cpu().numpy(), s.debug(capi.IDP_DBG_BOUNDS), phi_min(U1))
+        U2 = torch.where(hold, U, U + 0.25 * (E2 - U))
+        E3, w = s.euler_stage(U2, dt)
+        warn.append(w)
+        check_invariants(E3.cpu().numpy(), s.debug(capi.IDP_DBG_BOUNDS), phi_min(U2))
+        Un = torch.where(hold, U, U + (2.0 / 3.0) * (E3 - U))
+        assert warn == [0, 0, 0], (k, warn)
+        used, st = s.step(ref)
+        assert st == 0 and used == dt
+        assert torch.equal(ref, Un), k
+        # the step is a convex combination of admissible states: the
+        # minimum of phi over the mesh does not decrease from step to step
+        assert phi_min(Un) >= phi_step * (1 - 1e-12)
+        U = Un
+        print(f"  step {k}: dt {dt:.6e}, min phi {phi_step:.15e}", flush=True)
 
 
 def test_mach3_257_max_dt_property(torch, oracle_mod, big):
