@@ -304,6 +304,34 @@ int idp_step_vjp(idp_ctx *ctx, const double *U_dev, double dt,
 int idp_forward_checkpoints(idp_ctx *ctx, double *U_dev, int n_steps,
                             const double *dt, int every);
 
+/* Decision trace, for tests of the adjoint (its callers are finite-
+ * difference checks that need to know whether two nearby forward runs
+ * took the same branches): n_steps SSP-RK3 steps in place on U_dev with the
+ * steps dt[s] (as idp_forward_checkpoints, no checkpoints kept), and after
+ * every stage its decisions written to the device buffer trace_dev, stage
+ * k (0-based, three per step) at byte offset k * (*stage_bytes):
+ *   [npairs] uint64: per unordered pair {i < j}: bits 0-13 the branches of
+ *     the graph viscosity (which state holds p_max; for each orientation
+ *     evaluated: psi(p_max) < 0, p_max < p~, the two-rarefaction
+ *     numerator > 0, p* > p_i, p* > p_j, which wave speed is larger; which
+ *     orientation set the max), bits 16-23 / 24-31 the limiter of (i,j) /
+ *     (j,i) in pass 1 (density cut at rho_max, at rho_min, clamped;
+ *     enclosure steps taken; how the search ended; a safeguard acted),
+ *     bits 32-39 / 40-47 the same in pass 2, bits 48 / 49 which side set
+ *     min(l_ij, l_ji) in pass 1 / 2;
+ *   then (256-byte aligned) [n] uint32: per node the signs of the terms of
+ *     the smoothness indicator (Section 3.8);
+ *   then (256-byte aligned) [n] int32: per node the row positions of the
+ *     entries that set rho_min, rho_max and phi_min (bits 0-7, 8-15,
+ *     16-23; 255: the node itself).
+ * Node and pair indices are the library's; two traces of one context
+ * compare element by element.  n_steps = 0 only returns *stage_bytes.
+ * trace_bytes must hold 3 n_steps stages.  Returns IDP_OK, IDP_WARN_CFL,
+ * IDP_EINVAL, IDP_ENOTSUP (batch or renumbered context, relaxed bounds,
+ * newton_max_iter > 8), IDP_ENOMEM or IDP_EHIP; synchronises.           */
+int idp_trace_decisions(idp_ctx *ctx, double *U_dev, int n_steps, const double *dt,
+                        void *trace_dev, int64_t trace_bytes, int64_t *stage_bytes);
+
 /* Ubar0 = (d U_final / d U_0)^T Ubar_final for the steps of the last
  * idp_forward_checkpoints call (same n_steps, dt, every): each segment of
  * `every` steps is recomputed from its checkpoint, then stepped backwards

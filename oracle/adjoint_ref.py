@@ -193,7 +193,11 @@ class Reference:
             nl, nr = self._newton(tL, tR, psiL, psiR, dpsiL, dpsiR, rhoP)
             tL = torch.where(active, nl, tL)
             tR = torch.where(active, nr, tR)
-        return tL
+        # a direction below 2^-40 of its state is rounding noise: the
+        # coefficient is taken as locally constant there (its branches are
+        # decided by rounding; the hand-written adjoint does the same)
+        noise = torch.amax(torch.abs(P), 1) <= 2.0 ** -40 * torch.amax(torch.abs(U), 1)
+        return torch.where(noise, tL.detach(), tL)
 
     # ------------------------------------------------------------- stage
     def stage(self, U, tau, keep=None):

@@ -314,68 +314,80 @@ static void ora_psi_line(const double *U, const double *P, double t,
                 phi_min * (gamma + 1.0) * (rg1 / rho) * P[0];
 }
 
-/* Alg. 3, one quadratic Newton step on the bracket [tL, tR]. */
-static void ora_quadratic_newton(double *tL, double *tR, double psiL,
-                                 double psiR, double dpsiL, double dpsiR,
-                                 double rhoP, int literal)
+/* One step of the quadratic enclosure of Alg. 3.  The bracket [a, b] has
+ * Psi(a) = fa >= 0 > Psi(b) = fb and slopes ga, gb.  Divided differences
+ * over the width w = b - a (kept positive by 2^-52): p = (fb - fa)/w,
+ * ka = (p - ga)/w, kb = (gb - p)/w.  The quadratic through (a, fa, ga) and
+ * (b, fb) is fa + ga (t - a) + ka (t - a)^2, the one through (b, fb, gb)
+ * and (a, fa) is fb + gb (t - b) + kb (t - b)^2.  Along the line the third
+ * derivative of Psi has the sign of -rho(P), so (Hermite remainder) for
+ * rho(P) >= 0 the first quadratic stays below Psi on [a, b] and its root
+ * is an admissible new a, the root of the second a new b; for rho(P) < 0
+ * the roots change roles (unless literal, which keeps the printed
+ * assignment).  Each root nearest its expansion point t0 is computed as
+ * t0 - 2 f/(g - sqrt(g^2 - 4 f k)); a negative discriminant counts as 0
+ * and a zero denominator keeps t0.  The new end points are clamped into
+ * [a, b] and kept ordered.                                                */
+static void ora_enclosure_step(double *a, double *b, double fa, double fb,
+                               double ga, double gb, double rhoP, int literal)
 {
-    const double eps = 2.220446049250313e-16; /* 2^-52 */
-    const double sign = -1.0;
-    double scaling = 1.0 / (*tR - *tL + eps);
-    double d11 = dpsiL;
-    double d12 = (psiR - psiL) * scaling;
-    double d22 = dpsiR;
-    double d112 = (d12 - d11) * scaling;
-    double d122 = (d22 - d12) * scaling;
-    double LL = dpsiL * dpsiL - 4.0 * psiL * d112;
-    double LR = dpsiR * dpsiR - 4.0 * psiR * d122;
-    if (LL < 0.0) LL = 0.0;
-    if (LR < 0.0) LR = 0.0;
-    double denL = dpsiL + sign * sqrt(LL);
-    double denR = dpsiR + sign * sqrt(LR);
-    double rootL = denL != 0.0 ? *tL - 2.0 * psiL / denL : *tL;
-    double rootR = denR != 0.0 ? *tR - 2.0 * psiR / denR : *tR;
-    double nl, nr;
-    if (rhoP >= 0.0 || literal) { nl = rootL; nr = rootR; }
-    else { nl = rootR; nr = rootL; }
-    /* keep the new points inside the old bracket, in order */
-    if (!(nl >= *tL)) nl = *tL;
-    if (!(nl <= *tR)) nl = *tR;
-    if (!(nr <= *tR)) nr = *tR;
-    if (!(nr >= *tL)) nr = *tL;
-    if (nr < nl) nr = nl;
-    *tL = nl;
-    *tR = nr;
+    double w_inv = 1.0 / (*b - *a + 0x1p-52);
+    double slope = (fb - fa) * w_inv;
+    double ka = (slope - ga) * w_inv;
+    double kb = (gb - slope) * w_inv;
+    double disc_a = ga * ga - 4.0 * fa * ka;
+    double disc_b = gb * gb - 4.0 * fb * kb;
+    if (disc_a < 0.0) disc_a = 0.0;
+    if (disc_b < 0.0) disc_b = 0.0;
+    double den_a = ga - sqrt(disc_a);
+    double den_b = gb - sqrt(disc_b);
+    double root_a = *a, root_b = *b;
+    if (den_a != 0.0) root_a = *a - 2.0 * fa / den_a;
+    if (den_b != 0.0) root_b = *b - 2.0 * fb / den_b;
+    int swap = rhoP < 0.0 && !literal;
+    double na = swap ? root_b : root_a;
+    double nb = swap ? root_a : root_b;
+    if (!(na >= *a)) na = *a;
+    if (!(na <= *b)) na = *b;
+    if (!(nb <= *b)) nb = *b;
+    if (!(nb >= *a)) nb = *a;
+    if (nb < na) nb = na;
+    *a = na;
+    *b = nb;
 }
 
-/* Alg. 2: limiter.compute(U, P, bounds) -> largest admissible t found. */
+/* Limiter of Section 3.9 (Alg. 2): the largest t in [0, 1] found along
+ * U + t P with rho in [rho_min, rho_max] and Psi(t) >= 0.  The density is
+ * linear in t: cut t = 1 where it leaves a violated bound (the maximum
+ * tested first, then the minimum at the cut value; a zero density
+ * direction gives 0) and keep the cut in [0, 1].  Then at most newton_max
+ * enclosure steps on [a, b] = [0, cut]: stop with b if Psi(b) >= 0, with a
+ * if Psi(a) <= TOL.                                                       */
 double ora_limiter(const double *U, const double *P, const double *bounds,
                    int dim, double gamma, int newton_max, double tol,
                    int literal_alg3)
 {
-    double rho_min = bounds[0], rho_max = bounds[1], phi_min = bounds[2];
-    double rhoU = U[0], rhoP = P[0];
-    double tL = 0.0, tR = 1.0;
-    if (rhoU + tR * rhoP > rho_max)
-        tR = rhoP != 0.0 ? fabs(rho_max - rhoU) / fabs(rhoP) : 0.0;
-    if (rhoU + tR * rhoP < rho_min)
-        tR = rhoP != 0.0 ? fabs(rho_min - rhoU) / fabs(rhoP) : 0.0;
-    if (tR > 1.0) tR = 1.0;
-    if (tR < 0.0) tR = 0.0;
-    for (int it = 0; it < newton_max; ++it) {
-        double psiR;
-        ora_psi_line(U, P, tR, phi_min, dim, gamma, &psiR, NULL);
-        if (psiR >= 0.0) { tL = tR; break; }
-        double psiL;
-        ora_psi_line(U, P, tL, phi_min, dim, gamma, &psiL, NULL);
-        if (psiL <= tol) break;
-        double dpsiL, dpsiR;
-        ora_psi_line(U, P, tL, phi_min, dim, gamma, NULL, &dpsiL);
-        ora_psi_line(U, P, tR, phi_min, dim, gamma, NULL, &dpsiR);
-        ora_quadratic_newton(&tL, &tR, psiL, psiR, dpsiL, dpsiR, rhoP,
-                             literal_alg3);
+    const double rho_min = bounds[0], rho_max = bounds[1], phi_min = bounds[2];
+    const double rho0 = U[0], drho = P[0];
+    double b = 1.0;
+    if (rho0 + b * drho > rho_max)
+        b = drho != 0.0 ? fabs(rho_max - rho0) / fabs(drho) : 0.0;
+    if (rho0 + b * drho < rho_min)
+        b = drho != 0.0 ? fabs(rho_min - rho0) / fabs(drho) : 0.0;
+    if (b > 1.0) b = 1.0;
+    if (b < 0.0) b = 0.0;
+    double a = 0.0;
+    for (int step = 0; step < newton_max; ++step) {
+        double fb, fa, ga, gb;
+        ora_psi_line(U, P, b, phi_min, dim, gamma, &fb, NULL);
+        if (fb >= 0.0) return b;
+        ora_psi_line(U, P, a, phi_min, dim, gamma, &fa, NULL);
+        if (fa <= tol) return a;
+        ora_psi_line(U, P, a, phi_min, dim, gamma, NULL, &ga);
+        ora_psi_line(U, P, b, phi_min, dim, gamma, NULL, &gb);
+        ora_enclosure_step(&a, &b, fa, fb, ga, gb, drho, literal_alg3);
     }
-    return tL;
+    return a;
 }
 
 /* ---------------------------------------------------------- geometry */

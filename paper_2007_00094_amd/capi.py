@@ -87,6 +87,7 @@ SIGNATURES = {
     "idp_euler_stage_vjp": (C.c_int, [_vp, _vp, C.c_double, _vp, _vp]),
     "idp_step_vjp": (C.c_int, [_vp, _vp, C.c_double, _vp, _vp]),
     "idp_forward_checkpoints": (C.c_int, [_vp, _vp, C.c_int, _dp, C.c_int]),
+    "idp_trace_decisions": (C.c_int, [_vp, _vp, C.c_int, _dp, _vp, C.c_int64, _i64p]),
     "idp_adjoint_checkpoints": (C.c_int, [_vp, C.c_int, _dp, C.c_int, _vp, _vp]),
     "idp_debug_adjoint": (C.c_int, [_vp, C.c_int, _dp]),
     "idp_strerror": (C.c_char_p, [C.c_int]),

@@ -365,7 +365,17 @@ __device__ __forceinline__ void newton_vjp(double tL, double tR, double psiL, do
 
 // Alg. 2 backwards for the result's cotangent tb: adds to Ub, Pb and
 // bb = (rho_min, rho_max, phi_min) cotangents.
+//
+// A direction whose largest component is below 2^-40 of the largest
+// component of the state it starts from is rounding noise (a region that
+// is uniform up to rounding): the limiter's branches on it are decided by
+// rounding, and the derivative of the coefficient there (up to |P|/|P_rho|
+// times that of P where a density bound cuts the step) describes the
+// rounding, not the method.  For such a direction the coefficient is taken
+// as locally constant (no contribution here); the coefficient still
+// multiplies the direction's own cotangent in the passes.
 constexpr int kAdjNewtonMax = 8;
+constexpr double kNoiseDirection = 0x1p-40;
 
 // NMAX: the compile-time bound of newton_max; at NMAX <= 2 the loops unroll
 // and the recorded brackets stay in registers.
@@ -375,6 +385,15 @@ __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, do
                                             int newton_max, double tol, double tb,
                                             double *Ub, double *Pb, double *bb)
 {
+    {
+        double pm = 0.0, um = 0.0;
+#pragma unroll
+        for (int r = 0; r < D + 2; ++r) {
+            pm = fmax(pm, fabs(P[r]));
+            um = fmax(um, fabs(U[r]));
+        }
+        if (pm <= kNoiseDirection * um) return;
+    }
     const double rhoU = U[0], rhoP = P[0];
     // density bounds, recorded
     double tR = 1.0;
@@ -402,7 +421,7 @@ __device__ __forceinline__ void limiter_vjp(const double *U, const double *P, do
         double psiL, dpsiL;
         psi_line<D>(U, P, tL, phimin, g, psiL, dpsiL);
         if (psiL <= tol) { brk = 2; break; }
-        quadratic_newton(tL, tR, psiL, psiR, dpsiL, dpsiR, rhoP);
+        enclose_step(tL, tR, psiL, psiR, dpsiL, dpsiR, rhoP);
         ++steps;
     }
     // backwards: cotangents of (tL, tR) at the start of iteration `steps`

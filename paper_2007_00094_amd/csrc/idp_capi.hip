@@ -1326,6 +1326,44 @@ static int forward_checkpoints(idp_ctx *c, double *U, int n_steps, const double 
     return rc;
 }
 
+// Decision traces: see idp_trace_decisions.
+static int64_t trace_stage_bytes(const idp_ctx *c)
+{
+    return int64_t(al256(size_t(c->P.npairs) * 8) + 2 * al256(size_t(c->n) * 4));
+}
+
+int idp_trace_decisions(idp_ctx *c, double *U, int n_steps, const double *dt,
+                        void *trace_dev, int64_t trace_bytes, int64_t *stage_bytes)
+{
+    if (!c || n_steps < 0) return IDP_EINVAL;
+    if (c->pos_dev) return IDP_ENOTSUP;
+    int rc = adj_check(c);   // the stage records of the adjoint (bounds' argk)
+    if (rc != IDP_OK) return rc;
+    const int64_t sb = trace_stage_bytes(c);
+    if (stage_bytes) *stage_bytes = sb;
+    if (n_steps == 0) return IDP_OK;
+    if (!U || !dt || !trace_dev || trace_bytes < sb * 3 * int64_t(n_steps)) return IDP_EINVAL;
+    for (int s = 0; s < n_steps; ++s)
+        if (!(dt[s] > 0.0) || !std::isfinite(dt[s])) return IDP_EINVAL;
+    const idp::StageArgs P = rec_args(c);
+    const size_t pb = al256(size_t(c->P.npairs) * 8), rb = al256(size_t(c->n) * 4);
+    char *base = static_cast<char *>(trace_dev);
+    for (int s = 0; s < n_steps; ++s)
+        for (int k = 0; k < 3; ++k) {
+            const double *in = k == 0 ? U : c->U1;
+            double *out = k == 2 ? U : c->U1;
+            stage_p(c, P, in, U, out, k + 1, k == 0 ? 1 : 0, k == 0 ? dt[s] : 0.0,
+                    k == 0 ? 1 : 0, s == 0 && k == 0 ? 1 : 0);
+            char *at = base + (int64_t(3 * s + k)) * sb;
+            idp::launch_trace(P, c->stream, reinterpret_cast<unsigned long long *>(at),
+                              reinterpret_cast<unsigned *>(at + pb));
+            if (hipMemcpyAsync(at + pb + rb, c->argk, size_t(c->n) * 4, hipMemcpyDeviceToDevice,
+                               c->stream) != hipSuccess)
+                return IDP_EHIP;
+        }
+    return finish(c);
+}
+
 static int adjoint_checkpoints(idp_ctx *c, int n_steps, const double *dt, int every,
                                const double *Ubar_final, double *Ubar0);
 

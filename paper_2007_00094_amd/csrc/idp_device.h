@@ -206,27 +206,41 @@ __host__ __device__ inline GasC make_gas(double g)
 // commutes), so a pair evaluates it once.  The state whose pressure is
 // p_max contributes exactly +0 (its shock branch has p - p_s = 0 over a
 // positive root), and x + 0 = x for the other term (never -0), so only the
-// other state's term is evaluated.
-template <int D>
+// other state's term is evaluated.  TR: *code receives 1 if p_i > p_j.
+template <int D, bool TR = false>
 __device__ __forceinline__ double psi_sum(double rhoi, double pi, double ci, double rhoj,
-                                          double pj, double cj, const GasC &G)
+                                          double pj, double cj, const GasC &G,
+                                          unsigned *code = nullptr)
 {
     const bool jlow = pi > pj;
     const double pmax = jlow ? pi : pj;
     const double rho = jlow ? rhoj : rhoi, ps = jlow ? pj : pi, cs = jlow ? cj : ci;
+    if constexpr (TR) *code = jlow ? 1u : 0u;
     return psi_branch<D>(rho, ps, cs, pmax, G.g);
 }
+
+// Decision bits of one wave-speed bound (decision traces): which branch
+// each comparison, clamp and max of the bound took.
+enum : unsigned {
+    kLamPsiNeg = 1u,       // psi(p_max) < 0: p* = p~
+    kLamCapped = 2u,       // p_max < p~ (p* = p_max when psi(p_max) >= 0)
+    kLamNumPos = 4u,       // the two-rarefaction numerator is positive
+    kLamShock1 = 8u,       // p* > p_i: the 1-wave speed grows
+    kLamShock3 = 16u,      // p* > p_j: the 3-wave speed grows
+    kLamWave1 = 32u        // [lambda_1]_neg > [lambda_3]_pos
+};
 
 // The guaranteed upper bound on the maximum wave speed of the 1D Riemann
 // problem along n between U_i (left) and U_j (right) (Section 3.7): the
 // pressure bound is the two-rarefaction pressure p~, capped at p_max when
 // psi(p_max) >= 0 (then p* <= p_max); then the extreme speeds of the 1-wave
 // and 3-wave at that pressure.  S is psi_sum of the pair (psi(p_max)
-// without its u_j - u_i term).
-template <int D>
+// without its u_j - u_i term).  TR: *code receives the kLam* bits.
+template <int D, bool TR = false>
 __device__ __forceinline__ double lambda_max_s(const double *n, const double *Ui, double pi,
                                                double ci, const double *Uj, double pj,
-                                               double cj, double S, const GasC &G)
+                                               double cj, double S, const GasC &G,
+                                               unsigned *code = nullptr)
 {
     double mti = 0.0, mtj = 0.0;
 #pragma unroll
@@ -245,9 +259,14 @@ __device__ __forceinline__ double lambda_max_s(const double *n, const double *Ui
         pstar = ptilde;
     else
         pstar = pmax < ptilde ? pmax : ptilde;
-    const double lam1 = ui - ci * sqrt(1.0 + G.f * pos_part((pstar - pi) / pi));
-    const double lam3 = uj + cj * sqrt(1.0 + G.f * pos_part((pstar - pj) / pj));
+    const double gi = (pstar - pi) / pi, gj = (pstar - pj) / pj;
+    const double lam1 = ui - ci * sqrt(1.0 + G.f * pos_part(gi));
+    const double lam3 = uj + cj * sqrt(1.0 + G.f * pos_part(gj));
     const double a = neg_part(lam1), b = pos_part(lam3);
+    if constexpr (TR)
+        *code = (psi < 0.0 ? kLamPsiNeg : 0u) | (pmax < ptilde ? kLamCapped : 0u) |
+                (num > 0.0 ? kLamNumPos : 0u) | (gi > 0.0 ? kLamShock1 : 0u) |
+                (gj > 0.0 ? kLamShock3 : 0u) | (a > b ? kLamWave1 : 0u);
     return a > b ? a : b;
 }
 
@@ -274,68 +293,115 @@ __device__ __forceinline__ void psi_line(const double *U, const double *P, doubl
     dpsi = P[0] * E + rho * P[D + 1] - mP - phi_min * (g + 1.0) * (rg1 / rho) * P[0];
 }
 
-// Alg. 3 with sign = -1, eps = 2^-52; Lambda clipped at 0; a zero
-// denominator leaves the end point; new points clamped into the old
-// bracket; for rho(P) < 0 (third derivative of Psi positive) the q_R root
-// bounds from below and the q_L root from above.
-__device__ __forceinline__ void quadratic_newton(double &tL, double &tR, double psiL,
-                                                 double psiR, double dpsiL,
-                                                 double dpsiR, double rhoP)
+// Decision bits of one limiter evaluation (decision traces).
+enum : unsigned {
+    kLimRhoMax = 1u,       // the step was cut where rho reaches rho_max
+    kLimRhoMin = 2u,       // ... where rho reaches rho_min
+    kLimClamp = 4u,        // the cut step fell outside [0, 1]
+    kLimStepShift = 3,     // bits 3-4: enclosure steps taken (saturating at 3)
+    kLimExitHi = 32u,      // the search ended with Psi(hi) >= 0 (hi accepted)
+    kLimExitLo = 64u,      // ... with Psi(lo) <= TOL (lo accepted)
+    kLimGuard = 128u       // a safeguard of an enclosure step acted
+};
+
+// One step of the quadratic enclosure of Alg. 3 on the bracket [lo, hi],
+// where Psi(lo) = f_lo >= 0 > Psi(hi) = f_hi, with slopes s_lo, s_hi.  With
+// the divided differences D1 = (f_hi - f_lo)/w over the width w (w kept
+// above zero by 2^-52), k_lo = (D1 - s_lo)/w and k_hi = (s_hi - D1)/w, the
+// quadratics q_lo(t) = f_lo + s_lo (t - lo) + k_lo (t - lo)^2 and
+// q_hi(t) = f_hi + s_hi (t - hi) + k_hi (t - hi)^2 interpolate Psi and its
+// slope at one end and Psi at the other.  Along the line the third
+// derivative of Psi is -phi_min (gamma+1) gamma (gamma-1) rho^(gamma-2)
+// rho(P)^3, so by the Hermite remainder q_lo lies below Psi on the bracket
+// when rho(P) >= 0: its root is a safe new lo and the root of q_hi a new
+// hi; for rho(P) < 0 the two swap.  A root is taken next to its expansion
+// point in the cancellation-free form t0 - 2 f/(s - sqrt(s^2 - 4 f k)),
+// with the discriminant clipped at 0 and a vanishing denominator leaving
+// t0; the new points are kept inside [lo, hi] and in order.  TR: kLimGuard
+// into *code when a clip, a vanishing denominator or a clamp acted.
+template <bool TR = false>
+__device__ __forceinline__ void enclose_step(double &lo, double &hi, double f_lo, double f_hi,
+                                             double s_lo, double s_hi, double rhoP,
+                                             unsigned *code = nullptr)
 {
-    const double eps = 2.220446049250313e-16;
-    const double sign = -1.0;
-    const double scaling = 1.0 / (tR - tL + eps);
-    const double d11 = dpsiL;
-    const double d12 = (psiR - psiL) * scaling;
-    const double d22 = dpsiR;
-    const double d112 = (d12 - d11) * scaling;
-    const double d122 = (d22 - d12) * scaling;
-    double LL = dpsiL * dpsiL - 4.0 * psiL * d112;
-    double LR = dpsiR * dpsiR - 4.0 * psiR * d122;
-    if (LL < 0.0) LL = 0.0;
-    if (LR < 0.0) LR = 0.0;
-    const double denL = dpsiL + sign * sqrt(LL);
-    const double denR = dpsiR + sign * sqrt(LR);
-    const double rootL = denL != 0.0 ? tL - 2.0 * psiL / denL : tL;
-    const double rootR = denR != 0.0 ? tR - 2.0 * psiR / denR : tR;
-    double nl, nr;
-    if (rhoP >= 0.0) { nl = rootL; nr = rootR; }
-    else { nl = rootR; nr = rootL; }
-    if (!(nl >= tL)) nl = tL;
-    if (!(nl <= tR)) nl = tR;
-    if (!(nr <= tR)) nr = tR;
-    if (!(nr >= tL)) nr = tL;
-    if (nr < nl) nr = nl;
-    tL = nl;
-    tR = nr;
+    const double inv_w = 1.0 / (hi - lo + 0x1p-52);
+    const double D1 = (f_hi - f_lo) * inv_w;
+    const double k_lo = (D1 - s_lo) * inv_w;
+    const double k_hi = (s_hi - D1) * inv_w;
+    double disc_lo = s_lo * s_lo - 4.0 * f_lo * k_lo;
+    double disc_hi = s_hi * s_hi - 4.0 * f_hi * k_hi;
+    bool guard = disc_lo < 0.0 || disc_hi < 0.0;
+    if (disc_lo < 0.0) disc_lo = 0.0;
+    if (disc_hi < 0.0) disc_hi = 0.0;
+    const double den_lo = s_lo - sqrt(disc_lo);
+    const double den_hi = s_hi - sqrt(disc_hi);
+    guard = guard || den_lo == 0.0 || den_hi == 0.0;
+    const double root_lo = den_lo != 0.0 ? lo - 2.0 * f_lo / den_lo : lo;
+    const double root_hi = den_hi != 0.0 ? hi - 2.0 * f_hi / den_hi : hi;
+    double new_lo = rhoP >= 0.0 ? root_lo : root_hi;
+    double new_hi = rhoP >= 0.0 ? root_hi : root_lo;
+    const double in_lo = new_lo, in_hi = new_hi;
+    if (!(new_lo >= lo)) new_lo = lo;
+    if (!(new_lo <= hi)) new_lo = hi;
+    if (!(new_hi <= hi)) new_hi = hi;
+    if (!(new_hi >= lo)) new_hi = lo;
+    if (new_hi < new_lo) new_hi = new_lo;
+    if constexpr (TR)
+        if (guard || !(new_lo == in_lo) || !(new_hi == in_hi)) *code |= kLimGuard;
+    lo = new_lo;
+    hi = new_hi;
 }
 
-// Alg. 2: largest admissible t in [0,1] found for U + t P under the
-// bounds (rho_min, rho_max, phi_min).
-template <int D>
+// Limiter of Section 3.9 (Alg. 2): the largest step t in [0, 1] found along
+// V(t) = U + t P that keeps rho(V) in [rho_min, rho_max] and
+// Psi(t) = rho eps(V) - phi_min rho(V)^(gamma+1) >= 0.  The density is
+// linear in t: the full step is cut where it crosses a violated bound (a
+// zero density direction cannot cross: step 0), then kept in [0, 1].  Psi is
+// concave along the line and Psi(0) >= 0: a bracket [lo, hi] = [0, cut]
+// shrinks by enclosure steps, at most newton_max, and the search ends when
+// hi is admissible (returned) or Psi(lo) <= TOL (lo returned).  TR: the
+// kLim* bits into *code.
+template <int D, bool TR = false>
 __device__ __forceinline__ double limiter(const double *U, const double *P,
                                           double rho_min, double rho_max,
                                           double phi_min, double g, int newton_max,
-                                          double tol)
+                                          double tol, unsigned *code = nullptr)
 {
-    const double rhoU = U[0], rhoP = P[0];
-    double tL = 0.0, tR = 1.0;
-    if (rhoU + tR * rhoP > rho_max)
-        tR = rhoP != 0.0 ? fabs(rho_max - rhoU) / fabs(rhoP) : 0.0;
-    if (rhoU + tR * rhoP < rho_min)
-        tR = rhoP != 0.0 ? fabs(rho_min - rhoU) / fabs(rhoP) : 0.0;
-    if (tR > 1.0) tR = 1.0;
-    if (tR < 0.0) tR = 0.0;
-    for (int it = 0; it < newton_max; ++it) {
-        double psiR, dpsiR;
-        psi_line<D>(U, P, tR, phi_min, g, psiR, dpsiR);
-        if (psiR >= 0.0) { tL = tR; break; }
-        double psiL, dpsiL;
-        psi_line<D>(U, P, tL, phi_min, g, psiL, dpsiL);
-        if (psiL <= tol) break;
-        quadratic_newton(tL, tR, psiL, psiR, dpsiL, dpsiR, rhoP);
+    const double r0 = U[0], dr = P[0];
+    unsigned bits = 0;
+    double hi = 1.0;
+    if (r0 + hi * dr > rho_max) {
+        hi = dr != 0.0 ? fabs(rho_max - r0) / fabs(dr) : 0.0;
+        bits |= kLimRhoMax;
     }
-    return tL;
+    if (r0 + hi * dr < rho_min) {
+        hi = dr != 0.0 ? fabs(rho_min - r0) / fabs(dr) : 0.0;
+        bits |= kLimRhoMin;
+    }
+    if (hi > 1.0 || hi < 0.0) bits |= kLimClamp;
+    if (hi > 1.0) hi = 1.0;
+    if (hi < 0.0) hi = 0.0;
+    double lo = 0.0;
+    int steps = 0;
+    for (int it = 0; it < newton_max; ++it) {
+        double f_hi, s_hi;
+        psi_line<D>(U, P, hi, phi_min, g, f_hi, s_hi);
+        if (f_hi >= 0.0) {
+            lo = hi;
+            bits |= kLimExitHi;
+            break;
+        }
+        double f_lo, s_lo;
+        psi_line<D>(U, P, lo, phi_min, g, f_lo, s_lo);
+        if (f_lo <= tol) {
+            bits |= kLimExitLo;
+            break;
+        }
+        enclose_step<TR>(lo, hi, f_lo, f_hi, s_lo, s_hi, dr, &bits);
+        ++steps;
+    }
+    if constexpr (TR) *code = bits | (unsigned(steps < 3 ? steps : 3) << kLimStepShift);
+    return lo;
 }
 
 }  // namespace idp

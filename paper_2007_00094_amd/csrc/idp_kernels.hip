@@ -288,10 +288,11 @@ __device__ __forceinline__ void node_sweep(const StageArgs &P, int64_t i, int64_
 // lambda~(n_ij, U_i, U_j)|c_ij| and lambda~(n_ji, U_j, U_i)|c_ji|, from
 // c_ij, c_ji (stored at the position of c_ij) and the two nodes' pack A
 // records (U, p, c); p_ is the pair's index, e and t its two entries.
-template <int D>
-__device__ __forceinline__ void dpair_eval(const StageArgs &P, int64_t p_, int64_t e,
-                                           int64_t t, const double *c, const double *ct,
-                                           const double *Ai, const double *Aj)
+template <int D, bool TR = false>
+__device__ __forceinline__ double pair_viscosity(const double *c, const double *ct,
+                                                 const double *Ai, const double *Aj,
+                                                 const GasC &G, bool &first,
+                                                 unsigned *code = nullptr)
 {
     constexpr int NC = D + 2;
     double aij = 0.0, aji = 0.0;
@@ -318,29 +319,45 @@ __device__ __forceinline__ void dpair_eval(const StageArgs &P, int64_t p_, int64
         mirror = s <= 0x1p-36 * m;
     }
     double t1 = 0.0, t2 = 0.0;
+    unsigned cs = 0, c1 = 0, c2 = 0;
     // the psi_branch terms of the two states serve both orientations
     const double S = (aij > 0.0 || aji > 0.0)
-                         ? psi_sum<D>(Ai[0], Ai[NC], Ai[NC + 1], Aj[0], Aj[NC], Aj[NC + 1], P.gas)
-                         : 0.0;
+        ? psi_sum<D, TR>(Ai[0], Ai[NC], Ai[NC + 1], Aj[0], Aj[NC], Aj[NC + 1], G, &cs)
+        : 0.0;
     if (aij > 0.0) {
         const double inv = 1.0 / aij;
         double nn[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) nn[q] = c[q] * inv;
-        t1 = lambda_max_s<D>(nn, Ai, Ai[NC], Ai[NC + 1], Aj, Aj[NC], Aj[NC + 1], S, P.gas) * aij;
+        t1 = lambda_max_s<D, TR>(nn, Ai, Ai[NC], Ai[NC + 1], Aj, Aj[NC], Aj[NC + 1], S, G, &c1) *
+             aij;
     }
     if (!mirror && aji > 0.0) {
         const double inv = 1.0 / aji;
         double nn[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) nn[q] = ct[q] * inv;
-        t2 = lambda_max_s<D>(nn, Aj, Aj[NC], Aj[NC + 1], Ai, Ai[NC], Ai[NC + 1], S, P.gas) * aji;
+        t2 = lambda_max_s<D, TR>(nn, Aj, Aj[NC], Aj[NC + 1], Ai, Ai[NC], Ai[NC + 1], S, G, &c2) *
+             aji;
     }
-    const double dd = t1 > t2 ? t1 : t2;
+    first = mirror || t1 > t2;
+    // trace: bit 0 the state with p_max, bits 1-6 the (i, j) bound, bits
+    // 7-12 the (j, i) bound, bit 13 which of the two set d_ij
+    if constexpr (TR) *code = cs | (c1 << 1) | (c2 << 7) | (t1 > t2 ? 1u << 13 : 0u);
+    return t1 > t2 ? t1 : t2;
+}
+
+template <int D>
+__device__ __forceinline__ void dpair_eval(const StageArgs &P, int64_t p_, int64_t e,
+                                           int64_t t, const double *c, const double *ct,
+                                           const double *Ai, const double *Aj)
+{
+    bool first;
+    const double dd = pair_viscosity<D>(c, ct, Ai, Aj, P.gas, first);
     P.d[e] = dd;
     P.d[t] = dd;
     if (P.sided) P.dp[p_] = dd;   // pair order: read by the stage adjoint only
-    if (P.sided) P.sided[p_] = mirror || t1 > t2;
+    if (P.sided) P.sided[p_] = first;
 }
 
 // c_ij and c_ji of pair p (16-byte loads from the pair-order copy)
@@ -383,6 +400,37 @@ __device__ __forceinline__ void dpair_sweep(const StageArgs &P, int64_t pidx, in
     }
     if (!valid_) return;
     dpair_eval<D>(P, p_, e, t, c, ct, Ai, Aj);
+}
+
+// Section 3.8: alpha_i = N_i/D_i from the row sums a_i and b_i, with
+// N_i = |a_i - eta'_i . b_i + (eta_i/rho_i)(b_i)_1| and
+// D_i = |a_i| + sum_k |eta'_{i,k} - delta_1k eta_i/rho_i| |(b_i)_k|
+// (0 if D_i = 0).  TR: *code receives the sign of each term under |.|
+// (bit 0 that of N_i's argument, bit 1 a_i, bits 2.. (b_i)_k, bits
+// 2 + nc.. the eta' terms) and bit 2 + 2 nc for D_i > 0.
+template <int D, bool TR = false>
+__device__ __forceinline__ double indicator(const double *U, double er, double a,
+                                            const double *b, double g,
+                                            unsigned *code = nullptr)
+{
+    constexpr int NC = D + 2;
+    double etap[NC];
+    harten_entropy_derivative<D>(U, g, etap);
+    double etab = 0.0;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) etab += etap[r] * b[r];
+    const double x = a - etab + er * b[0];
+    const double N = fabs(x);
+    double Dn = fabs(a);
+    unsigned bits = (x > 0.0 ? 1u : 0u) | (a > 0.0 ? 2u : 0u);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        const double y = etap[r] - (r == 0 ? er : 0.0);
+        Dn += fabs(y) * fabs(b[r]);
+        bits |= (b[r] > 0.0 ? 1u << (2 + r) : 0u) | (y > 0.0 ? 1u << (2 + NC + r) : 0u);
+    }
+    if constexpr (TR) *code = bits | (Dn > 0.0 ? 1u << (2 + 2 * NC) : 0u);
+    return Dn > 0.0 ? N / Dn : 0.0;
 }
 
 // --------------------------------------------------------- row diagonal
@@ -447,16 +495,7 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
     P.taui[i] = ti;
     atomicMin(taumin + inst_, (unsigned long long)__double_as_longlong(ti));
     if (with_alpha) {
-        double etap[NC];
-        harten_entropy_derivative<D>(Ai.U, g, etap);
-        double etab = 0.0;
-#pragma unroll
-        for (int r = 0; r < NC; ++r) etab += etap[r] * b[r];
-        const double N = fabs(a - etab + Ai.er * b[0]);
-        double Dn = fabs(a);
-#pragma unroll
-        for (int r = 0; r < NC; ++r) Dn += fabs(etap[r] - (r == 0 ? Ai.er : 0.0)) * fabs(b[r]);
-        const double al = Dn > 0.0 ? N / Dn : 0.0;
+        const double al = indicator<D>(Ai.U, Ai.er, a, b, g);
         P.alpha[i] = al;
         P.packL[int64_t(i) * kPackL + kPackLAlpha] = al;
         // pack A's copy is read only by the stage adjoint, which runs on
@@ -1258,6 +1297,113 @@ __global__ void k_debug_entries(StageArgs P, int what, int comp, double *out)
     }
 }
 
+// Decision traces (tests only): after a stage, the branch every
+// comparison, clamp, max and min of the stage took, recomputed from the
+// stage's buffers with the sweeps' own device functions.
+//  k_trace_pairs, one thread per pair: bits 0-13 the viscosity's
+//    (pair_viscosity), bits 16-23 / 24-31 the pass-1 limiter of (i,j) /
+//    (j,i), bits 32-39 / 40-47 those of pass 2 (kLim* bits), bit 48 / 49
+//    whether l_ij < l_ji in pass 1 / 2;
+//  k_trace_rows, one thread per row: the indicator's signs (indicator).
+template <int D>
+__global__ void k_trace_pairs(StageArgs P, unsigned long long *out)
+{
+    constexpr int NC = D + 2;
+    const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (p >= P.npairs) return;
+    const int64_t e = P.pair_e[p];
+    const int i = P.pair_i[p], j = P.pair_j[p];
+    double c[D], ct[D];
+    c[0] = P.c0[e];
+    c[1] = P.c1[e];
+    ct[0] = P.ct0[e];
+    ct[1] = P.ct1[e];
+    if constexpr (D == 3) {
+        c[2] = P.c2[e];
+        ct[2] = P.ct2[e];
+    }
+    double Ai[NC + 2], Aj[NC + 2];
+#pragma unroll
+    for (int k = 0; k < NC + 2; ++k) {
+        Ai[k] = P.packA[int64_t(i) * kPack + k];
+        Aj[k] = P.packA[int64_t(j) * kPack + k];
+    }
+    bool first;
+    unsigned cv = 0;
+    pair_viscosity<D, true>(c, ct, Ai, Aj, P.gas, first, &cv);
+    NodeB<D> Bi, Bj;
+    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
+    load_b<D>(P.packB + int64_t(j) * kPack, Bj);
+    const double dL = P.d[e], m = P.mij[e];
+    double Pij[NC], Pji[NC];
+    direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
+    direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
+    const double *Wi = P.rowB + int64_t(i) * kRowB, *Wj = P.rowB + int64_t(j) * kRowB;
+    unsigned a1 = 0, b1 = 0, a2 = 0, b2 = 0;
+    const double lij = limiter<D, true>(Wi, Pij, Wi[NC], Wi[NC + 1], Wi[NC + 2], P.gamma,
+                                        P.newton_max, P.tol, &a1);
+    const double lji = limiter<D, true>(Wj, Pji, Wj[NC], Wj[NC + 1], Wj[NC + 2], P.gamma,
+                                        P.newton_max, P.tol, &b1);
+    unsigned long long code = cv | (a1 << 16) | (b1 << 24) | (lij < lji ? 1ull << 48 : 0ull);
+    if (P.passes >= 2) {
+        const double l = P.l1[e];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            Pij[q] = (1.0 - l) * Pij[q];
+            Pji[q] = (1.0 - l) * Pji[q];
+        }
+        const double *Ui = P.upass + int64_t(i) * kRowU, *Uj = P.upass + int64_t(j) * kRowU;
+        const double mij2 = limiter<D, true>(Ui, Pij, Ui[NC], Ui[NC + 1], Ui[NC + 2], P.gamma,
+                                             P.newton_max, P.tol, &a2);
+        const double mji2 = limiter<D, true>(Uj, Pji, Uj[NC], Uj[NC + 1], Uj[NC + 2], P.gamma,
+                                             P.newton_max, P.tol, &b2);
+        code |= (static_cast<unsigned long long>(a2) << 32) |
+                (static_cast<unsigned long long>(b2) << 40) | (mij2 < mji2 ? 1ull << 49 : 0ull);
+    }
+    out[p] = code;
+}
+
+template <int D>
+__global__ void k_trace_rows(StageArgs P, unsigned *out)
+{
+    constexpr int NC = D + 2;
+    const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (r >= P.nslices * kSlice) return;
+    const int i = P.perm[r];
+    if (i < 0) return;
+    const int L = P.row_len[r];
+    const int64_t off = P.slice_off[r / kSlice] + r % kSlice;
+    NodeA<D> Ai;
+    load_a_fwd<D>(P.packA + int64_t(i) * kPack, Ai);
+    double Fi[NC][D];
+    flux<D>(Ai.U, Ai.v, Ai.p, Fi);
+    double a = 0.0, b[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) b[q] = 0.0;
+    // the row sums of the diagonal sweep, in its order
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = off + int64_t(k) * kSlice;
+        NodeA<D> Aj;
+        load_a_fwd<D>(P.packA + int64_t(P.scol[e]) * kPack, Aj);
+        double c[D];
+        c[0] = P.c0[e];
+        c[1] = P.c1[e];
+        if constexpr (D == 3) c[2] = P.c2[e];
+        double mc = 0.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) mc += Aj.U[1 + q] * c[q];
+        a += (Aj.er - Ai.er) * mc;
+        double Fj[NC][D], fd[NC];
+        flux<D>(Aj.U, Aj.v, Aj.p, Fj);
+        flux_diff_dot<D>(Fi, Fj, c, fd);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) b[q] += fd[q];
+    }
+    unsigned code = 0;
+    indicator<D, true>(Ai.U, Ai.er, a, b, P.gamma, &code);
+    out[i] = code;
+}
+
 // Widening of the bounds: r_i = (m_i/|Omega|)^(1.5/d), |Omega| = sum_i m_i
 // (summed on the host in the caller's node order).
 __global__ void k_relax(StageArgs P, double mass_total, double expo)
@@ -1303,6 +1449,20 @@ void launch_debug_entries(const StageArgs &P, hipStream_t st, int what, int comp
         hipLaunchKernelGGL(k_debug_entries<2>, g, dim3(kBlock), 0, st, P, what, comp, out);
     else
         hipLaunchKernelGGL(k_debug_entries<3>, g, dim3(kBlock), 0, st, P, what, comp, out);
+}
+
+void launch_trace(const StageArgs &P, hipStream_t st, unsigned long long *pairs,
+                  unsigned *rows)
+{
+    const dim3 gp(unsigned((P.npairs + kBlock - 1) / kBlock));
+    const dim3 gr(unsigned((P.nslices * kSlice + kBlock - 1) / kBlock));
+    if (P.dim == 2) {
+        if (P.npairs) hipLaunchKernelGGL(k_trace_pairs<2>, gp, dim3(kBlock), 0, st, P, pairs);
+        hipLaunchKernelGGL(k_trace_rows<2>, gr, dim3(kBlock), 0, st, P, rows);
+    } else {
+        if (P.npairs) hipLaunchKernelGGL(k_trace_pairs<3>, gp, dim3(kBlock), 0, st, P, pairs);
+        hipLaunchKernelGGL(k_trace_rows<3>, gr, dim3(kBlock), 0, st, P, rows);
+    }
 }
 
 void launch_relax(const StageArgs &P, hipStream_t st, double mass_total)

@@ -122,6 +122,9 @@ struct BatchArgs {
     double *dt_rec;             // [nsteps][ninst] tau of every step
 };
 
+// decision traces of the last stage: [npairs] pair codes, [n] row codes
+void launch_trace(const StageArgs &P, hipStream_t st, unsigned long long *pairs,
+                  unsigned *rows);
 // per-entry P_ij component / pass-1 / pass-2 candidates into out [sell]
 void launch_debug_entries(const StageArgs &P, hipStream_t st, int what, int comp, double *out);
 // r_i = (m_i / mass_total)^(1.5/d) into P.relax_r

@@ -139,6 +139,23 @@ class Solver:
         return capi.check("idp_forward_checkpoints", capi.lib().idp_forward_checkpoints(
             self._h, self._u(U), len(d), d.ctypes.data_as(capi._dp), int(every)))
 
+    def trace_decisions(self, U, dts, out=None):
+        """len(dts) steps in place with the given steps, every stage's
+        decisions into a device byte tensor (allocated if out is None);
+        returns (trace [3 len(dts), stage_bytes] uint8, stage_bytes)."""
+        torch = _require_torch_gpu()
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        sb = C.c_int64(0)
+        capi.check("idp_trace_decisions", capi.lib().idp_trace_decisions(
+            self._h, None, 0, None, None, 0, C.byref(sb)))
+        nb = int(sb.value)
+        if out is None:
+            out = torch.empty((3 * len(d), nb), dtype=torch.uint8, device=U.device)
+        capi.check("idp_trace_decisions", capi.lib().idp_trace_decisions(
+            self._h, self._u(U), len(d), d.ctypes.data_as(capi._dp),
+            C.c_void_p(out.data_ptr()), out.numel(), C.byref(sb)))
+        return out, nb
+
     def adjoint_checkpoints(self, dts, every: int, Ubar_final):
         """Cotangent of the initial state of the last forward_checkpoints run."""
         torch = _require_torch_gpu()
