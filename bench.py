@@ -288,6 +288,9 @@ def main():
     ap.add_argument("--order", default="morton", choices=["morton", "random", "lex"])
     ap.add_argument("--renumber", action="store_true",
                     help="the library renumbers the nodes along a Morton curve")
+    ap.add_argument("--split-p", action="store_true",
+                    help="the paper's variant 3: the low-order sweep stores the viscous "
+                         "part of P_ij for the limiter sweeps and passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched measurement")
     ap.add_argument("--batch-steps", type=int, default=100)
@@ -339,7 +342,8 @@ def main():
     log(f"mesh {mesh.n_nodes} nodes, {mesh.n_cells} cells in {time.perf_counter() - t:.1f} s")
     t = time.perf_counter()
     s = Solver(mesh, asynchronous=True, newton_max=args.newton_max,
-               staging=not args.no_staging, sell_sigma=args.sell_sigma, renumber=args.renumber)
+               staging=not args.no_staging, sell_sigma=args.sell_sigma, renumber=args.renumber,
+               split_p=args.split_p)
     torch.cuda.synchronize()
     log(f"solver created: nnz {s.nnz}, {s.device_bytes / 2**30:.1f} GiB device, "
         f"{time.perf_counter() - t:.1f} s")
@@ -379,7 +383,8 @@ def main():
     kernels = {k: {"ms_per_launch": round(times[k][0] / times[k][1], 4),
                    "GB_per_s": round(algo[k] / (times[k][0] / times[k][1] / 1e3) / 1e9, 1)}
                for k in algo if times[k][1]}
-    traffic = measured_traffic(dom) if args.n == 257 and args.order == "morton" else None
+    traffic = measured_traffic(dom) if (args.n == 257 and args.order == "morton" and
+                                        not args.split_p and not args.renumber) else None
     if dom == "pair_viscosity":
         # bound by FP64 issue, not by memory: priced against the vector FP64 peak
         flops = VISCOSITY_FLOP_PER_PAIR * (s.nnz - mesh.n_nodes) / 2
@@ -434,6 +439,7 @@ def main():
         "config": {"workload": f"mach3_3d_{args.n}^3_{args.order}",
                    "newton_max_iter": args.newton_max, "lds_staging": not args.no_staging,
                    "sell_sigma": args.sell_sigma, "renumbered": args.renumber,
+                   "split_p_variant3": args.split_p,
                    "nodes": mesh.n_nodes, "nnz": s.nnz, "stages": stages,
                    "parallelism": "single GPU"},
         "cfl_warning": st == 1,

@@ -66,6 +66,14 @@ extern "C" {
                                    order.  For meshes numbered without
                                    locality.  Single meshes only
                                    (idp_create_batch returns IDP_ENOTSUP)  */
+#define IDP_FLAG_SPLIT_P 8      /* the paper's variant 3 of Section 5: the
+                                   low-order sweep stores the viscous part
+                                   (d^H_ij - d^L_ij)(U_j - U_i) of P_ij per
+                                   entry (nc doubles) and the limiter sweeps
+                                   and passes read it instead of forming it
+                                   (same results, bit for bit; more memory
+                                   traffic).  Single meshes only, no adjoint
+                                   (IDP_ENOTSUP)                           */
 
 /* Parameters of the scheme.  gamma: ratio of specific heats (Section 2);
  * cfl: c_cfl of Section 3.3 (0 < cfl <= 1); limiter_passes: 1 or 2

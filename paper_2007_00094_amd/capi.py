@@ -26,6 +26,7 @@ IDP_ESCRATCH = -9
 IDP_FLAG_ASYNC = 1
 IDP_FLAG_NO_STAGING = 2
 IDP_FLAG_RENUMBER = 4
+IDP_FLAG_SPLIT_P = 8
 IDP_SCHED_LAUNCHES = 1
 IDP_SCHED_PERSISTENT = 2
 

@@ -494,6 +494,11 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
     TRY(dalloc(c, &P.upass, g.n * idp::kRowU));
     TRY(dalloc(c, &P.alpha, g.n));
     TRY(dalloc(c, &P.taui, g.n));
+    if (p.flags & IDP_FLAG_SPLIT_P) {
+        // the paper's variant 3: the viscous part of P_ij per entry
+        TRY(dalloc(c, &P.q, S * (dim + 2)));
+        P.qstride = S;
+    }
     TRY(dalloc(c, &c->U1, g.n * (dim + 2)));
     TRY(dalloc(c, &c->scal, scal_bytes(K)));
     uint8_t *hold = nullptr;
@@ -699,6 +704,7 @@ int idp_create_batch(idp_ctx **out, const idp_params *prm, int n_inst,
     if (rc != IDP_OK) return rc;
     if (prm->flags & IDP_FLAG_RENUMBER) return IDP_ENOTSUP;   // single meshes only
     if (prm->relax_bounds) return IDP_ENOTSUP;                 // single meshes only
+    if (prm->flags & IDP_FLAG_SPLIT_P) return IDP_ENOTSUP;     // single meshes only
     std::vector<MeshIn> meshes;
     try {
         meshes.resize(n_inst);
@@ -1010,7 +1016,9 @@ int adj_setup(idp_ctx *c)
 int adj_check(idp_ctx *c)
 {
     // the adjoint differentiates the paper's bounds (no relaxation)
-    if (c->ninst != 1 || c->prm.newton_max_iter > 8 || c->prm.relax_bounds) return IDP_ENOTSUP;
+    if (c->ninst != 1 || c->prm.newton_max_iter > 8 || c->prm.relax_bounds ||
+        (c->prm.flags & IDP_FLAG_SPLIT_P))
+        return IDP_ENOTSUP;
     return adj_setup(c);
 }
 

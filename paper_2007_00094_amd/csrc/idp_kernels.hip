@@ -509,7 +509,7 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
 // block's LDS staging, else from per-lane loads (3D: its per-entry
 // arithmetic hides them better than a cooperative gather) or a cooperative
 // gather (2D).
-template <int D, class F>
+template <int D, bool SP = false, class F>
 __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int64_t send,
                                           const F &fetch)
 {
@@ -567,6 +567,12 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
             R[r] += -fd[r] + dH * (Aj.U[r] - Ai.U[r]);
             Lw[r] += -fd[r] + dL * (Aj.U[r] - Ai.U[r]);
         }
+        if constexpr (SP) {
+            // variant 3: the direction's viscous part for steps 4 to 6
+#pragma unroll
+            for (int r = 0; r < NC; ++r)
+                P.q[int64_t(r) * P.qstride + e] = (dH - dL) * (Aj.U[r] - Ai.U[r]);
+        }
         double rbar = 0.5 * (Ai.U[0] + Aj.U[0]);
         if (dL > 0.0) rbar -= fd[0] / (2.0 * dL);
         if (rbar < rho_min) { rho_min = rbar; kmn = k; }
@@ -611,7 +617,7 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
 // Step 4, once per unordered pair: l_ij from (U^L_i, P_ij, bounds_i) and
 // l_ji from (U^L_j, P_ji, bounds_j), each evaluated exactly as its own row
 // would; s_ij = s_ji = min(l_ij, l_ji) stored at (i,j) and (j,i).
-template <int D>
+template <int D, bool SP = false>
 __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int64_t pend,
                                            double2 *lw)
 {
@@ -633,8 +639,19 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
             gather_b<D>(P.packB, i, lw, Bi);
             gather_b<D>(P.packB, j, lw, Bj);
         }
-        direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
-        direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
+        if constexpr (SP) {
+            double Q[NC], nQ[NC];
+#pragma unroll
+            for (int r = 0; r < NC; ++r) {
+                Q[r] = P.q[int64_t(r) * P.qstride + e];
+                nQ[r] = -Q[r];
+            }
+            direction_q<D>(Bi, Bj, Bi.coef, m, Q, Pij);
+            direction_q<D>(Bj, Bi, Bj.coef, m, nQ, Pji);
+        } else {
+            direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
+            direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
+        }
     }
     constexpr int NW = CH::rowB;
     double lij, lji;
@@ -665,7 +682,7 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
 
 // -------------------------------------------------------- row pass 1
 // Step 5, first half: U_i = U^L_i + sum_{j != i} lambda_i s_ij P_ij.
-template <int D, class F>
+template <int D, bool SP = false, class F>
 __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, int64_t send,
                                             const F &fetch)
 {
@@ -712,7 +729,14 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
         NodeB<D> Bj;
         unpack_b<D, false>(rec, Bj);
         double Pd[NC];
-        direction<D>(Bi, Bj, coef, dL, m, Pd);
+        if constexpr (SP) {
+            double Q[NC];
+#pragma unroll
+            for (int r = 0; r < NC; ++r) Q[r] = P.q[int64_t(r) * P.qstride + ENTRY(k)];
+            direction_q<D>(Bi, Bj, coef, m, Q, Pd);
+        } else {
+            direction<D>(Bi, Bj, coef, dL, m, Pd);
+        }
 #pragma unroll
         for (int r = 0; r < NC; ++r) V[r] += lam * l * Pd[r];
     }
@@ -733,7 +757,7 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
 // ------------------------------------------------------ pair limiter 2
 // Step 5, second half, once per unordered pair: candidates of pass 2 on the
 // rescaled directions (1 - s_ij) P_ij from the pass-1 states.
-template <int D>
+template <int D, bool SP = false>
 __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int64_t pend,
                                            double2 *lw)
 {
@@ -752,8 +776,19 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
             gather_b<D>(P.packB, i, lw, Bi);
             gather_b<D>(P.packB, j, lw, Bj);
         }
-        direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
-        direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
+        if constexpr (SP) {
+            double Q[NC], nQ[NC];
+#pragma unroll
+            for (int r = 0; r < NC; ++r) {
+                Q[r] = P.q[int64_t(r) * P.qstride + e];
+                nQ[r] = -Q[r];
+            }
+            direction_q<D>(Bi, Bj, Bi.coef, m, Q, Pij);
+            direction_q<D>(Bj, Bi, Bj.coef, m, nQ, Pji);
+        } else {
+            direction<D>(Bi, Bj, Bi.coef, dL, m, Pij);
+            direction<D>(Bj, Bi, Bj.coef, dL, m, Pji);
+        }
     }
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
@@ -795,7 +830,7 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
 // Step 6: U_i += sum_{j != i} lambda_i s2_ij (1 - s1_ij) P_ij, then
 // mode 0: out = E(U); 1: out = E (stage 1); 2: out = U0 + 1/4 (E - U0);
 // 3: out = U0 + 2/3 (E - U0); modes 1-3 keep held nodes at U0.
-template <int D, class F>
+template <int D, bool SP = false, class F>
 __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, int64_t send,
                                             const double *U0, double *out, int mode,
                                             const F &fetch)
@@ -844,7 +879,14 @@ __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, in
             NodeB<D> Bj;
             unpack_b<D, false>(rec, Bj);
             double Pd[NC];
-            direction<D>(Bi, Bj, coef, dL, m, Pd);
+            if constexpr (SP) {
+                double Q[NC];
+#pragma unroll
+                for (int r = 0; r < NC; ++r) Q[r] = P.q[int64_t(r) * P.qstride + ENTRY(k)];
+                direction_q<D>(Bi, Bj, coef, m, Q, Pd);
+            } else {
+                direction<D>(Bi, Bj, coef, dL, m, Pd);
+            }
 #pragma unroll
             for (int r = 0; r < NC; ++r) {
                 const double P2 = (1.0 - s1) * Pd[r];
@@ -1011,16 +1053,17 @@ __global__ void __launch_bounds__(kBlock, 4) k_diag(StageArgs P, int with_alpha)
                   GatherFetch<kDiagChunks<D>>{P.packA, lw});
 }
 
-template <int D>
+template <int D, bool SP>
 __global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
 {
     constexpr int NCH = kPackL / 2;
     if constexpr (D == 3) {
-        low_sweep<D>(P, ROW_SLICE(P), P.nslices, LaneTailFetch<NCH, NCH - 1, kPackL>{P.packL});
+        low_sweep<D, SP>(P, ROW_SLICE(P), P.nslices,
+                         LaneTailFetch<NCH, NCH - 1, kPackL>{P.packL});
     } else {
         WAVE_LDS(NCH)
-        low_sweep<D>(P, ROW_SLICE(P), P.nslices,
-                     GatherTailFetch<NCH, NCH - 1, kPackL>{P.packL, lw});
+        low_sweep<D, SP>(P, ROW_SLICE(P), P.nslices,
+                         GatherTailFetch<NCH, NCH - 1, kPackL>{P.packL, lw});
     }
 }
 
@@ -1044,34 +1087,35 @@ struct LowFetch {
     }
 };
 
-template <int D>
+template <int D, bool SP>
 __global__ void __launch_bounds__(kBlock) k_lim1p(StageArgs P)
 {
     WAVE_LDS(Chunks<D>::packB)
-    lim1_sweep<D>(P, PAIR_INDEX(P), P.npairs, lw);
+    lim1_sweep<D, SP>(P, PAIR_INDEX(P), P.npairs, lw);
 }
 
-template <int D>
+template <int D, bool SP>
 __global__ void __launch_bounds__(kBlock) k_pass1a(StageArgs P)
 {
     WAVE_LDS(Chunks<D>::packBrow)
-    pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
+    pass1_sweep<D, SP>(P, ROW_SLICE(P), P.nslices,
+                       GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
 }
 
-template <int D>
+template <int D, bool SP>
 __global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
 {
     WAVE_LDS(Chunks<D>::packB)
-    lim2_sweep<D>(P, PAIR_INDEX(P), P.npairs, lw);
+    lim2_sweep<D, SP>(P, PAIR_INDEX(P), P.npairs, lw);
 }
 
-template <int D>
+template <int D, bool SP>
 __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0, double *out,
                                                   int mode)
 {
     WAVE_LDS(Chunks<D>::packBrow)
-    pass2_sweep<D>(P, ROW_SLICE(P), P.nslices, U0, out, mode,
-                   GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
+    pass2_sweep<D, SP>(P, ROW_SLICE(P), P.nslices, U0, out, mode,
+                       GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
 }
 
 // LDS-staged row sweeps: the block first stages its rows' neighbourhood
@@ -1093,28 +1137,28 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
         CALL;                                                                \
     }
 
-template <int D>
+template <int D, bool SP>
 __global__ void __launch_bounds__(kBlock) k_pass1a_h(StageArgs P)
 {
     constexpr int NCH = Chunks<D>::packBrow;
-    HALO_SWEEP(NCH, NCH - 1, kPack, P.packB, pass1_sweep<D>(P, ROW_SLICE(P), P.nslices, f_))
+    HALO_SWEEP(NCH, NCH - 1, kPack, P.packB, (pass1_sweep<D, SP>(P, ROW_SLICE(P), P.nslices, f_)))
 }
 
-template <int D>
+template <int D, bool SP>
 __global__ void __launch_bounds__(kBlock) k_pass2_h(StageArgs P, const double *U0, double *out,
                                                     int mode)
 {
     constexpr int NCH = Chunks<D>::packBrow;
     HALO_SWEEP(NCH, NCH - 1, kPack, P.packB,
-               pass2_sweep<D>(P, ROW_SLICE(P), P.nslices, U0, out, mode, f_))
+               (pass2_sweep<D, SP>(P, ROW_SLICE(P), P.nslices, U0, out, mode, f_)))
 }
 
 // staged low-order sweep
-template <int D>
+template <int D, bool SP>
 __global__ void __launch_bounds__(kBlock) k_low_h(StageArgs P)
 {
     HALO_SWEEP(kPackL / 2, kPackL / 2 - 1, kPackL, P.packL,
-               low_sweep<D>(P, ROW_SLICE(P), P.nslices, f_))
+               (low_sweep<D, SP>(P, ROW_SLICE(P), P.nslices, f_)))
 }
 
 // ------------------------------------------------ persistent batch launch
@@ -1498,6 +1542,21 @@ static inline int grid_pairs(const StageArgs &P) { return P.pper * kXcd; }
         else                                                                            \
             hipLaunchKernelGGL(K<3>, dim3(grid), dim3(kBlock), 0, st, __VA_ARGS__);     \
     } while (0)
+// sweeps with a variant-3 instantiation (the viscous part of P_ij stored)
+#define LAUNCH_DS(K, grid, ...)                                                         \
+    do {                                                                                \
+        if (P.q) {                                                                      \
+            if (P.dim == 2)                                                             \
+                hipLaunchKernelGGL((K<2, true>), dim3(grid), dim3(kBlock), 0, st, __VA_ARGS__); \
+            else                                                                        \
+                hipLaunchKernelGGL((K<3, true>), dim3(grid), dim3(kBlock), 0, st, __VA_ARGS__); \
+        } else {                                                                        \
+            if (P.dim == 2)                                                             \
+                hipLaunchKernelGGL((K<2, false>), dim3(grid), dim3(kBlock), 0, st, __VA_ARGS__); \
+            else                                                                        \
+                hipLaunchKernelGGL((K<3, false>), dim3(grid), dim3(kBlock), 0, st, __VA_ARGS__); \
+        }                                                                               \
+    } while (0)
 
 void launch_dpair(const StageArgs &P, hipStream_t st)
 {
@@ -1513,25 +1572,25 @@ void launch_diag(const StageArgs &P, hipStream_t st, int with_alpha)
 void launch_low(const StageArgs &P, hipStream_t st)
 {
     if (P.halo_cnt)
-        LAUNCH_D(k_low_h, grid_rows(P), P);
+        LAUNCH_DS(k_low_h, grid_rows(P), P);
     else
-        LAUNCH_D(k_low, grid_rows(P), P);
+        LAUNCH_DS(k_low, grid_rows(P), P);
 }
-void launch_lim1p(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_lim1p, grid_pairs(P), P); }
+void launch_lim1p(const StageArgs &P, hipStream_t st) { LAUNCH_DS(k_lim1p, grid_pairs(P), P); }
 void launch_pass1a(const StageArgs &P, hipStream_t st)
 {
     if (P.halo_cnt)
-        LAUNCH_D(k_pass1a_h, grid_rows(P), P);
+        LAUNCH_DS(k_pass1a_h, grid_rows(P), P);
     else
-        LAUNCH_D(k_pass1a, grid_rows(P), P);
+        LAUNCH_DS(k_pass1a, grid_rows(P), P);
 }
-void launch_lim2p(const StageArgs &P, hipStream_t st) { LAUNCH_D(k_lim2p, grid_pairs(P), P); }
+void launch_lim2p(const StageArgs &P, hipStream_t st) { LAUNCH_DS(k_lim2p, grid_pairs(P), P); }
 void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out, int mode)
 {
     if (P.halo_cnt)
-        LAUNCH_D(k_pass2_h, grid_rows(P), P, U0, out, mode);
+        LAUNCH_DS(k_pass2_h, grid_rows(P), P, U0, out, mode);
     else
-        LAUNCH_D(k_pass2, grid_rows(P), P, U0, out, mode);
+        LAUNCH_DS(k_pass2, grid_rows(P), P, U0, out, mode);
 }
 
 void launch_batch_init(const StageArgs &P, const BatchArgs &B, hipStream_t st, int clear_status)

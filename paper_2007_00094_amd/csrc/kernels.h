@@ -94,6 +94,11 @@ struct StageArgs {
     const int32_t *inst_slice;  // [nslices] instance of each slice (null: one)
     unsigned long long *taumin; // [ninst] bits of min_i m_i/(-2 d_ii)
     double *tau, *bound;        // [ninst]
+    // the paper's variant 3 (IDP_FLAG_SPLIT_P), or null: [nc][qstride] the
+    // viscous part (d^H - d^L)(U_j - U_i) of P_ij per SELL entry, written by
+    // the low-order sweep and read by the limiter sweeps and the passes
+    double *q;
+    int64_t qstride;
     const double *dt_inst;      // [ninst] per-instance dt of a batch call, or null
     int *status;
 };

@@ -462,6 +462,19 @@ __device__ __forceinline__ void direction(const NodeB<D> &Bi, const NodeB<D> &Bj
         Pd[r] = coef * (bij * Bj.R[r] - bji * Bi.R[r] + (dH - dL) * (Bj.U[r] - Bi.U[r]));
 }
 
+// The same with the viscous part Q = (d^H - d^L)(U_j - U_i) given (the
+// paper's variant 3 stores it in step 3): the same value, bit for bit.
+template <int D>
+__device__ __forceinline__ void direction_q(const NodeB<D> &Bi, const NodeB<D> &Bj,
+                                            double coef, double mij, const double *Q,
+                                            double *Pd)
+{
+    const double bij = -mij / Bj.m;
+    const double bji = -mij / Bi.m;
+#pragma unroll
+    for (int r = 0; r < D + 2; ++r) Pd[r] = coef * (bij * Bj.R[r] - bji * Bi.R[r] + Q[r]);
+}
+
 // Candidate of row i on the line U + t P_ij under the bounds of row i.
 template <int D>
 __device__ __forceinline__ double row_limiter(const double *Urow, const double *W,

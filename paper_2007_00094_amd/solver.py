@@ -25,7 +25,7 @@ class Solver:
     def __init__(self, mesh=None, *, dim=None, coords=None, cells=None,
                  dirichlet=None, gamma=1.4, cfl=0.5, passes=2, newton_max=2,
                  newton_tol=1e-10, asynchronous=False, stream=None, staging=True,
-                 sell_sigma=0, renumber=False, relax=False):
+                 sell_sigma=0, renumber=False, relax=False, split_p=False):
         torch = _require_torch_gpu()
         if mesh is not None:
             dim, coords, cells = mesh.dim, mesh.coords, mesh.cells
@@ -44,7 +44,8 @@ class Solver:
         p.newton_tol = float(newton_tol)
         p.flags = (capi.IDP_FLAG_ASYNC if asynchronous else 0) | \
             (0 if staging else capi.IDP_FLAG_NO_STAGING) | \
-            (capi.IDP_FLAG_RENUMBER if renumber else 0)
+            (capi.IDP_FLAG_RENUMBER if renumber else 0) | \
+            (capi.IDP_FLAG_SPLIT_P if split_p else 0)
         p.sell_sigma = int(sell_sigma)
         p.relax_bounds = 1 if relax else 0
         self.params = p

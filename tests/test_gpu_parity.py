@@ -176,6 +176,18 @@ def test_step_parity_relaxed_bounds_3d(torch, oracle_mod):
     s.close()
 
 
+@pytest.mark.parametrize("dim,n,steps", [(2, 33, 20), (3, 13, 4)])
+def test_split_p_variant_is_bitwise(torch, oracle_mod, dim, n, steps):
+    """The paper's variant 3 (the low-order sweep stores the viscous part of
+    P_ij, the limiter sweeps and passes read it): the oracle's steps, bit
+    for bit, staged (Morton) and gathered (random order)."""
+    for order in ("morton", "random"):
+        announce(f"variant 3 (split P_ij): dim={dim} n={n} {order}, {steps} steps")
+        mesh = inputs.q1_grid(n, dim, 0.2, seed=0, order=order)
+        U0 = inputs.ic_four_quadrant(mesh.coords) if dim == 2 else inputs.ic_sphere(mesh.coords)
+        assert _run_steps(torch, oracle_mod, mesh, U0, steps, split_p=True) == 0.0
+
+
 def test_step_parity_sphere_3d(torch, oracle_mod):
     announce("sphere 3D 17^3 random order, 10 steps")
     mesh = inputs.q1_grid(17, 3, 0.2, seed=0, order="random", perm_seed=1)
