@@ -170,22 +170,33 @@ def hbm_copy_bandwidth(gib=4.0, reps=3):
             "bytes_per_array": 8 * n}
 
 
-def batched_bench(steps):
+def batched_bench(steps, schedule=None, tile=0, loop=True):
     """64 independent 2D four-quadrant meshes of uneven sizes: the tuned
-    batched schedule against one context per instance stepped in a loop."""
+    batched schedule (or the given one) against one context per instance
+    stepped in a loop."""
     import torch
     from paper_2007_00094_amd import inputs
     from paper_2007_00094_amd.solver import BatchSolver, Solver
     batch = inputs.batch_workload()
     U0 = np.concatenate([u for _, u in batch])
     bs = BatchSolver([m for m, _ in batch])
-    best, tuner_ms = bs.tune(torch.tensor(U0, device="cuda"), 2)
+    if schedule is None:
+        best, tuner_ms = bs.tune(torch.tensor(U0, device="cuda"), 2)
+        sched = None
+    else:
+        sched = BatchSolver.schedule(schedule, tile)
+        best, tuner_ms = sched, {}
     U = torch.tensor(U0, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    bs.steps(U, steps)
+    bs.steps(U, steps, schedule=sched)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    if not loop:
+        n = int(bs.n)
+        bs.close()
+        return {"schedule": {"kind": schedule, "tile": tile}, "nodes": n, "steps": steps,
+                "batched_ms_per_step": t_batch / steps * 1e3}
     sols = [Solver(m, asynchronous=True) for m, _ in batch]
     Us = [torch.tensor(u, device="cuda") for _, u in batch]
     for so, u in zip(sols, Us):
@@ -294,6 +305,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched measurement")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-schedule", choices=["launches", "persistent"], default=None,
+                    help="with --only batch: run this schedule (no tuner, no loop)")
+    ap.add_argument("--batch-tile", type=int, default=64,
+                    help="persistent: units per item, or -n: n items per instance sweep")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--only", choices=["batch", "adjoint"], default=None,
                     help="run only that measurement and print its object (for profiling)")
@@ -332,7 +347,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.only == "batch":
-        print(json.dumps(batched_bench(args.batch_steps)), flush=True)
+        if args.batch_schedule:
+            out = batched_bench(args.batch_steps, args.batch_schedule, args.batch_tile,
+                                loop=False)
+        else:
+            out = batched_bench(args.batch_steps)
+        print(json.dumps(out), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_bench(args.adjoint_steps, 20)), flush=True)

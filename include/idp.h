@@ -242,7 +242,9 @@ int idp_batch_info(const idp_ctx *ctx, int *n_inst, int64_t *node_offsets);
 #define IDP_SCHED_PERSISTENT 2
 typedef struct {
     int kind;
-    int tile;     /* persistent: units per work item, 1..1024 */
+    int tile;     /* persistent: units per work item, 1..1024; or -1..-256:
+                     each sweep of each instance in at most -tile items of
+                     equal size (coarse items for large instances)        */
 } idp_schedule;
 
 /* n_steps SSP-RK3 steps of every instance, in place on U_dev.

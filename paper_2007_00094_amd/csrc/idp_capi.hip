@@ -46,7 +46,7 @@ inline size_t scal_bytes(int ninst) { return kScalHead + size_t(ninst) * 24; }
 struct PersistTables {
     int tile = 0;
     idp::BatchArgs B{};
-    int32_t *item_inst = nullptr;
+    int32_t *item_inst = nullptr, *item_tile = nullptr;
     int64_t *item_first = nullptr, *pre = nullptr;
 };
 
@@ -1527,7 +1527,9 @@ namespace {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Work-item tables of the persistent schedule with `tile` tiles per item.
+// Work-item tables of the persistent schedule with `tile` units per item;
+// tile < 0: every instance's sweep in (at most) -tile items, so that large
+// instances take coarse items and small ones fine items.
 int persist_tables(idp_ctx *c, int tile, PersistTables **out)
 {
     for (auto &t : c->tables)
@@ -1555,6 +1557,7 @@ int persist_tables(idp_ctx *c, int tile, PersistTables **out)
     const int64_t unit[3] = {idp::kSlice, idp::kSlice, 1};
     constexpr int S1 = idp::kSweeps + 1;
     std::vector<int64_t> items(size_t(K) * idp::kSweeps), pre(size_t(K) * S1);
+    std::vector<int64_t> tiles(size_t(K) * idp::kSweeps);
     idp::BatchArgs B{};
     B.tile = tile;
     for (int s = 0; s < idp::kSweeps; ++s) {
@@ -1562,9 +1565,16 @@ int persist_tables(idp_ctx *c, int tile, PersistTables **out)
         for (int k = 0; k < K; ++k) {
             const int64_t *range = kind[s] == 0 ? L.node.data() : kind[s] == 1 ? L.pair.data()
                                                                               : L.slice.data();
-            int64_t n = cdiv(cdiv(range[k + 1] - range[k], unit[kind[s]]), tile);
+            const int64_t units = cdiv(range[k + 1] - range[k], unit[kind[s]]);
+            int64_t t = tile;
+            if (tile < 0) {
+                const int64_t want = std::min<int64_t>(units, -tile);
+                t = want > 0 ? cdiv(units, want) : 1;
+            }
+            int64_t n = cdiv(units, t);
             if (s == 6 && c->prm.limiter_passes < 2) n = 0;
             items[size_t(k) * idp::kSweeps + s] = n;
+            tiles[size_t(k) * idp::kSweeps + s] = t;
             B.sweep_off[s + 1] += n;
         }
     }
@@ -1577,28 +1587,33 @@ int persist_tables(idp_ctx *c, int tile, PersistTables **out)
         pre[size_t(k) * S1 + idp::kSweeps] = acc + 1;
     }
     B.items_per_stage = B.sweep_off[idp::kSweeps];
-    std::vector<int32_t> inst(B.items_per_stage);
+    std::vector<int32_t> inst(B.items_per_stage), ntile(B.items_per_stage);
     std::vector<int64_t> first(B.items_per_stage);
     int64_t q = 0;
     for (int s = 0; s < idp::kSweeps; ++s)
         for (int k = 0; k < K; ++k) {
             const int64_t *range = kind[s] == 0 ? L.node.data() : kind[s] == 1 ? L.pair.data()
                                                                               : L.slice.data();
+            const int64_t t = tiles[size_t(k) * idp::kSweeps + s];
             for (int64_t it = 0; it < items[size_t(k) * idp::kSweeps + s]; ++it, ++q) {
                 inst[q] = k;
-                first[q] = range[k] + it * tile * unit[kind[s]];
+                ntile[q] = int32_t(t);
+                first[q] = range[k] + it * t * unit[kind[s]];
             }
         }
     PersistTables T;
     T.tile = tile;
     if ((e = dalloc(c, &T.item_inst, inst.size())) != IDP_OK) return e;
+    if ((e = dalloc(c, &T.item_tile, ntile.size())) != IDP_OK) return e;
     if ((e = dalloc(c, &T.item_first, first.size())) != IDP_OK) return e;
     if ((e = dalloc(c, &T.pre, pre.size())) != IDP_OK) return e;
     if (hipMemcpy(T.item_inst, inst.data(), inst.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(T.item_tile, ntile.data(), ntile.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(T.item_first, first.data(), first.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(T.pre, pre.data(), pre.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
         return IDP_EHIP;
     B.item_inst = T.item_inst;
+    B.item_tile = T.item_tile;
     B.item_first = T.item_first;
     B.pre = T.pre;
     B.unit_end = c->unit_end;
@@ -1672,7 +1687,8 @@ int batch_steps(idp_ctx *c, double *U, int n_steps, const double *dt, double *dt
 bool valid_schedule(const idp_schedule &s)
 {
     if (s.kind == IDP_SCHED_LAUNCHES) return true;
-    return s.kind == IDP_SCHED_PERSISTENT && s.tile >= 1 && s.tile <= 1024;
+    return s.kind == IDP_SCHED_PERSISTENT &&
+           ((s.tile >= 1 && s.tile <= 1024) || (s.tile >= -256 && s.tile <= -1));
 }
 
 }  // namespace
@@ -1695,10 +1711,13 @@ int idp_batch_tune(idp_ctx *c, const double *U, int n_steps, idp_schedule *best,
 {
     if (!c || !U || n_steps < 1) return IDP_EINVAL;
     if (c->pos_dev) return IDP_ENOTSUP;
+    // fixed tiles, and tiles per instance size (every sweep of an instance
+    // in at most 8, 32 or 128 items)
     const idp_schedule cand[] = {{IDP_SCHED_LAUNCHES, 0},    {IDP_SCHED_PERSISTENT, 4},
                                  {IDP_SCHED_PERSISTENT, 16},  {IDP_SCHED_PERSISTENT, 32},
                                  {IDP_SCHED_PERSISTENT, 64},  {IDP_SCHED_PERSISTENT, 128},
-                                 {IDP_SCHED_PERSISTENT, 256}};
+                                 {IDP_SCHED_PERSISTENT, 256}, {IDP_SCHED_PERSISTENT, -8},
+                                 {IDP_SCHED_PERSISTENT, -32}, {IDP_SCHED_PERSISTENT, -128}};
     const int nc = int(sizeof(cand) / sizeof(cand[0]));
     const size_t bytes = size_t(c->n) * (c->prm.dim + 2) * 8;
     int e = IDP_OK;

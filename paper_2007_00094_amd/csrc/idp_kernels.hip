@@ -1246,7 +1246,8 @@ __global__ void __launch_bounds__(kBlock) k_persistent(StageArgs P, BatchArgs B)
         const int stage = int(sg % 3);
         const int64_t *end = B.unit_end + int64_t(k) * 3;   // nodes, pairs, slices
         const int64_t e0 = uniform64(end[0]), e1 = uniform64(end[1]), e2 = uniform64(end[2]);
-        for (int u = 0; u < B.tile; ++u) {
+        const int ntile = int(uniform32(uint32_t(B.item_tile[r])));
+        for (int u = 0; u < ntile; ++u) {
             const int64_t lin = first + int64_t(u) * kSlice + lane;   // node, pair
             const int64_t sl = first + u;                               // slice
             switch (s) {

@@ -116,6 +116,7 @@ struct BatchArgs {
     int64_t total_items;
     int64_t sweep_off[kSweeps + 1];   // item offsets of the sweeps inside a stage
     const int32_t *item_inst;   // [items_per_stage] instance of each item
+    const int32_t *item_tile;   // [items_per_stage] units of each item
     const int64_t *item_first;  // [items_per_stage] first node/pair/slice of each item
     const int64_t *pre;         // [ninst][kSweeps + 1] completions required before each
                                 // sweep inside a stage; [kSweeps]: completions per stage

@@ -325,7 +325,8 @@ class BatchSolver:
         capi.check("idp_batch_tune", capi.lib().idp_batch_tune(
             self._h, self._u(U), int(n_steps), C.byref(best), ms.ctypes.data_as(capi._dp),
             C.byref(nc)))
-        names = ["launches"] + [f"persistent_tile{t}" for t in (4, 16, 32, 64, 128, 256)]
+        names = (["launches"] + [f"persistent_tile{t}" for t in (4, 16, 32, 64, 128, 256)] +
+                 [f"persistent_{n}_items_per_instance" for n in (8, 32, 128)])
         return best, {names[i]: float(ms[i]) for i in range(nc.value)}
 
 

@@ -9,7 +9,8 @@ from paper_2007_00094_amd import capi, inputs
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [("launches", 0), ("persistent", 1), ("persistent", 3), ("persistent", 16)]
+SCHEDULES = [("launches", 0), ("persistent", 1), ("persistent", 3), ("persistent", 16),
+             ("persistent", -2), ("persistent", -8)]
 
 
 def announce(msg):
@@ -147,7 +148,7 @@ def test_tuner_keeps_state_and_results(torch):
     keep = U0.clone()
     best, ms = bs.tune(U0, 2)
     assert torch.equal(U0, keep)
-    assert len(ms) == 7 and all(v > 0 for v in ms.values()), ms
+    assert len(ms) == 10 and all(v > 0 for v in ms.values()), ms
     assert best.kind in (capi.IDP_SCHED_LAUNCHES, capi.IDP_SCHED_PERSISTENT)
     A, B = U0.clone(), U0.clone()
     bs.steps(A, 2)                                        # tuned default
@@ -188,17 +189,29 @@ def test_batch_calls_refuse_a_renumbered_context(torch):
     s.close()
 
 
-def test_full_batch_workload_sampled_instances(torch, oracle_mod):
+_FULL_BATCH = {}
+
+
+@pytest.mark.parametrize("kind,tile", [("launches", 0), ("persistent", 64),
+                                       ("persistent", -32)])
+def test_full_batch_workload_sampled_instances(torch, oracle_mod, kind, tile):
     """The benchmark's batch (64 2D meshes, sides 33-513, per-instance CFL
-    dt) for 3 steps under the launch schedule: the smallest, the largest
-    and two more instances bit for bit against the oracle run alone."""
-    announce("full 64-mesh batch workload, 3 steps, sampled instances vs oracle")
+    dt) for 3 steps under the launch schedule and the persistent one (fixed
+    tiles; tiles per instance size): the smallest, the largest and two more
+    instances bit for bit against the oracle run alone, and the whole batch
+    bit for bit the same under every schedule."""
+    announce(f"full 64-mesh batch workload, 3 steps, schedule {kind} tile {tile}, "
+             "sampled instances vs oracle")
     batch = inputs.batch_workload()
     bs = make(batch)
     U = torch.tensor(np.concatenate([u for _, u in batch]), device="cuda")
     from paper_2007_00094_amd.solver import BatchSolver
-    used, _ = bs.steps(U, 3, schedule=BatchSolver.schedule("launches"))
+    used, _ = bs.steps(U, 3, schedule=BatchSolver.schedule(kind, tile))
     Ug = U.cpu().numpy()
+    if kind == "launches":
+        _FULL_BATCH["launches"] = Ug
+    elif "launches" in _FULL_BATCH:
+        assert np.array_equal(Ug, _FULL_BATCH["launches"])
     off = np.cumsum([0] + [m.n_nodes for m, _ in batch])
     sizes = [m.n_nodes for m, _ in batch]
     picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 40})
