@@ -144,14 +144,16 @@ def cpu_baseline(mesh, U0, radius, steps, single_steps):
 
 def hbm_copy_bandwidth(gib=4.0, reps=3):
     """Achievable HBM bandwidth: the best of ``reps`` timed device copies of
-    ``gib`` GiB (bytes read + written) and triads a = b + s c (2 read, 1
-    written), in GB/s."""
+    ``gib`` GiB (bytes read + written), triads a = b + s c (2 read, 1
+    written) and sums (read only: the sweeps read far more than they
+    write), in GB/s."""
     import torch
     n = int(gib * 2**30 // 8)
     x = torch.ones(n, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     z = torch.full_like(x, 2.0)
-    best_copy = best_triad = 0.0
+    best_copy = best_triad = best_read = 0.0
+    acc = torch.zeros((), dtype=torch.float64, device="cuda")
     for _ in range(reps + 1):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
@@ -164,10 +166,15 @@ def hbm_copy_bandwidth(gib=4.0, reps=3):
         b.record()
         b.synchronize()
         best_triad = max(best_triad, 24.0 * n / (a.elapsed_time(b) * 1e-3) / 1e9)
-    del x, y, z
+        a.record()
+        torch.sum(y, out=acc)
+        b.record()
+        b.synchronize()
+        best_read = max(best_read, 8.0 * n / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del x, y, z, acc
     torch.cuda.empty_cache()
     return {"copy_GB_per_s": round(best_copy, 1), "triad_GB_per_s": round(best_triad, 1),
-            "bytes_per_array": 8 * n}
+            "read_GB_per_s": round(best_read, 1), "bytes_per_array": 8 * n}
 
 
 def batched_bench(steps, schedule=None, tile=0, loop=True):
