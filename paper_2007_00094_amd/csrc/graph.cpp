@@ -412,6 +412,25 @@ int build_halos(const HostGraph &g, int64_t nblocks, int hmax, Halos &h)
     return IDP_OK;
 }
 
+void upper_bases(const HostGraph &g, std::vector<int64_t> &base)
+{
+    const int64_t ns = g.nslices;
+    base.assign(size_t(ns) + 1, 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < ns; ++s) {
+        int64_t cnt = 0;
+        for (int l = 0; l < kSellC; ++l) {
+            const int64_t r = s * kSellC + l;
+            const int32_t i = g.perm[size_t(r)];
+            if (i < 0) continue;
+            for (int k = 0; k < g.row_len[size_t(r)]; ++k)
+                cnt += g.scol[size_t(g.slice_off[size_t(s)] + l + int64_t(k) * kSellC)] > i;
+        }
+        base[size_t(s) + 1] = cnt;
+    }
+    for (int64_t s = 0; s < ns; ++s) base[size_t(s) + 1] += base[size_t(s)];
+}
+
 int concat_graphs(const std::vector<HostGraph> &parts, HostGraph &g, BatchLayout &lay)
 {
     if (parts.empty()) return IDP_EINVAL;

@@ -86,6 +86,11 @@ struct Halos {
 // Returns 0 or IDP_ENOMEM.
 int build_halos(const HostGraph &g, int64_t nblocks, int hmax, Halos &h);
 
+// base[s] = the number of SELL entries (i, j) with j > i in the slices
+// before s (s = 0..nslices): each unordered pair has one such entry, so
+// base[nslices] = npairs.
+void upper_bases(const HostGraph &g, std::vector<int64_t> &base);
+
 // Where each instance of a concatenated batch lives (k = 0..ninst, the
 // last entry is the total): nodes, cells, CSR entries, slices, SELL
 // entries, pairs.

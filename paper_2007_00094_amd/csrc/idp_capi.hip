@@ -260,7 +260,7 @@ void stage_p(idp_ctx *c, const idp::StageArgs &P, const double *in, const double
     timed_on(c, st, K_LOW, [&] { idp::launch_low(P, st); });
     timed_on(c, st, K_LIM1P, [&] { idp::launch_lim1p(P, st); });
     timed_on(c, st, K_PASS1A, [&] { idp::launch_pass1a(P, st); });
-    if (P.passes >= 2) timed_on(c, st, K_LIM2P, [&] { idp::launch_lim2p(P, st); });
+    if (P.passes >= 2) timed_on(c, st, K_LIM2P, [&] { idp::launch_lim2(P, st); });
     timed_on(c, st, K_PASS2, [&] { idp::launch_pass2(P, st, U0, out, mode); });
 }
 
@@ -492,6 +492,23 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
     TRY(dalloc(c, &P.packB, g.n * idp::kPack));
     TRY(dalloc(c, &P.rowB, g.n * idp::kRowB));
     TRY(dalloc(c, &P.upass, g.n * idp::kRowU));
+    TRY(dalloc(c, &P.l2self, g.n));
+    {
+        // pass 2's work list (see StageArgs::slow)
+        std::vector<int64_t> base;
+        idp::upper_bases(g, base);
+        int64_t *sb = nullptr;
+        TRY(dalloc(c, &P.slowmask, std::max<int64_t>(S / 64, 1)));
+        TRY(dalloc(c, &P.slow, std::max<int64_t>(g.npairs, 1)));
+        TRY(dalloc(c, &P.slow_cnt, std::max<int64_t>(g.nslices, 1)));
+        TRY(dalloc(c, &sb, int64_t(base.size())));
+        HIPTRY(hipMemcpyAsync(sb, base.data(), base.size() * 8, hipMemcpyHostToDevice,
+                              c->stream));
+        HIPTRY(hipMemsetAsync(P.slow_cnt, 0, size_t(std::max<int64_t>(g.nslices, 1)) * 4,
+                              c->stream));
+        HIPTRY(hipStreamSynchronize(c->stream));   // base leaves scope
+        P.slow_base = sb;
+    }
     TRY(dalloc(c, &P.alpha, g.n));
     TRY(dalloc(c, &P.taui, g.n));
     if (p.flags & IDP_FLAG_SPLIT_P) {
@@ -896,7 +913,9 @@ int idp_debug_export(idp_ctx *c, int what, double *out)
     switch (what) {
     case IDP_DBG_D: return sell_to_csr(c, c->P.d, out, 1, 0);
     case IDP_DBG_L1: return sell_to_csr(c, c->P.l1, out, 1, 0);
-    case IDP_DBG_L2: return sell_to_csr(c, c->P.l2, out, 1, 0);
+    case IDP_DBG_L2:
+        if (c->P.passes >= 2) idp::launch_l2_fill(c->P, c->stream);
+        return sell_to_csr(c, c->P.l2, out, 1, 0);
     case IDP_DBG_ALPHA: return node_to_host(c, c->P.alpha, 1, 0, 1, out);
     case IDP_DBG_TAUI: return node_to_host(c, c->P.taui, 1, 0, 1, out);
     case IDP_DBG_R: return node_to_host(c, c->P.packB, idp::kPack, nc, nc, out);
@@ -1040,8 +1059,8 @@ size_t tape_slot_bytes(const idp_ctx *c)
 {
     const size_t S = size_t(c->sell_size), np = size_t(c->P.npairs), n = size_t(c->n);
     return 3 * al256(S * 8) + 2 * al256(np * 8) + 2 * al256(n * idp::kPack * 8) +
-           al256(n * idp::kRowB * 8) + al256(n * idp::kRowU * 8) + al256(n * 8) +
-           3 * al256(np) + al256(n * 4);
+           al256(n * idp::kRowB * 8) + al256(n * idp::kRowU * 8) + 2 * al256(n * 8) +
+           3 * al256(np) + al256(n * 4) + al256(S / 64 * 8);
 }
 
 // Room for `steps` steps (fewer if device memory is short: the largest
@@ -1092,6 +1111,8 @@ int tape_reserve(idp_ctx *c, int steps)
         P.packB = reinterpret_cast<double *>(take(n * idp::kPack * 8));
         P.rowB = reinterpret_cast<double *>(take(n * idp::kRowB * 8));
         P.upass = reinterpret_cast<double *>(take(n * idp::kRowU * 8));
+        P.l2self = reinterpret_cast<double *>(take(n * 8));
+        P.slowmask = reinterpret_cast<unsigned long long *>(take(S / 64 * 8));
         P.alpha = reinterpret_cast<double *>(take(n * 8));
         P.sided = reinterpret_cast<uint8_t *>(take(np));
         P.side1 = reinterpret_cast<uint8_t *>(take(np));
@@ -1669,7 +1690,9 @@ int batch_steps(idp_ctx *c, double *U, int n_steps, const double *dt, double *dt
             hipSuccess) { P.dt_inst = nullptr; return IDP_EHIP; }
         const int grid = idp::persistent_blocks_per_cu(P.dim) * cus;
         idp::launch_batch_init(P, B, c->stream, 1);
-        timed(c, K_PERSIST, [&] { idp::launch_persistent(P, B, c->stream, grid); });
+        idp::StageArgs Pw = P;
+        Pw.slow = nullptr;   // the persistent worker sweeps every pass-2 pair
+        timed(c, K_PERSIST, [&] { idp::launch_persistent(Pw, B, c->stream, grid); });
     }
     P.dt_inst = nullptr;
     if (hipGetLastError() != hipSuccess) return IDP_EHIP;

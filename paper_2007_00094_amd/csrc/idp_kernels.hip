@@ -676,6 +676,7 @@ __device__ __forceinline__ void lim1_sweep(const StageArgs &P, int64_t pidx, int
     const double sv = lij < lji ? lij : lji;
     P.l1[e] = sv;
     P.l1[t] = sv;
+
     if (P.side1) P.l1p[p_] = sv;   // pair order: read by the stage adjoint only
     if (P.side1) P.side1[p_] = lij < lji;
 }
@@ -699,6 +700,16 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
     const double tau = P.tau[inst_];
     const double lam = P.lam[i];
     const double coef = tau / (lam * Bi.m);
+    // pass 2's work list: the entries (i, j), j > i, with s1 < 1, packed at
+    // the slice's base (not for stages that keep the adjoint's records,
+    // whose pass-2 limiter sweeps all pairs)
+    const bool list = P.slow && P.passes >= 2 && !P.side2;
+    const int64_t sbase = list ? P.slow_base[s_] : 0;
+    int nslow = 0;
+    // and the slice's mask words of the entries with s1 < 1 (word k: the
+    // 64 rows' entries k), which pass 2 visits
+    unsigned long long *const mw =
+        P.slowmask && P.passes >= 2 ? P.slowmask + (P.slice_off[s_] >> 6) : nullptr;
     // the next entry's column, scalars and fetch token are loaded one
     // entry ahead
     int jn = 0, tn = 0;
@@ -723,6 +734,20 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
             mn = P.mij[e1];
         }
         const bool act = k < L && j != i;
+        if (mw) {
+            const unsigned long long bm = __ballot(act && !(l == 1.0));
+            if (lane_ == 0) mw[k] = bm;
+        }
+        if (list) {
+            const bool slow = act && j > i && !(l == 1.0);
+            const unsigned long long bal = __ballot(slow);
+            if (slow) {
+                const unsigned below = __builtin_amdgcn_mbcnt_hi(
+                    unsigned(bal >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(bal), 0u));
+                P.slow[sbase + nslow + below] = int32_t(ENTRY(k));
+            }
+            nslow += __popcll(bal);
+        }
         double rec[2 * CH::packBrow];
         fetch(tk, act ? j : -1, rec);
         if (!act) continue;
@@ -740,6 +765,7 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
 #pragma unroll
         for (int r = 0; r < NC; ++r) V[r] += lam * l * Pd[r];
     }
+    if (list && lane_ == 0) P.slow_cnt[s_] = nslow;
     if (!valid_) return;
     P.l1[ENTRY(P.diag_k[r_])] = 1.0;   // the diagonal's s1 (pass 2 reads it as 1)
     // whole 64-byte records (a partly written line costs the memory a
@@ -752,21 +778,44 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
     for (int q = 0; q < 3; ++q) Up[NC + q] = W[NC + q];
 #pragma unroll
     for (int r = NC + 3; r < kRowU; ++r) Up[r] = 0.0;
+    if (P.passes >= 2) {
+        // pass 2's candidate of this row along a zero direction: the one
+        // every pair with s_ij = 1 gets, since its (1 - s_ij) P_ij is zero
+        // (the limiter's outcome is the same for +0 and -0 components)
+        double Z[NC];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) Z[r] = 0.0;
+        P.l2self[i] = limiter<D>(V, Z, W[NC], W[NC + 1], W[NC + 2], P.gamma, P.newton_max,
+                                 P.tol);
+    }
 }
 
 // ------------------------------------------------------ pair limiter 2
 // Step 5, second half, once per unordered pair: candidates of pass 2 on the
-// rescaled directions (1 - s_ij) P_ij from the pass-1 states.
+// rescaled directions (1 - s_ij) P_ij from the pass-1 states.  A pair that
+// pass 1 left unlimited (s_ij = 1) has the pass-2 direction (1 - 1) P_ij =
+// 0, along which the candidate of each side depends on that side's row only
+// (pass 1 stores it: l2self); its pass-2 term is a zero whatever s2 is, and
+// pass 2 does not read s2 there.  So only the pairs with s_ij < 1 need the
+// limiter: pass 1 lists them (slow), and k_lim2c runs over that list.  The
+// full sweep over all pairs (k_lim2p) runs for stages that keep the
+// adjoint's records and in the persistent batch schedule; a wavefront of it
+// whose pairs all have s_ij = 1 stores min of the two l2self (bit for bit
+// what the limiter returns along a zero direction) where records are kept
+// and skips them otherwise.  A debug export of s2 fills the skipped pairs in.
+
+// The limiter of one pair (i, j) at SELL positions e = (i,j), t = (j,i)
+// with m = m_ij; p: the pair's index for the records (< 0: none).  Every
+// lane of the wavefront calls it (cooperative gathers); valid_: whether
+// the lane has a pair.
 template <int D, bool SP = false>
-__device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int64_t pend,
-                                           double2 *lw)
+__device__ __forceinline__ void lim2_pair(const StageArgs &P, bool valid_, int64_t p_,
+                                          int64_t e, int64_t t, int i, int j, double m,
+                                          double l, double2 *lw)
 {
-    WAVE_PAIR_SETUP(P, pidx, pend)
-    if (failed(P)) return;
     constexpr int NC = D + 2;
     using CH = Chunks<D>;
-    const double dL = P.d[e], m = P.mp[pq_];   // d_ij at (i, j): the viscosity sweep's value
-    const double l = P.l1[e];
+    const double dL = P.d[e];   // d_ij at (i, j): the viscosity sweep's value
     double Pij[NC], Pji[NC];
     {
         NodeB<D> Bi, Bj;
@@ -823,10 +872,37 @@ __device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int
     const double sv = lij < lji ? lij : lji;
     P.l2[e] = sv;
     P.l2[t] = sv;
-    if (P.side2) P.side2[p_] = lij < lji;
+    if (P.side2 && p_ >= 0) P.side2[p_] = lij < lji;
+}
+
+template <int D, bool SP = false>
+__device__ __forceinline__ void lim2_sweep(const StageArgs &P, int64_t pidx, int64_t pend,
+                                           double2 *lw)
+{
+    const int64_t p_ = pidx;
+    if (p_ - threadIdx.x % kSlice >= pend) return;
+    if (failed(P)) return;
+    const bool valid_ = p_ < pend;
+    const int64_t pq_ = valid_ ? p_ : 0;
+    const int64_t e = P.pair_e[pq_];
+    const double l = P.l1[e];
+    if (__all(!valid_ || l == 1.0)) {
+        if (!valid_ || !P.side2) return;
+        const int64_t t = P.pair_t[pq_];
+        const int i = P.pair_i[pq_], j = P.pair_j[pq_];
+        const double lij = P.l2self[i], lji = P.l2self[j];
+        const double sv = lij < lji ? lij : lji;
+        P.l2[e] = sv;
+        P.l2[t] = sv;
+        P.side2[p_] = lij < lji;
+        return;
+    }
+    lim2_pair<D, SP>(P, valid_, p_, e, P.pair_t[pq_], P.pair_i[pq_], P.pair_j[pq_], P.mp[pq_],
+                     l, lw);
 }
 
 // -------------------------------------------------------- row pass 2
+
 // Step 6: U_i += sum_{j != i} lambda_i s2_ij (1 - s1_ij) P_ij, then
 // mode 0: out = E(U); 1: out = E (stage 1); 2: out = U0 + 1/4 (E - U0);
 // 3: out = U0 + 2/3 (E - U0); modes 1-3 keep held nodes at U0.
@@ -839,8 +915,7 @@ __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, in
     if (failed(P)) return;
     constexpr int NC = D + 2;
     using CH = Chunks<D>;
-    NodeB<D> Bi;
-    load_b<D>(P.packB + int64_t(i) * kPack, Bi);
+    NodeB<D> Bi;   // loaded once an entry of the wavefront needs it
     double V[NC];
     const double *Up = P.upass + int64_t(i) * kRowU;
 #pragma unroll
@@ -848,31 +923,40 @@ __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, in
     if (P.passes >= 2) {
         const double tau = P.tau[inst_];
         const double lam = P.lam[i];
-        const double coef = tau / (lam * Bi.m);
-        int jn = 0, tn = 0;
-        double s1n = 0.0, s2n = 0.0, dn = 0.0, mn = 0.0;
-        if (Lmax_ > 0) {
-            const int64_t e0 = ENTRY(0);
-            jn = P.scol[e0];
-            tn = fetch.token(e0);
-            s1n = P.l1[e0];
-            s2n = P.l2[e0];
-            dn = P.d[e0];
-            mn = P.mij[e0];
-        }
+        double coef = 0.0;
+        bool have_b = false;
+        // An entry with s1 = 1 or s2 = 0 adds lambda s2 (1 - s1) P_ij = +-0,
+        // which leaves V as it is unless a component of V is zero (whose sign
+        // the term could change).  The entries with s1 < 1 are marked in the
+        // slice's mask words (word k: the 64 rows' entries k), so only they,
+        // and any entry of a row whose V has a zero component, are visited;
+        // without the mask every entry is.
+        const unsigned long long *mw =
+            P.slowmask ? P.slowmask + (P.slice_off[s_] >> 6) : nullptr;
         for (int k = 0; k < Lmax_; ++k) {
-            const int j = jn, tk = tn;
-            const double s1 = s1n, s2 = s2n, dL = dn, m = mn;
-            if (k + 1 < Lmax_) {
-                const int64_t e1 = ENTRY(k + 1);
-                jn = P.scol[e1];
-                tn = fetch.token(e1);
-                s1n = P.l1[e1];
-                s2n = P.l2[e1];
-                dn = P.d[e1];
-                mn = P.mij[e1];
+            bool vzero = false;
+#pragma unroll
+            for (int r = 0; r < NC; ++r) vzero = vzero || V[r] == 0.0;
+            const bool marked = mw ? ((mw[k] >> lane_) & 1ull) != 0 : true;
+            const bool need = k < L && (marked || vzero);
+            if (!__any(need)) continue;
+            if (!have_b) {
+                load_b<D>(P.packB + int64_t(i) * kPack, Bi);
+                coef = tau / (lam * Bi.m);
+                have_b = true;
             }
-            const bool act = k < L && j != i;
+            int j = i, tk = 0;
+            double s1 = 1.0, s2 = 1.0, dL = 0.0, m = 0.0;
+            if (need) {
+                const int64_t ek = ENTRY(k);
+                j = P.scol[ek];
+                tk = fetch.token(ek);
+                s1 = P.l1[ek];
+                s2 = P.l2[ek];
+                dL = P.d[ek];
+                m = P.mij[ek];
+            }
+            const bool act = need && j != i;
             double rec[2 * CH::packBrow];
             fetch(tk, act ? j : -1, rec);
             if (!act) continue;
@@ -887,10 +971,13 @@ __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, in
             } else {
                 direction<D>(Bi, Bj, coef, dL, m, Pd);
             }
+            // s1 = 1: the term is a zero with the sign of P_ij, s2 being +0
+            // or 1 there (its stored value may be skipped: see lim2_pair)
+            const double s2e = s1 == 1.0 ? 1.0 : s2;
 #pragma unroll
             for (int r = 0; r < NC; ++r) {
                 const double P2 = (1.0 - s1) * Pd[r];
-                V[r] += lam * s2 * P2;
+                V[r] += lam * s2e * P2;
             }
         }
     }
@@ -1107,6 +1194,55 @@ __global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
 {
     WAVE_LDS(Chunks<D>::packB)
     lim2_sweep<D, SP>(P, PAIR_INDEX(P), P.npairs, lw);
+}
+
+// Pass 2's limiter over the work list: one wavefront per kSlowGroup
+// consecutive slices takes their listed pairs, 64 at a time (lane g first
+// reads slice g's count; a prefix over the lanes maps each pair to its
+// slice).
+constexpr int kSlowGroup = 16;
+template <int D, bool SP>
+__global__ void __launch_bounds__(kBlock) k_lim2s(StageArgs P)
+{
+    WAVE_LDS(Chunks<D>::packB)
+    if (failed(P)) return;
+    const int lane = int(threadIdx.x % kSlice);
+    const int64_t s0 = (int64_t(blockIdx.x) * (kBlock / kSlice) + threadIdx.x / kSlice) *
+                       kSlowGroup;
+    if (s0 >= P.nslices) return;
+    // lane g < kSlowGroup: slice s0 + g's count (0 past the end)
+    int cnt = 0;
+    int64_t base = 0;
+    if (lane < kSlowGroup && s0 + lane < P.nslices) {
+        base = P.slow_base[s0 + lane];
+        const int cap = int(P.slow_base[s0 + lane + 1] - base);
+        cnt = P.slow_cnt[s0 + lane];
+        cnt = cnt < cap ? cnt : cap;
+    }
+    int incl = cnt;   // inclusive prefix over the lanes
+#pragma unroll
+    for (int o = 1; o < kSlowGroup; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, kSlowGroup - 1);
+    for (int q0 = 0; q0 < total; q0 += kSlice) {
+        const int q = q0 + lane;
+        const bool valid = q < total;
+        const int qq = valid ? q : q0;
+        // the first slice g whose inclusive prefix exceeds qq
+        int g = 0;
+#pragma unroll
+        for (int step = kSlowGroup / 2; step > 0; step >>= 1) {
+            const int pre = __shfl(incl, g + step - 1);
+            if (pre <= qq) g += step;
+        }
+        const int before = __shfl(incl, g) - __shfl(cnt, g);
+        const int64_t e = P.slow[__shfl(base, g) + (qq - before)];
+        const int64_t t = P.stpos[e];
+        const int j = P.scol[e], i = P.scol[t];
+        lim2_pair<D, SP>(P, valid, -1, e, t, i, j, P.mij[e], P.l1[e], lw);
+    }
 }
 
 template <int D, bool SP>
@@ -1487,6 +1623,28 @@ void launch_matrices(const StageArgs &P, hipStream_t st, const double *coords,
     }
 }
 
+// s2 of every pair that pass 1 left unlimited (s1 = 1), which the pass-2
+// limiter sweep skips unless records are kept: the smaller of the two rows'
+// l2self, as the limiter returns it along the zero direction
+__global__ void __launch_bounds__(kBlock) k_l2_fill(StageArgs P)
+{
+    const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (p >= P.npairs) return;
+    const int64_t e = P.pair_e[p];
+    if (P.l1[e] != 1.0) return;
+    const double a = P.l2self[P.pair_i[p]], b = P.l2self[P.pair_j[p]];
+    const double sv = a < b ? a : b;
+    P.l2[e] = sv;
+    P.l2[P.pair_t[p]] = sv;
+}
+
+void launch_l2_fill(const StageArgs &P, hipStream_t st)
+{
+    if (P.npairs == 0) return;
+    const dim3 g(unsigned((P.npairs + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_l2_fill, g, dim3(kBlock), 0, st, P);
+}
+
 void launch_debug_entries(const StageArgs &P, hipStream_t st, int what, int comp, double *out)
 {
     const dim3 g(unsigned((P.nslices * kSlice + kBlock - 1) / kBlock));
@@ -1586,9 +1744,21 @@ void launch_pass1a(const StageArgs &P, hipStream_t st)
         LAUNCH_DS(k_pass1a, grid_rows(P), P);
 }
 void launch_lim2p(const StageArgs &P, hipStream_t st) { LAUNCH_DS(k_lim2p, grid_pairs(P), P); }
+
+void launch_lim2(const StageArgs &P, hipStream_t st)
+{
+    if (!P.slow || P.side2) {
+        launch_lim2p(P, st);
+        return;
+    }
+    if (P.nslices == 0) return;
+    const int64_t waves = (P.nslices + kSlowGroup - 1) / kSlowGroup;
+    const int grid = int((waves + kBlock / kSlice - 1) / (kBlock / kSlice));
+    LAUNCH_DS(k_lim2s, grid, P);
+}
 void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out, int mode)
 {
-    if (P.halo_cnt)
+    if (P.halo_cnt && !P.slowmask)
         LAUNCH_DS(k_pass2_h, grid_rows(P), P, U0, out, mode);
     else
         LAUNCH_DS(k_pass2, grid_rows(P), P, U0, out, mode);

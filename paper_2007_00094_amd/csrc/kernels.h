@@ -67,6 +67,20 @@ struct StageArgs {
     double *l1, *l2;            // [sell] min(l_ij, l_ji) of pass 1, 2
     double *packA, *alpha, *packB, *rowB, *upass, *taui;
     double *packL;              // [n][kPackL]
+    // [n] pass 2's limiter candidate of row i along a zero direction, from
+    // its pass-1 state and bounds (written by pass 1): the candidate l_ij of
+    // every pair that pass 1 left unlimited, min(l_ij, l_ji) = 1, whose
+    // pass-2 direction (1 - 1) P_ij is zero
+    double *l2self;
+    // pass 2's work list, built by pass 1: per slice s the SELL positions of
+    // the entries (i, j), j > i, whose s1 < 1, packed from slow_base[s]
+    // ([nslices + 1]: the slice's entries with j > i before it) and counted
+    // in slow_cnt[s].  Null: no list (every pair of pass 2 is swept).
+    int32_t *slow, *slow_cnt;
+    const int64_t *slow_base;
+    // [sell / 64] bit l of word w: SELL entry 64 w + l has s1 < 1 (written
+    // by pass 1), or null: pass 2 visits every entry
+    unsigned long long *slowmask;
     // records for the stage adjoint (null: not kept): which orientation
     // set d_ij = max(...) (1: i -> j), which side of a pair set min(l_ij,
     // l_ji) (1: the row of pair_i) per limiter pass; and per node the row
@@ -131,6 +145,11 @@ struct BatchArgs {
 // decision traces of the last stage: [npairs] pair codes, [n] row codes
 void launch_trace(const StageArgs &P, hipStream_t st, unsigned long long *pairs,
                   unsigned *rows);
+// s2 at the pairs with s1 = 1, which the pass-2 limiter sweep leaves out
+void launch_l2_fill(const StageArgs &P, hipStream_t st);
+// pass 2's limiter: over the work list built by pass 1, or over every pair
+// (stages that keep the adjoint's records, or no list)
+void launch_lim2(const StageArgs &P, hipStream_t st);
 // per-entry P_ij component / pass-1 / pass-2 candidates into out [sell]
 void launch_debug_entries(const StageArgs &P, hipStream_t st, int what, int comp, double *out);
 // r_i = (m_i / mass_total)^(1.5/d) into P.relax_r
