@@ -257,6 +257,40 @@ def test_invariant_domain_every_stage(oracle_mod, name, n, steps):
         U = Un
 
 
+@pytest.mark.parametrize("name,n,steps", [("four_quadrant", 21, 3), ("mach3", 9, 2)])
+def test_pass2_candidate_of_an_unlimited_pair_is_its_rows(oracle_mod, name, n, steps):
+    """Where pass 1 left a pair unlimited (s1 = min(l_ij, l_ji) = 1), its
+    pass-2 direction (1 - s1) P_ij is zero, and the pass-2 candidate of each
+    side (Alg. 2 along that direction, eq. iterative-limiter) depends on the
+    side's row alone: every such entry of row i carries the limiter's value
+    along a zero direction from row i's pass-1 state and bounds, the same
+    for +0 and -0 components, and that value is 0 or 1.  The library
+    evaluates it once per row on this basis."""
+    mesh, U, o = _stage_setup(oracle_mod, name, n, order="random", hold=True)
+    for _ in range(steps):
+        U, _, st = o.step(U)
+        assert st == 0
+    o.euler_stage(U, o.max_dt(U))
+    rp, col, tp = o.row_ptr(), o.col(), o.tpos()
+    raw1 = o.l1()
+    s1 = np.minimum(raw1, raw1[tp])
+    raw2 = o.l2()
+    Up, b = o.U_pass1(), o.bounds()
+    row = np.repeat(np.arange(o.n), np.diff(rp))
+    off = col != row
+    sel = np.nonzero(off & (s1 == 1.0))[0]
+    # both kinds of pairs occur
+    assert 0 < len(sel) < np.count_nonzero(off)
+    nc = Up.shape[1]
+    val = np.full(o.n, np.nan)
+    for i in np.unique(row[sel]):
+        z = oracle_mod.limiter(Up[i], np.zeros(nc), b[i])
+        assert oracle_mod.limiter(Up[i], -np.zeros(nc), b[i]) == z
+        assert z in (0.0, 1.0)
+        val[i] = z
+    assert np.array_equal(raw2[sel], val[row[sel]])
+
+
 def test_alpha_small_on_smooth_large_at_jump(oracle_mod):
     """The indicator decays with the mesh size on smooth data (its median
     falls about 4x per refinement; isolated O(1) values sit at extrema
