@@ -96,6 +96,7 @@ struct idp_ctx {
     int32_t *argk = nullptr;
     double *ckpt = nullptr;          // [slots][n][nc]
     int64_t ckpt_slots = 0;
+    int64_t unstaged_blocks = 0;   // row blocks whose halo exceeds the LDS cap
     int ck_steps = -1, ck_every = 0;
     std::vector<double> ck_dt;
     // tape: the per-stage arrays of tape_steps steps (3 stage argument sets
@@ -254,10 +255,28 @@ void stage_p(idp_ctx *c, const idp::StageArgs &P, const double *in, const double
 {
     timed_on(c, st, K_BEGIN, [&] { idp::launch_begin(P, st, clear); });
     timed_on(c, st, K_NODE, [&] { idp::launch_node(P, st, in, check); });
-    timed_on(c, st, K_DPAIR, [&] { idp::launch_dpair(P, st); });
-    timed_on(c, st, K_DIAG, [&] { idp::launch_diag(P, st, 1); });
-    timed_on(c, st, K_TAU, [&] { idp::launch_tau(P, st, dt_in, tau_mode); });
-    timed_on(c, st, K_LOW, [&] { idp::launch_low(P, st); });
+    // the staged viscosity sweep computes the indicator of its staged blocks
+    const bool staged = P.halo_cnt && P.pair_blk;
+    timed_on(c, st, K_DPAIR, [&] { idp::launch_dpair(P, st, staged ? 1 : 0); });
+    if (staged && tau_mode == 0) {
+        // tau held (stages 2 and 3): the low-order sweep sums d_ii and tau_i
+        // on its way, and the CFL check follows it; the diagonal sweep only
+        // computes the indicator of blocks whose halo did not fit
+        if (c->unstaged_blocks)
+            timed_on(c, st, K_DIAG, [&] { idp::launch_diag(P, st, 3); });
+        timed_on(c, st, K_LOW, [&] { idp::launch_low(P, st, 1); });
+        timed_on(c, st, K_TAU, [&] {
+            idp::launch_tau_fold(P, st);
+            idp::launch_tau(P, st, dt_in, tau_mode);
+        });
+    } else {
+        timed_on(c, st, K_DIAG, [&] { idp::launch_diag(P, st, staged ? 2 : 1); });
+        timed_on(c, st, K_TAU, [&] {
+            idp::launch_tau_fold(P, st);
+            idp::launch_tau(P, st, dt_in, tau_mode);
+        });
+        timed_on(c, st, K_LOW, [&] { idp::launch_low(P, st, 0); });
+    }
     timed_on(c, st, K_LIM1P, [&] { idp::launch_lim1p(P, st); });
     timed_on(c, st, K_PASS1A, [&] { idp::launch_pass1a(P, st); });
     if (P.passes >= 2) timed_on(c, st, K_LIM2P, [&] { idp::launch_lim2(P, st); });
@@ -511,6 +530,8 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
     }
     TRY(dalloc(c, &P.alpha, g.n));
     TRY(dalloc(c, &P.taui, g.n));
+    TRY(dalloc(c, &P.wmin, std::max<int64_t>(g.nslices, 1)));
+    TRY(dalloc(c, &P.wmin_blk, std::max<int64_t>((g.nslices + idp::kBlock - 1) / idp::kBlock, 1)));
     if (p.flags & IDP_FLAG_SPLIT_P) {
         // the paper's variant 3: the viscous part of P_ij per entry
         TRY(dalloc(c, &P.q, S * (dim + 2)));
@@ -563,6 +584,7 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
         idp::Halos h;
         const int64_t nblk = int64_t(P.per) * idp::kXcd;
         TRY(idp::build_halos(g, nblk, dim == 3 ? idp::kHaloMax3 : idp::kHaloMax2, h));
+        for (int64_t q = 0; q < nblk; ++q) c->unstaged_blocks += h.cnt[size_t(q)] < 0;
         int64_t *hs;
         int32_t *hc, *hn;
         uint16_t *hl;
@@ -792,8 +814,9 @@ int max_dt_all(idp_ctx *c, const double *U, double *dt_out)
     const idp::StageArgs &P = c->P;
     timed(c, K_BEGIN, [&] { idp::launch_begin(P, c->stream, 1); });
     timed(c, K_NODE, [&] { idp::launch_node(P, c->stream, U, 1); });
-    timed(c, K_DPAIR, [&] { idp::launch_dpair(P, c->stream); });
+    timed(c, K_DPAIR, [&] { idp::launch_dpair(P, c->stream, 0); });
     timed(c, K_DIAG, [&] { idp::launch_diag(P, c->stream, 0); });
+    timed(c, K_TAU, [&] { idp::launch_tau_fold(P, c->stream); });
     Scalars h{};
     int rc = read_scalars(c, &h);
     if (rc != IDP_OK) return rc;

@@ -194,6 +194,40 @@ __global__ void __launch_bounds__(kBlock) k_pair_c(StageArgs P)
 }
 
 // ------------------------------------------------------------ helpers
+// Minimum over the wavefront's lanes of the bit patterns of non-negative
+// doubles (their order as values; +inf for lanes without a row).
+__device__ __forceinline__ unsigned long long wave_min_bits(unsigned long long t)
+{
+#pragma unroll
+    for (int o = kSlice / 2; o > 0; o /= 2) {
+        const unsigned long long u = __shfl_xor(t, o);
+        t = u < t ? u : t;
+    }
+    return t;
+}
+
+// The low-order sweep's per-slice minima of tau_i towards each instance's
+// minimum: a batch's slices by atomics into their instance's; a single
+// mesh's by block into wmin_blk, which k_tau reduces (same-address atomics
+// from many blocks at once queue for microseconds).
+__global__ void __launch_bounds__(kBlock) k_tau_fold(StageArgs P)
+{
+    __shared__ unsigned long long red[kBlock / kSlice];
+    const int64_t s = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (P.ninst > 1) {
+        if (s < P.nslices) atomicMin(P.taumin + P.inst_slice[s], P.wmin[s]);
+        return;
+    }
+    const unsigned long long t = wave_min_bits(s < P.nslices ? P.wmin[s] : 0x7FF0000000000000ull);
+    if (threadIdx.x % kSlice == 0) red[threadIdx.x / kSlice] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = red[0];
+        for (int w = 1; w < kBlock / kSlice; ++w) m = red[w] < m ? red[w] : m;
+        P.wmin_blk[blockIdx.x] = m;
+    }
+}
+
 __global__ void k_begin(StageArgs P, int clear_status)
 {
     if (blockIdx.x != 0) return;
@@ -219,6 +253,28 @@ __device__ __forceinline__ void select_tau(const StageArgs &P, int k, double bou
     } else {
         if (P.tau[k] > bound) atomicOr(P.status, kWarnCfl);
     }
+}
+
+// k_tau_fold's block minima into the mesh's minimum (one block; a single
+// mesh only: a batch's slices went in by atomics).
+__global__ void __launch_bounds__(kBlock) k_tau_reduce(StageArgs P)
+{
+    __shared__ unsigned long long red[kBlock];
+    if (P.ninst != 1) return;
+    const int64_t nb = (P.nslices + kBlock - 1) / kBlock;
+    unsigned long long m = 0x7FF0000000000000ull;
+    for (int64_t q = threadIdx.x; q < nb; q += kBlock) {
+        const unsigned long long v = P.wmin_blk[q];
+        m = v < m ? v : m;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (int(threadIdx.x) < o && red[threadIdx.x + o] < red[threadIdx.x])
+            red[threadIdx.x] = red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] < P.taumin[0]) P.taumin[0] = red[0];
 }
 
 __global__ void k_tau(StageArgs P, double dt_in, int mode)
@@ -434,9 +490,33 @@ __device__ __forceinline__ double indicator(const double *U, double er, double a
 }
 
 // --------------------------------------------------------- row diagonal
+// d_ii = -sum_{j != i} d_ij in ascending column order (the diagonal at its
+// known position) and tau_i, the slice's minimum into wmin: the diagonal
+// sweep without the indicator, reading d alone.
+__device__ __forceinline__ void diag_only(const StageArgs &P, int64_t sidx, int64_t send)
+{
+    WAVE_ROW_SETUP(P, sidx, send)
+    if (failed(P)) return;
+    const int dk = valid_ ? P.diag_k[r_] : -1;
+    double dsum = 0.0;
+    for (int k = 0; k < L; ++k) {
+        const double dd = ld_stream(P.d + ENTRY(k));
+        if (k != dk) dsum += dd;
+    }
+    const double dii = -dsum;
+    const double ti = valid_ ? P.mi[i] / (-2.0 * dii) : 0.0;
+    const unsigned long long m = wave_min_bits(
+        valid_ ? (unsigned long long)__double_as_longlong(ti) : 0x7FF0000000000000ull);
+    if (lane_ == 0) P.wmin[s_] = m;
+    if (!valid_) return;
+    P.d[ENTRY(dk)] = dii;
+    P.taui[i] = ti;
+}
+
 // Step 2: d_ii = -sum_{j != i} d_ij (columns ascending), tau_i, the
-// instance's min tau_i (into taumin[instance]); indicator alpha_i
-// (Section 3.8) over all j in I(i).
+// instance's min tau_i (into taumin[instance], or with taumin null the
+// slice's minimum into wmin); indicator alpha_i (Section 3.8) over all j in
+// I(i).
 template <int D, class F>
 __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int64_t send,
                                            int with_alpha, unsigned long long *taumin,
@@ -488,12 +568,18 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
             for (int r = 0; r < NC; ++r) b[r] += fd[r];
         }
     }
-    if (!valid_) return;
     const double dii = -dsum;
+    const double ti = valid_ ? P.mi[i] / (-2.0 * dii) : 0.0;
+    if (!taumin) {
+        // the slice's minimum into wmin (k_tau_fold takes it in)
+        const unsigned long long m = wave_min_bits(
+            valid_ ? (unsigned long long)__double_as_longlong(ti) : 0x7FF0000000000000ull);
+        if (lane_ == 0) P.wmin[s_] = m;
+    }
+    if (!valid_) return;
     P.d[ENTRY(P.diag_k[r_])] = dii;
-    const double ti = P.mi[i] / (-2.0 * dii);
     P.taui[i] = ti;
-    atomicMin(taumin + inst_, (unsigned long long)__double_as_longlong(ti));
+    if (taumin) atomicMin(taumin + inst_, (unsigned long long)__double_as_longlong(ti));
     if (with_alpha) {
         const double al = indicator<D>(Ai.U, Ai.er, a, b, g);
         P.alpha[i] = al;
@@ -511,7 +597,7 @@ __device__ __forceinline__ void diag_sweep(const StageArgs &P, int64_t sidx, int
 // gather (2D).
 template <int D, bool SP = false, class F>
 __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int64_t send,
-                                          const F &fetch)
+                                          const F &fetch, int with_diag = 0)
 {
     WAVE_ROW_SETUP(P, sidx, send)
     if (failed(P)) return;
@@ -535,6 +621,7 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
 #pragma unroll
     for (int r = 0; r < NC; ++r) { R[r] = 0.0; Lw[r] = 0.0; }
     double rho_min = Ai.U[0], rho_max = Ai.U[0], phi_min = Ai.phi;
+    double dsum = 0.0;   // with_diag: -d_ii, summed as the diagonal sweep sums it
     int kmn = 255, kmx = 255, kph = 255;
     int jn = Lmax_ > 0 ? ld_stream(P.scol + ENTRY(0)) : 0;
     for (int k = 0; k < Lmax_; ++k) {
@@ -545,6 +632,7 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
         double c[D];
         load_c_stream<D>(P, e, c);
         const double dL = ld_stream(P.d + e);
+        if (act) dsum += dL;
         // the neighbour's record U, p, phi, alpha (pack L); v = m/rho is
         // recomputed exactly as the node pass computes it
         double rec[kPackL];
@@ -578,6 +666,19 @@ __device__ __forceinline__ void low_sweep(const StageArgs &P, int64_t sidx, int6
         if (rbar < rho_min) { rho_min = rbar; kmn = k; }
         if (rbar > rho_max) { rho_max = rbar; kmx = k; }
         if (Aj.phi < phi_min) { phi_min = Aj.phi; kph = k; }
+    }
+    if (with_diag) {
+        // tau held (stages 2 and 3): d_ii and tau_i for the CFL check, the
+        // slice's minimum into wmin
+        const double dii = -dsum;
+        const double ti = P.mi[i] / (-2.0 * dii);
+        const unsigned long long m = wave_min_bits(
+            valid_ ? (unsigned long long)__double_as_longlong(ti) : 0x7FF0000000000000ull);
+        if (lane_ == 0) P.wmin[s_] = m;
+        if (valid_) {
+            P.d[ENTRY(P.diag_k[r_])] = dii;
+            P.taui[i] = ti;
+        }
     }
     if (!valid_) return;
     if (P.argk) P.argk[i] = kmn | (kmx << 8) | (kph << 16);
@@ -1048,8 +1149,88 @@ __device__ __forceinline__ bool stage_halo_a3(const StageArgs &P, int64_t b, dou
     return true;
 }
 
+// ------------------------------------------- indicator in the staged block
+// Step 1's indicator (Section 3.8) for the rows of a block whose halo is
+// staged: after the block's pairs the halo is restaged as (U, eta/rho) in
+// 3D (p recomputed from U with the node pass's own function, so bit for bit
+// its value) or (U, p, eta/rho) in 2D, and one lane per row sums the row's
+// entries in ascending column order exactly as the diagonal sweep does.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P)
+__device__ __forceinline__ void restage_alpha(const StageArgs &P, int64_t b, double2 *halo)
+{
+    constexpr int NC = D + 2;
+    const int cnt = P.halo_cnt[b];
+    const int64_t h0 = P.halo_start[b];
+    __syncthreads();   // every lane is done with the pair phase's records
+    for (int q = int(threadIdx.x); q < 3 * cnt; q += kBlock) {
+        const int r = q / 3, c = q - 3 * r;
+        const double *a = P.packA + int64_t(P.halo_node[h0 + r]) * kPack;
+        halo[q] = c < 2 ? *reinterpret_cast<const double2 *>(a + 2 * c)
+                        : make_double2(a[D == 3 ? NC - 1 : NC], a[NC + 2]);
+    }
+    __syncthreads();
+}
+
+template <int D>
+__device__ __forceinline__ void alpha_rows(const StageArgs &P, int64_t b, const double2 *halo)
+{
+    constexpr int NC = D + 2;
+    const int64_t s = b * (kBlock / kSlice) + threadIdx.x / kSlice;
+    if (s >= P.nslices) return;
+    const int lane = int(threadIdx.x % kSlice);
+    const int64_t r = s * kSlice + lane;
+    const int i = P.perm[r];
+    if (i < 0) return;
+    const int L = P.row_len[r];
+    const int64_t off = P.slice_off[s] + lane;
+    const double g = P.gamma;
+    NodeA<D> Ai;
+    load_a_fwd<D>(P.packA + int64_t(i) * kPack, Ai);
+    double Fi[NC][D];
+    flux<D>(Ai.U, Ai.v, Ai.p, Fi);
+    double a = 0.0, bs[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) bs[q] = 0.0;
+    for (int k = 0; k < L; ++k) {
+        const int64_t e = off + int64_t(k) * kSlice;
+        double c[D];
+        load_c_stream<D>(P, e, c);
+        const double2 *rec = halo + 3 * int(P.loc[e]);
+        const double2 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+        NodeA<D> Aj;
+        Aj.U[0] = r0.x;
+        Aj.U[1] = r0.y;
+        Aj.U[2] = r1.x;
+        Aj.U[3] = r1.y;
+        if constexpr (D == 3) {
+            Aj.U[4] = r2.x;
+            Aj.p = pressure<D>(Aj.U, g);
+        } else {
+            Aj.p = r2.x;
+        }
+        Aj.er = r2.y;
+#pragma unroll
+        for (int q = 0; q < D; ++q) Aj.v[q] = Aj.U[1 + q] / Aj.U[0];
+        double mc = 0.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) mc += Aj.U[1 + q] * c[q];
+        a += (Aj.er - Ai.er) * mc;
+        double Fj[NC][D], fd[NC];
+        flux<D>(Aj.U, Aj.v, Aj.p, Fj);
+        flux_diff_dot<D>(Fi, Fj, c, fd);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) bs[q] += fd[q];
+    }
+    const double al = indicator<D>(Ai.U, Ai.er, a, bs, g);
+    P.alpha[i] = al;
+    P.packL[int64_t(i) * kPackL + kPackLAlpha] = al;
+    // pack A's copy is read only by the stage adjoint, which runs on stages
+    // recomputed with their records kept
+    if (P.argk) P.packA[int64_t(i) * kPack + kPackAlpha] = al;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P, int with_alpha)
 {
     constexpr int NCH = (D + 5) / 2;   // gathered chunks per record
     constexpr int NS = D == 3 ? 3 : NCH;   // staged chunks per record
@@ -1063,7 +1244,8 @@ __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P)
     else
         staged = stage_halo<NCH, NCH - 1, kPack>(P, b, P.packA, sh_);
     if (staged) {
-        if (failed(P)) return;
+        // block-uniform: the indicator phase below has block barriers
+        if (__syncthreads_or(failed(P))) return;
         // the next pair's entries, halo positions and coefficients are
         // loaded one pair ahead
         int64_t p = p0 + threadIdx.x, en = 0, tn = 0;
@@ -1126,6 +1308,10 @@ __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P)
             }
             dpair_eval<D>(P, p, e, t, c, ct, Ai, Aj);
         }
+        if (with_alpha) {
+            restage_alpha<D>(P, b, sh_);
+            alpha_rows<D>(P, b, sh_);
+        }
     } else {
         double2 *lw = sh_ + (threadIdx.x / kSlice) * NCH * kLdsRow;
         for (int64_t q0 = p0; q0 < p1; q0 += kBlock) dpair_sweep<D>(P, q0 + threadIdx.x, p1, lw);
@@ -1133,24 +1319,29 @@ __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P)
 }
 
 template <int D>
-__global__ void __launch_bounds__(kBlock, 4) k_diag(StageArgs P, int with_alpha)
+__global__ void __launch_bounds__(kBlock, 4) k_diag(StageArgs P, int mode)
 {
     WAVE_LDS(kDiagChunks<D>)
-    diag_sweep<D>(P, ROW_SLICE(P), P.nslices, with_alpha, P.taumin,
+    if (mode >= 2 && P.halo_cnt[logical_block(P.per)] >= 0) {
+        // the staged viscosity sweep computed this block's indicator
+        if (mode == 2) diag_only(P, ROW_SLICE(P), P.nslices);
+        return;
+    }
+    diag_sweep<D>(P, ROW_SLICE(P), P.nslices, mode != 0, nullptr,
                   GatherFetch<kDiagChunks<D>>{P.packA, lw});
 }
 
 template <int D, bool SP>
-__global__ void __launch_bounds__(kBlock) k_low(StageArgs P)
+__global__ void __launch_bounds__(kBlock) k_low(StageArgs P, int with_diag)
 {
     constexpr int NCH = kPackL / 2;
     if constexpr (D == 3) {
         low_sweep<D, SP>(P, ROW_SLICE(P), P.nslices,
-                         LaneTailFetch<NCH, NCH - 1, kPackL>{P.packL});
+                         LaneTailFetch<NCH, NCH - 1, kPackL>{P.packL}, with_diag);
     } else {
         WAVE_LDS(NCH)
         low_sweep<D, SP>(P, ROW_SLICE(P), P.nslices,
-                         GatherTailFetch<NCH, NCH - 1, kPackL>{P.packL, lw});
+                         GatherTailFetch<NCH, NCH - 1, kPackL>{P.packL, lw}, with_diag);
     }
 }
 
@@ -1291,10 +1482,10 @@ __global__ void __launch_bounds__(kBlock) k_pass2_h(StageArgs P, const double *U
 
 // staged low-order sweep
 template <int D, bool SP>
-__global__ void __launch_bounds__(kBlock) k_low_h(StageArgs P)
+__global__ void __launch_bounds__(kBlock) k_low_h(StageArgs P, int with_diag)
 {
     HALO_SWEEP(kPackL / 2, kPackL / 2 - 1, kPackL, P.packL,
-               (low_sweep<D, SP>(P, ROW_SLICE(P), P.nslices, f_)))
+               (low_sweep<D, SP>(P, ROW_SLICE(P), P.nslices, f_, with_diag)))
 }
 
 // ------------------------------------------------ persistent batch launch
@@ -1717,23 +1908,30 @@ static inline int grid_pairs(const StageArgs &P) { return P.pper * kXcd; }
         }                                                                               \
     } while (0)
 
-void launch_dpair(const StageArgs &P, hipStream_t st)
+void launch_dpair(const StageArgs &P, hipStream_t st, int with_alpha)
 {
     if (P.halo_cnt && P.pair_blk)
-        LAUNCH_D(k_dpair_h, grid_rows(P), P);
+        LAUNCH_D(k_dpair_h, grid_rows(P), P, with_alpha);
     else
         LAUNCH_D(k_dpair, grid_pairs(P), P);
 }
-void launch_diag(const StageArgs &P, hipStream_t st, int with_alpha)
+void launch_diag(const StageArgs &P, hipStream_t st, int mode)
 {
-    LAUNCH_D(k_diag, grid_rows(P), P, with_alpha);
+    LAUNCH_D(k_diag, grid_rows(P), P, mode);
 }
-void launch_low(const StageArgs &P, hipStream_t st)
+void launch_low(const StageArgs &P, hipStream_t st, int with_diag)
 {
     if (P.halo_cnt)
-        LAUNCH_DS(k_low_h, grid_rows(P), P);
+        LAUNCH_DS(k_low_h, grid_rows(P), P, with_diag);
     else
-        LAUNCH_DS(k_low, grid_rows(P), P);
+        LAUNCH_DS(k_low, grid_rows(P), P, with_diag);
+}
+void launch_tau_fold(const StageArgs &P, hipStream_t st)
+{
+    if (P.nslices == 0) return;
+    hipLaunchKernelGGL(k_tau_fold, dim3(unsigned((P.nslices + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, st, P);
+    hipLaunchKernelGGL(k_tau_reduce, dim3(1), dim3(kBlock), 0, st, P);
 }
 void launch_lim1p(const StageArgs &P, hipStream_t st) { LAUNCH_DS(k_lim1p, grid_pairs(P), P); }
 void launch_pass1a(const StageArgs &P, hipStream_t st)

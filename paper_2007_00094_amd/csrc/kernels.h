@@ -67,6 +67,10 @@ struct StageArgs {
     double *l1, *l2;            // [sell] min(l_ij, l_ji) of pass 1, 2
     double *packA, *alpha, *packB, *rowB, *upass, *taui;
     double *packL;              // [n][kPackL]
+    // [nslices] bits of the slice's minimum tau_i where the low-order sweep
+    // sums d_ii (stages with tau held), folded into taumin by k_tau_fold
+    unsigned long long *wmin;
+    unsigned long long *wmin_blk;   // [nslices / kBlock] their block minima
     // [n] pass 2's limiter candidate of row i along a zero direction, from
     // its pass-1 state and bounds (written by pass 1): the candidate l_ij of
     // every pair that pass 1 left unlimited, min(l_ij, l_ji) = 1, whose
@@ -162,10 +166,20 @@ void launch_batch_init(const StageArgs &P, const BatchArgs &B, hipStream_t st, i
 void launch_persistent(const StageArgs &P, const BatchArgs &B, hipStream_t st, int grid);
 int persistent_blocks_per_cu(int dim);
 void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode);
+// the per-slice minima of tau_i (wmin, left by the diagonal or low-order
+// sweep) into taumin
+void launch_tau_fold(const StageArgs &P, hipStream_t st);
 void launch_node(const StageArgs &P, hipStream_t st, const double *U, int check);
-void launch_dpair(const StageArgs &P, hipStream_t st);
-void launch_diag(const StageArgs &P, hipStream_t st, int with_alpha);
-void launch_low(const StageArgs &P, hipStream_t st);
+// with_alpha: the staged viscosity sweep also computes the indicator of the
+// rows of its staged blocks (the diagonal sweep then skips them)
+void launch_dpair(const StageArgs &P, hipStream_t st, int with_alpha);
+// mode 0: d_ii and tau_i; 1: and the indicator; 2: blocks whose indicator
+// the staged viscosity sweep computed d_ii and tau_i only, the others as 1;
+// 3: those blocks nothing, the others as 1
+void launch_diag(const StageArgs &P, hipStream_t st, int mode);
+// with_diag: the low-order sweep also sums d_ii and tau_i (per-slice minima
+// into wmin), for stages whose tau is held
+void launch_low(const StageArgs &P, hipStream_t st, int with_diag);
 void launch_lim1p(const StageArgs &P, hipStream_t st);
 void launch_pass1a(const StageArgs &P, hipStream_t st);
 void launch_lim2p(const StageArgs &P, hipStream_t st);
