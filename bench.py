@@ -42,10 +42,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(dim, n, nnz):
-    """Compulsory bytes per launch of each kernel: every array the kernel
-    reads or writes counted once (neighbour gathers and transposed reads
-    assumed cached), from the data layout of the library."""
+def algorithmic_bytes(dim, n, nnz, marked):
+    """Compulsory bytes of each kernel per SSP-RK3 step: every array a
+    launch reads or writes counted once (neighbour gathers and transposed
+    reads assumed cached), from the data layout of the library, summed over
+    the step's launches.  marked: off-diagonal entries with s1 < 1 (their
+    pairs are the pass-2 limiter's work list and the entries pass 2
+    visits)."""
     nc = dim + 2
     packa = 8 * (nc + 3)       # pack A as the forward reads it: U, p, c, eta/rho
     packl = 8 * (nc + 3)       # pack L: U, p, phi, alpha
@@ -54,23 +57,48 @@ def algorithmic_bytes(dim, n, nnz):
     rowb = 8 * (nc + 3)        # U^L, bounds
     cb = 8 * dim
     npairs = (nnz - n) // 2
+    slow = marked // 2
+    touched = min(n, marked)   # rows with a marked entry (at most)
     return {
-        # U read; pack A and pack L written (pack L's alpha by the diagonal sweep)
-        "node_pack": n * (8 * nc + packa + packl - 8),
-        # per pair: 4 ids, c_ij and c_ji, d written twice; U, p, c of the nodes
-        "pair_viscosity": npairs * (16 + 2 * cb + 16) + n * 8 * (nc + 2),
-        # per entry: column, c_ij, d_ij; per node: m_i read, d_ii, tau_i, alpha twice written
-        "row_diagonal": nnz * (4 + cb + 8) + n * (packa + 8 + 4 * 8),
-        # per node: alpha_i, m_i, lambda_i read; pack B and the row record written
-        "row_low_order": nnz * (4 + cb + 8) + n * (packl + 3 * 8 + packb + coef + rowb),
+        # U read; pack A and pack L written (pack L's alpha by the indicator)
+        "node_pack": 3 * n * (8 * nc + packa + packl - 8),
+        # per pair: 4 ids, c_ij and c_ji, d written twice; U, p, c of the
+        # nodes; the indicator: c_ij and a 16-bit halo position per entry,
+        # eta/rho per node, alpha written twice
+        "pair_viscosity": 3 * (npairs * (16 + 2 * cb + 16) + n * 8 * (nc + 2) +
+                               nnz * (cb + 2) + n * (8 + 16)),
+        # stage 1 only: d per entry; m_i, the diagonal's position read,
+        # d_ii and tau_i written
+        "row_diagonal": nnz * 8 + n * (8 + 4 + 16),
+        # per entry: column, c_ij, d_ij; per node: alpha_i, m_i, lambda_i
+        # read, pack B and the row record written; stages 2 and 3 also
+        # d_ii and tau_i
+        "row_low_order": 3 * (nnz * (4 + cb + 8) + n * (packl + 3 * 8 + packb + coef + rowb)) +
+                         2 * n * (4 + 16),
         # per pair: 4 ids, d, m_ij, s written twice and once in pair order
-        "pair_limiter1": npairs * (16 + 8 + 8 + 16 + 8) + n * (packb + coef + rowb),
-        # per node: lambda_i, U^L read, the pass-1 state written
-        "row_pass1": nnz * (4 + 8 + 8 + 8) + n * (packb + 8 + 8 * nc + 8 * nc),
-        # per pair: 4 ids, d, m_ij, s1, s2 written twice; per node: bounds, pass-1 state
-        "pair_limiter2": npairs * (16 + 8 + 8 + 8 + 16) + n * (packb + coef + 24 + 8 * nc),
-        "row_pass2": nnz * (4 + 8 + 8 + 8 + 8) + n * (packb + 8 + 8 * nc + 3 * 8 * nc + 1),
+        "pair_limiter1": 3 * (npairs * (16 + 8 + 8 + 16 + 8) + n * (packb + coef + rowb)),
+        # per entry: column, s1, d, m_ij and the entry's mask bit; per node:
+        # lambda_i, U^L read, the pass-1 state and l2self written; the list
+        "row_pass1": 3 * (nnz * (4 + 8 + 8 + 8) + nnz // 8 +
+                          n * (packb + 8 + 8 * nc + 8 * nc + 8) + slow * 4),
+        # per listed pair: its entry, the transposed position and the two
+        # columns, d, m_ij, s1, s2 written twice; the two rows' pack B and
+        # pass-1 records
+        "pair_limiter2": 3 * (slow * (4 + 4 + 8 + 8 + 8 + 8 + 16) +
+                              touched * (packb + coef + 64)),
+        # per node: the pass-1 state, U0 and the hold flag read, the output
+        # written, the mask bits; per marked entry: column, s1, s2, d,
+        # m_ij, the neighbour's pack B; its row's pack B and lambda
+        "row_pass2": 3 * (n * (8 * nc + 8 * nc + 8 * nc + 1) + nnz // 8 +
+                          marked * (4 + 8 + 8 + 8 + 8 + packb) +
+                          touched * (packb + coef + 8)),
     }
+
+
+# FP64 operations per stencil entry of the indicator phase of the viscosity
+# sweep (fluxes, their difference dotted with c_ij, v = m/rho, the a_i and
+# b_i sums): the diagonal sweep's measured count with the indicator.
+INDICATOR_FLOP_PER_ENTRY = 133
 
 
 def measured_traffic(kernel):
@@ -167,7 +195,7 @@ def hbm_copy_bandwidth(gib=4.0, reps=3):
         b.synchronize()
         best_triad = max(best_triad, 24.0 * n / (a.elapsed_time(b) * 1e-3) / 1e9)
         a.record()
-        torch.sum(y, out=acc)
+        torch.sum(y, dim=0, out=acc)
         b.record()
         b.synchronize()
         best_read = max(best_read, 8.0 * n / (a.elapsed_time(b) * 1e-3) / 1e9)
@@ -349,7 +377,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2007_00094_amd import inputs
+    from paper_2007_00094_amd import capi, inputs
     from paper_2007_00094_amd.solver import Solver
 
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -404,29 +432,36 @@ def main():
 
     stages = 3 * args.steps
     value = mesh.n_nodes * stages / elapsed
-    algo = algorithmic_bytes(mesh.dim, mesh.n_nodes, s.nnz)
-    dom = max(algo, key=lambda k: times[k][0])
-    avg_s = times[dom][0] / times[dom][1] / 1e3
-    kernels = {k: {"ms_per_launch": round(times[k][0] / times[k][1], 4),
-                   "GB_per_s": round(algo[k] / (times[k][0] / times[k][1] / 1e3) / 1e9, 1)}
+    # the entries with s1 < 1 of the last stage (pass 2's work)
+    s1 = s.debug(capi.IDP_DBG_L1)
+    marked = int(np.count_nonzero(s1 != 1.0))
+    del s1
+    log(f"entries with s1 < 1 in the last stage: {marked} of {s.nnz - mesh.n_nodes}")
+    algo = algorithmic_bytes(mesh.dim, mesh.n_nodes, s.nnz, marked)
+    per_step = {k: times[k][0] / args.steps for k in algo}
+    dom = max(algo, key=lambda k: per_step[k])
+    kernels = {k: {"ms_per_step": round(per_step[k], 4),
+                   "launches_per_step": times[k][1] // args.steps,
+                   "GB_per_s": round(algo[k] / (per_step[k] / 1e3) / 1e9, 1)}
                for k in algo if times[k][1]}
     traffic = measured_traffic(dom) if (args.n == 257 and args.order == "morton" and
                                         not args.split_p and not args.renumber) else None
+    launches = times[dom][1] // args.steps
+    avg_s = per_step[dom] / launches / 1e3
+    bytes_launch = algo[dom] // launches
+    achieved = bytes_launch / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": bytes_launch,
+                "launch_ms": round(avg_s * 1e3, 4)}
     if dom == "pair_viscosity":
-        # bound by FP64 issue, not by memory: priced against the vector FP64 peak
-        flops = VISCOSITY_FLOP_PER_PAIR * (s.nnz - mesh.n_nodes) / 2
-        achieved = flops / avg_s / 1e12
-        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2),
-                    "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_PEAK_TFS, 4), "traffic": traffic,
-                    "algorithmic_flops_per_launch": flops,
-                    "hbm_GB_per_s_algorithmic": round(algo[dom] / avg_s / 1e9, 1)}
-    else:
-        achieved = algo[dom] / avg_s / 1e9
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "algorithmic_bytes_per_launch": algo[dom]}
+        # its FP64 work beside: the wave-speed bounds per pair, the indicator
+        # per entry, against the vector FP64 peak
+        flops = (VISCOSITY_FLOP_PER_PAIR * (s.nnz - mesh.n_nodes) / 2 +
+                 INDICATOR_FLOP_PER_ENTRY * s.nnz)
+        roofline["fp64_TFLOP_per_s"] = round(flops / avg_s / 1e12, 2)
+        roofline["fp64_frac"] = round(flops / avg_s / 1e12 / FP64_PEAK_TFS, 4)
 
     s.close()
     log("achievable HBM bandwidth: 4 GiB copy and triad")

@@ -266,14 +266,14 @@ void stage_p(idp_ctx *c, const idp::StageArgs &P, const double *in, const double
             timed_on(c, st, K_DIAG, [&] { idp::launch_diag(P, st, 3); });
         timed_on(c, st, K_LOW, [&] { idp::launch_low(P, st, 1); });
         timed_on(c, st, K_TAU, [&] {
-            idp::launch_tau_fold(P, st);
-            idp::launch_tau(P, st, dt_in, tau_mode);
+            idp::launch_tau_fold(P, st, 0);
+            idp::launch_tau(P, st, dt_in, tau_mode, 1);
         });
     } else {
         timed_on(c, st, K_DIAG, [&] { idp::launch_diag(P, st, staged ? 2 : 1); });
         timed_on(c, st, K_TAU, [&] {
-            idp::launch_tau_fold(P, st);
-            idp::launch_tau(P, st, dt_in, tau_mode);
+            idp::launch_tau_fold(P, st, 0);
+            idp::launch_tau(P, st, dt_in, tau_mode, 1);
         });
         timed_on(c, st, K_LOW, [&] { idp::launch_low(P, st, 0); });
     }
@@ -816,7 +816,7 @@ int max_dt_all(idp_ctx *c, const double *U, double *dt_out)
     timed(c, K_NODE, [&] { idp::launch_node(P, c->stream, U, 1); });
     timed(c, K_DPAIR, [&] { idp::launch_dpair(P, c->stream, 0); });
     timed(c, K_DIAG, [&] { idp::launch_diag(P, c->stream, 0); });
-    timed(c, K_TAU, [&] { idp::launch_tau_fold(P, c->stream); });
+    timed(c, K_TAU, [&] { idp::launch_tau_fold(P, c->stream, 1); });
     Scalars h{};
     int rc = read_scalars(c, &h);
     if (rc != IDP_OK) return rc;

@@ -255,9 +255,9 @@ __device__ __forceinline__ void select_tau(const StageArgs &P, int k, double bou
     }
 }
 
-// k_tau_fold's block minima into the mesh's minimum (one block; a single
-// mesh only: a batch's slices went in by atomics).
-__global__ void __launch_bounds__(kBlock) k_tau_reduce(StageArgs P)
+// k_tau_fold's block minima into the mesh's minimum (one block of kBlock
+// threads; a single mesh only: a batch's slices went in by atomics).
+__device__ __forceinline__ void tau_reduce(const StageArgs &P)
 {
     __shared__ unsigned long long red[kBlock];
     if (P.ninst != 1) return;
@@ -275,11 +275,16 @@ __global__ void __launch_bounds__(kBlock) k_tau_reduce(StageArgs P)
         __syncthreads();
     }
     if (threadIdx.x == 0 && red[0] < P.taumin[0]) P.taumin[0] = red[0];
+    __syncthreads();
 }
 
-__global__ void k_tau(StageArgs P, double dt_in, int mode)
+__global__ void __launch_bounds__(kBlock) k_tau_reduce(StageArgs P) { tau_reduce(P); }
+
+// fold: take in k_tau_fold's block minima first
+__global__ void __launch_bounds__(kBlock) k_tau(StageArgs P, double dt_in, int mode, int fold)
 {
     if (blockIdx.x != 0) return;
+    if (fold) tau_reduce(P);
     for (int k = threadIdx.x; k < P.ninst; k += blockDim.x) {
         const double bound = __longlong_as_double((long long)P.taumin[k]);
         select_tau(P, k, bound, P.dt_inst ? P.dt_inst[k] : dt_in, mode);
@@ -1387,24 +1392,25 @@ __global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
     lim2_sweep<D, SP>(P, PAIR_INDEX(P), P.npairs, lw);
 }
 
-// Pass 2's limiter over the work list: one wavefront per kSlowGroup
-// consecutive slices takes their listed pairs, 64 at a time (lane g first
-// reads slice g's count; a prefix over the lanes maps each pair to its
-// slice).
+// Pass 2's limiter over the work list: one wavefront per `group` (at most
+// kSlowGroup) consecutive slices takes their listed pairs, 64 at a time
+// (lane g first reads slice g's count; a prefix over the lanes maps each
+// pair to its slice).  Small meshes take one slice per wavefront, so that
+// the wavefronts stay many and their pair loops short.
 constexpr int kSlowGroup = 16;
 template <int D, bool SP>
-__global__ void __launch_bounds__(kBlock) k_lim2s(StageArgs P)
+__global__ void __launch_bounds__(kBlock) k_lim2s(StageArgs P, int group)
 {
     WAVE_LDS(Chunks<D>::packB)
     if (failed(P)) return;
     const int lane = int(threadIdx.x % kSlice);
     const int64_t s0 = (int64_t(blockIdx.x) * (kBlock / kSlice) + threadIdx.x / kSlice) *
-                       kSlowGroup;
+                       group;
     if (s0 >= P.nslices) return;
-    // lane g < kSlowGroup: slice s0 + g's count (0 past the end)
+    // lane g < group: slice s0 + g's count (0 past the end)
     int cnt = 0;
     int64_t base = 0;
-    if (lane < kSlowGroup && s0 + lane < P.nslices) {
+    if (lane < group && s0 + lane < P.nslices) {
         base = P.slow_base[s0 + lane];
         const int cap = int(P.slow_base[s0 + lane + 1] - base);
         cnt = P.slow_cnt[s0 + lane];
@@ -1870,9 +1876,9 @@ void launch_begin(const StageArgs &P, hipStream_t st, int clear_status)
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBlock), 0, st, P, clear_status);
 }
 
-void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode)
+void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode, int fold)
 {
-    hipLaunchKernelGGL(k_tau, dim3(1), dim3(kBlock), 0, st, P, dt_in, mode);
+    hipLaunchKernelGGL(k_tau, dim3(1), dim3(kBlock), 0, st, P, dt_in, mode, fold);
 }
 
 void launch_node(const StageArgs &P, hipStream_t st, const double *U, int check)
@@ -1926,12 +1932,12 @@ void launch_low(const StageArgs &P, hipStream_t st, int with_diag)
     else
         LAUNCH_DS(k_low, grid_rows(P), P, with_diag);
 }
-void launch_tau_fold(const StageArgs &P, hipStream_t st)
+void launch_tau_fold(const StageArgs &P, hipStream_t st, int reduce)
 {
     if (P.nslices == 0) return;
     hipLaunchKernelGGL(k_tau_fold, dim3(unsigned((P.nslices + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, P);
-    hipLaunchKernelGGL(k_tau_reduce, dim3(1), dim3(kBlock), 0, st, P);
+    if (reduce) hipLaunchKernelGGL(k_tau_reduce, dim3(1), dim3(kBlock), 0, st, P);
 }
 void launch_lim1p(const StageArgs &P, hipStream_t st) { LAUNCH_DS(k_lim1p, grid_pairs(P), P); }
 void launch_pass1a(const StageArgs &P, hipStream_t st)
@@ -1950,9 +1956,11 @@ void launch_lim2(const StageArgs &P, hipStream_t st)
         return;
     }
     if (P.nslices == 0) return;
-    const int64_t waves = (P.nslices + kSlowGroup - 1) / kSlowGroup;
+    int group = kSlowGroup;
+    while (group > 1 && P.nslices / group < 8192) group /= 2;
+    const int64_t waves = (P.nslices + group - 1) / group;
     const int grid = int((waves + kBlock / kSlice - 1) / (kBlock / kSlice));
-    LAUNCH_DS(k_lim2s, grid, P);
+    LAUNCH_DS(k_lim2s, grid, P, group);
 }
 void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out, int mode)
 {

@@ -165,10 +165,12 @@ void launch_begin(const StageArgs &P, hipStream_t st, int clear_status);
 void launch_batch_init(const StageArgs &P, const BatchArgs &B, hipStream_t st, int clear_status);
 void launch_persistent(const StageArgs &P, const BatchArgs &B, hipStream_t st, int grid);
 int persistent_blocks_per_cu(int dim);
-void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode);
+// fold: first take in the block minima of launch_tau_fold(.., 0)
+void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode, int fold);
 // the per-slice minima of tau_i (wmin, left by the diagonal or low-order
-// sweep) into taumin
-void launch_tau_fold(const StageArgs &P, hipStream_t st);
+// sweep) towards taumin: with reduce all the way, else to block minima
+// that launch_tau with fold takes in
+void launch_tau_fold(const StageArgs &P, hipStream_t st, int reduce);
 void launch_node(const StageArgs &P, hipStream_t st, const double *U, int check);
 // with_alpha: the staged viscosity sweep also computes the indicator of the
 // rows of its staged blocks (the diagonal sweep then skips them)
