@@ -501,6 +501,7 @@ __device__ __forceinline__ double indicator(const double *U, double er, double a
 __device__ __forceinline__ void diag_only(const StageArgs &P, int64_t sidx, int64_t send)
 {
     WAVE_ROW_SETUP(P, sidx, send)
+    (void)inst_;
     if (failed(P)) return;
     const int dk = valid_ ? P.diag_k[r_] : -1;
     double dsum = 0.0;
@@ -1148,47 +1149,12 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
 // records in LDS every node record is read from memory once per block
 // instead of once per pair (a node has 2 x 13 pairs in 3D).  A block whose
 // halo did not fit gathers as above.
-// In 3D a staged record is the 48 bytes the sweep reads, rho, m, p, c (E
-// and eta/rho left out): 38 KB per block, four blocks per CU.
-__device__ __forceinline__ bool stage_halo_a3(const StageArgs &P, int64_t b, double2 *halo)
-{
-    constexpr int NC = 5;
-    const int cnt = P.halo_cnt[b];
-    if (cnt < 0) return false;
-    const int64_t h0 = P.halo_start[b];
-#pragma unroll 4
-    for (int q = int(threadIdx.x); q < 3 * cnt; q += kBlock) {
-        const int r = q / 3, c = q - 3 * r;
-        const double *a = P.packA + int64_t(P.halo_node[h0 + r]) * kPack;
-        halo[q] = c < 2 ? *reinterpret_cast<const double2 *>(a + 2 * c)
-                        : make_double2(a[NC], a[NC + 1]);
-    }
-    __syncthreads();
-    return true;
-}
 
 // ------------------------------------------- indicator in the staged block
 // Step 1's indicator (Section 3.8) for the rows of a block whose halo is
-// staged: after the block's pairs the halo is restaged as (U, eta/rho) in
-// 3D (p recomputed from U with the node pass's own function, so bit for bit
-// its value) or (U, p, eta/rho) in 2D, and one lane per row sums the row's
-// entries in ascending column order exactly as the diagonal sweep does.
-template <int D>
-__device__ __forceinline__ void restage_alpha(const StageArgs &P, int64_t b, double2 *halo)
-{
-    constexpr int NC = D + 2;
-    const int cnt = P.halo_cnt[b];
-    const int64_t h0 = P.halo_start[b];
-    __syncthreads();   // every lane is done with the pair phase's records
-    for (int q = int(threadIdx.x); q < 3 * cnt; q += kBlock) {
-        const int r = q / 3, c = q - 3 * r;
-        const double *a = P.packA + int64_t(P.halo_node[h0 + r]) * kPack;
-        halo[q] = c < 2 ? *reinterpret_cast<const double2 *>(a + 2 * c)
-                        : make_double2(a[D == 3 ? NC - 1 : NC], a[NC + 2]);
-    }
-    __syncthreads();
-}
-
+// staged: after the block's pairs, one lane per row sums the row's entries
+// in ascending column order from the staged records (U, p, eta/rho),
+// exactly as the diagonal sweep does.
 template <int D>
 __device__ __forceinline__ void alpha_rows(const StageArgs &P, int64_t b, const double2 *halo)
 {
@@ -1213,20 +1179,19 @@ __device__ __forceinline__ void alpha_rows(const StageArgs &P, int64_t b, const 
         const int64_t e = off + int64_t(k) * kSlice;
         double c[D];
         load_c_stream<D>(P, e, c);
-        const double2 *rec = halo + 3 * int(P.loc[e]);
-        const double2 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-        NodeA<D> Aj;
-        Aj.U[0] = r0.x;
-        Aj.U[1] = r0.y;
-        Aj.U[2] = r1.x;
-        Aj.U[3] = r1.y;
-        if constexpr (D == 3) {
-            Aj.U[4] = r2.x;
-            Aj.p = pressure<D>(Aj.U, g);
-        } else {
-            Aj.p = r2.x;
+        const double2 *rec = halo + 4 * int(P.loc[e]);
+        double a8[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 v = rec[q];
+            a8[2 * q] = v.x;
+            a8[2 * q + 1] = v.y;
         }
-        Aj.er = r2.y;
+        NodeA<D> Aj;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) Aj.U[q] = a8[q];
+        Aj.p = a8[NC];
+        Aj.er = a8[NC + 2];
 #pragma unroll
         for (int q = 0; q < D; ++q) Aj.v[q] = Aj.U[1 + q] / Aj.U[0];
         double mc = 0.0;
@@ -1251,16 +1216,15 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P, int with_alpha)
 {
     constexpr int NCH = (D + 5) / 2;   // gathered chunks per record
-    constexpr int NS = D == 3 ? 3 : NCH;   // staged chunks per record
+    // staged record: pack A's first 64 bytes (U, p, c, eta/rho), which the
+    // pairs and then the indicator read (51 KB per block in 3D, three
+    // blocks per CU)
+    constexpr int NS = 4;
     static_assert(kHaloMaxD<D> * NS >= (kBlock / kSlice) * NCH * kLdsRow, "gather tiles fit");
     __shared__ double2 sh_[kHaloMaxD<D> * NS];
     const int64_t b = logical_block(P.per);
     const int64_t p0 = P.pair_blk[b], p1 = P.pair_blk[b + 1];
-    bool staged;
-    if constexpr (D == 3)
-        staged = stage_halo_a3(P, b, sh_);
-    else
-        staged = stage_halo<NCH, NCH - 1, kPack>(P, b, P.packA, sh_);
+    const bool staged = stage_halo<NS, NS - 1, kPack>(P, b, P.packA, sh_);
     if (staged) {
         // block-uniform: the indicator phase below has block barriers
         if (__syncthreads_or(failed(P))) return;
@@ -1295,41 +1259,17 @@ __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P, int with_alpha)
             const double2 *ri = sh_ + li * NS;
             const double2 *rj = sh_ + lj * NS;
             double Ai[2 * NCH], Aj[2 * NCH];
-            if constexpr (D == 3) {
-                // rho, m | p, c at the pack A slots (E and eta/rho unread)
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const double2 a = ri[k], q = rj[k];
-                    Ai[2 * k] = a.x;
-                    Ai[2 * k + 1] = a.y;
-                    Aj[2 * k] = q.x;
-                    Aj[2 * k + 1] = q.y;
-                }
-                const double2 a = ri[2], q = rj[2];
-                Ai[4] = 0.0;
-                Aj[4] = 0.0;
-                Ai[5] = a.x;
-                Ai[6] = a.y;
-                Aj[5] = q.x;
-                Aj[6] = q.y;
-                Ai[7] = 0.0;
-                Aj[7] = 0.0;
-            } else {
-#pragma unroll
-                for (int k = 0; k < NCH; ++k) {
-                    const double2 a = ri[k], q = rj[k];
-                    Ai[2 * k] = a.x;
-                    Ai[2 * k + 1] = a.y;
-                    Aj[2 * k] = q.x;
-                    Aj[2 * k + 1] = q.y;
-                }
+            for (int k = 0; k < NCH; ++k) {
+                const double2 a = ri[k], q = rj[k];
+                Ai[2 * k] = a.x;
+                Ai[2 * k + 1] = a.y;
+                Aj[2 * k] = q.x;
+                Aj[2 * k + 1] = q.y;
             }
             dpair_eval<D>(P, p, e, t, c, ct, Ai, Aj);
         }
-        if (with_alpha) {
-            restage_alpha<D>(P, b, sh_);
-            alpha_rows<D>(P, b, sh_);
-        }
+        if (with_alpha) alpha_rows<D>(P, b, sh_);
     } else {
         double2 *lw = sh_ + (threadIdx.x / kSlice) * NCH * kLdsRow;
         for (int64_t q0 = p0; q0 < p1; q0 += kBlock) dpair_sweep<D>(P, q0 + threadIdx.x, p1, lw);
