@@ -816,7 +816,9 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
     // and the slice's mask words of the entries with s1 < 1 (word k: the
     // 64 rows' entries k), which pass 2 visits
     unsigned long long *const mw =
-        P.slowmask && P.passes >= 2 ? P.slowmask + (P.slice_off[s_] >> 6) : nullptr;
+        P.slowmask && P.passes >= 2 && Lmax_ <= kSlice ? P.slowmask + (P.slice_off[s_] >> 6)
+                                                       : nullptr;
+    unsigned long long mword = 0ull;
     // the next entry's column, scalars and fetch token are loaded one
     // entry ahead
     int jn = 0, tn = 0;
@@ -842,8 +844,9 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
         }
         const bool act = k < L && j != i;
         if (mw) {
+            // column k's word, kept by lane k and stored after the loop
             const unsigned long long bm = __ballot(act && !(l == 1.0));
-            if (lane_ == 0) mw[k] = bm;
+            mword = lane_ == k ? bm : mword;
         }
         if (list) {
             const bool slow = act && j > i && !(l == 1.0);
@@ -873,6 +876,7 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
         for (int r = 0; r < NC; ++r) V[r] += lam * l * Pd[r];
     }
     if (list && lane_ == 0) P.slow_cnt[s_] = nslow;
+    if (mw && lane_ < Lmax_) mw[lane_] = mword;
     if (!valid_) return;
     P.l1[ENTRY(P.diag_k[r_])] = 1.0;   // the diagonal's s1 (pass 2 reads it as 1)
     // whole 64-byte records (a partly written line costs the memory a
@@ -1038,13 +1042,16 @@ __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, in
         // slice's mask words (word k: the 64 rows' entries k), so only they,
         // and any entry of a row whose V has a zero component, are visited;
         // without the mask every entry is.
-        const unsigned long long *mw =
-            P.slowmask ? P.slowmask + (P.slice_off[s_] >> 6) : nullptr;
+        // (pass 1 writes the words of slices up to 64 columns wide; wider
+        // ones visit every entry)
+        const unsigned long long *mw = P.slowmask && Lmax_ <= kSlice
+                                           ? P.slowmask + (P.slice_off[s_] >> 6)
+                                           : nullptr;
         // the slice's mask words held by the lanes (lane q: word q) and the
         // set of columns with a marked entry, so that unmarked columns cost
         // no memory access (loading the next marked column's scalars ahead
         // measured slower: 140 registers, three waves per SIMD)
-        const bool held = mw && Lmax_ <= kSlice;
+        const bool held = mw != nullptr;
         unsigned long long wq = 0ull;
         if (held && lane_ < Lmax_) wq = mw[lane_];
         const unsigned long long kset = held ? __ballot(wq != 0ull) : ~0ull;
@@ -1053,11 +1060,7 @@ __device__ __forceinline__ void pass2_sweep(const StageArgs &P, int64_t sidx, in
 #pragma unroll
             for (int r = 0; r < NC; ++r) vzero = vzero || V[r] == 0.0;
             if (held && !((kset >> k) & 1ull) && !__any(k < L && vzero)) continue;
-            bool marked = true;
-            if (held)
-                marked = ((__shfl(wq, k) >> lane_) & 1ull) != 0;
-            else if (mw)
-                marked = ((mw[k] >> lane_) & 1ull) != 0;
+            const bool marked = held ? ((__shfl(wq, k) >> lane_) & 1ull) != 0 : true;
             const bool need = k < L && (marked || vzero);
             if (!__any(need)) continue;
             if (!have_b) {
@@ -1345,50 +1348,27 @@ __global__ void __launch_bounds__(kBlock) k_lim2p(StageArgs P)
     lim2_sweep<D, SP>(P, PAIR_INDEX(P), P.npairs, lw);
 }
 
-// Pass 2's limiter over the work list: one wavefront per `group` (at most
-// kSlowGroup) consecutive slices takes their listed pairs, 64 at a time
-// (lane g first reads slice g's count; a prefix over the lanes maps each
-// pair to its slice).  Small meshes take one slice per wavefront, so that
-// the wavefronts stay many and their pair loops short.
-constexpr int kSlowGroup = 16;
+// Pass 2's limiter over the work list: one wavefront per slice takes the
+// slice's listed pairs, 64 at a time.  The listed pairs cluster where the
+// flow is limited, so consecutive slices go to consecutive blocks, which
+// the hardware deals out over the XCDs (the XCD-aware order of the sweeps,
+// a contiguous range of slices per XCD, measured 1.44 against 1.13 ms;
+// 4 and 16 slices per wavefront 1.18 and 1.29 ms).
 template <int D, bool SP>
-__global__ void __launch_bounds__(kBlock) k_lim2s(StageArgs P, int group)
+__global__ void __launch_bounds__(kBlock) k_lim2s(StageArgs P)
 {
     WAVE_LDS(Chunks<D>::packB)
-    if (failed(P)) return;
+    const int64_t s = int64_t(blockIdx.x) * (kBlock / kSlice) + threadIdx.x / kSlice;
+    if (s >= P.nslices || failed(P)) return;
+    const int64_t base = P.slow_base[s];
+    const int cap = int(P.slow_base[s + 1] - base);
+    int cnt = P.slow_cnt[s];
+    cnt = cnt < cap ? cnt : cap;
     const int lane = int(threadIdx.x % kSlice);
-    const int64_t s0 = (int64_t(blockIdx.x) * (kBlock / kSlice) + threadIdx.x / kSlice) *
-                       group;
-    if (s0 >= P.nslices) return;
-    // lane g < group: slice s0 + g's count (0 past the end)
-    int cnt = 0;
-    int64_t base = 0;
-    if (lane < group && s0 + lane < P.nslices) {
-        base = P.slow_base[s0 + lane];
-        const int cap = int(P.slow_base[s0 + lane + 1] - base);
-        cnt = P.slow_cnt[s0 + lane];
-        cnt = cnt < cap ? cnt : cap;
-    }
-    int incl = cnt;   // inclusive prefix over the lanes
-#pragma unroll
-    for (int o = 1; o < kSlowGroup; o <<= 1) {
-        const int v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
-    }
-    const int total = __shfl(incl, kSlowGroup - 1);
-    for (int q0 = 0; q0 < total; q0 += kSlice) {
+    for (int q0 = 0; q0 < cnt; q0 += kSlice) {
         const int q = q0 + lane;
-        const bool valid = q < total;
-        const int qq = valid ? q : q0;
-        // the first slice g whose inclusive prefix exceeds qq
-        int g = 0;
-#pragma unroll
-        for (int step = kSlowGroup / 2; step > 0; step >>= 1) {
-            const int pre = __shfl(incl, g + step - 1);
-            if (pre <= qq) g += step;
-        }
-        const int before = __shfl(incl, g) - __shfl(cnt, g);
-        const int64_t e = P.slow[__shfl(base, g) + (qq - before)];
+        const bool valid = q < cnt;
+        const int64_t e = P.slow[base + (valid ? q : q0)];
         const int64_t t = P.stpos[e];
         const int j = P.scol[e], i = P.scol[t];
         lim2_pair<D, SP>(P, valid, -1, e, t, i, j, P.mij[e], P.l1[e], lw);
@@ -1400,7 +1380,12 @@ __global__ void __launch_bounds__(kBlock) k_pass2(StageArgs P, const double *U0,
                                                   int mode)
 {
     WAVE_LDS(Chunks<D>::packBrow)
-    pass2_sweep<D, SP>(P, ROW_SLICE(P), P.nslices, U0, out, mode,
+    // consecutive slices to consecutive blocks, dealt out over the XCDs by
+    // the hardware: pass 2's work clusters where the flow is limited, and
+    // the XCD-aware order (a contiguous range of slices per XCD) left one
+    // XCD with most of it (3.30 against 2.44 ms per launch at 257^3)
+    pass2_sweep<D, SP>(P, int64_t(blockIdx.x) * (kBlock / kSlice) + threadIdx.x / kSlice,
+                       P.nslices, U0, out, mode,
                        GatherFetch<Chunks<D>::packBrow>{P.packB, lw});
 }
 
@@ -1909,11 +1894,8 @@ void launch_lim2(const StageArgs &P, hipStream_t st)
         return;
     }
     if (P.nslices == 0) return;
-    int group = kSlowGroup;
-    while (group > 1 && P.nslices / group < 8192) group /= 2;
-    const int64_t waves = (P.nslices + group - 1) / group;
-    const int grid = int((waves + kBlock / kSlice - 1) / (kBlock / kSlice));
-    LAUNCH_DS(k_lim2s, grid, P, group);
+    const int grid = int((P.nslices + kBlock / kSlice - 1) / (kBlock / kSlice));
+    LAUNCH_DS(k_lim2s, grid, P);
 }
 void launch_pass2(const StageArgs &P, hipStream_t st, const double *U0, double *out, int mode)
 {

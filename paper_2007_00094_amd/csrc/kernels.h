@@ -83,7 +83,8 @@ struct StageArgs {
     int32_t *slow, *slow_cnt;
     const int64_t *slow_base;
     // [sell / 64] bit l of word w: SELL entry 64 w + l has s1 < 1 (written
-    // by pass 1), or null: pass 2 visits every entry
+    // by pass 1 for slices up to 64 columns wide), or null: pass 2 visits
+    // every entry
     unsigned long long *slowmask;
     // records for the stage adjoint (null: not kept): which orientation
     // set d_ij = max(...) (1: i -> j), which side of a pair set min(l_ij,
