@@ -908,7 +908,7 @@ __device__ __forceinline__ void pass1_sweep(const StageArgs &P, int64_t sidx, in
 // 0, along which the candidate of each side depends on that side's row only
 // (pass 1 stores it: l2self); its pass-2 term is a zero whatever s2 is, and
 // pass 2 does not read s2 there.  So only the pairs with s_ij < 1 need the
-// limiter: pass 1 lists them (slow), and k_lim2c runs over that list.  The
+// limiter: pass 1 lists them (slow), and k_lim2s runs over that list.  The
 // full sweep over all pairs (k_lim2p) runs for stages that keep the
 // adjoint's records and in the persistent batch schedule; a wavefront of it
 // whose pairs all have s_ij = 1 stores min of the two l2self (bit for bit
