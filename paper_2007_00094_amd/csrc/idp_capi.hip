@@ -96,7 +96,6 @@ struct idp_ctx {
     int32_t *argk = nullptr;
     double *ckpt = nullptr;          // [slots][n][nc]
     int64_t ckpt_slots = 0;
-    int64_t unstaged_blocks = 0;   // row blocks whose halo exceeds the LDS cap
     int ck_steps = -1, ck_every = 0;
     std::vector<double> ck_dt;
     // tape: the per-stage arrays of tape_steps steps (3 stage argument sets
@@ -255,15 +254,12 @@ void stage_p(idp_ctx *c, const idp::StageArgs &P, const double *in, const double
 {
     timed_on(c, st, K_BEGIN, [&] { idp::launch_begin(P, st, clear); });
     timed_on(c, st, K_NODE, [&] { idp::launch_node(P, st, in, check); });
-    // the staged viscosity sweep computes the indicator of its staged blocks
+    // the row-block viscosity sweep computes the indicator of every row
     const bool staged = P.halo_cnt && P.pair_blk;
     timed_on(c, st, K_DPAIR, [&] { idp::launch_dpair(P, st, staged ? 1 : 0); });
     if (staged && tau_mode == 0) {
         // tau held (stages 2 and 3): the low-order sweep sums d_ii and tau_i
-        // on its way, and the CFL check follows it; the diagonal sweep only
-        // computes the indicator of blocks whose halo did not fit
-        if (c->unstaged_blocks)
-            timed_on(c, st, K_DIAG, [&] { idp::launch_diag(P, st, 3); });
+        // on its way, and the CFL check follows it
         timed_on(c, st, K_LOW, [&] { idp::launch_low(P, st, 1); });
         timed_on(c, st, K_TAU, [&] {
             idp::launch_tau_fold(P, st, 0);
@@ -584,7 +580,6 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
         idp::Halos h;
         const int64_t nblk = int64_t(P.per) * idp::kXcd;
         TRY(idp::build_halos(g, nblk, dim == 3 ? idp::kHaloMax3 : idp::kHaloMax2, h));
-        for (int64_t q = 0; q < nblk; ++q) c->unstaged_blocks += h.cnt[size_t(q)] < 0;
         int64_t *hs;
         int32_t *hc, *hn;
         uint16_t *hl;

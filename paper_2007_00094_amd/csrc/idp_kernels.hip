@@ -504,10 +504,18 @@ __device__ __forceinline__ void diag_only(const StageArgs &P, int64_t sidx, int6
     (void)inst_;
     if (failed(P)) return;
     const int dk = valid_ ? P.diag_k[r_] : -1;
+    // nine entries' loads in flight at a time (a Q1 row has 9 or 27), summed
+    // in column order as they arrive
+    constexpr int kU = 9;
     double dsum = 0.0;
-    for (int k = 0; k < L; ++k) {
-        const double dd = ld_stream(P.d + ENTRY(k));
-        if (k != dk) dsum += dd;
+    for (int k0 = 0; k0 < Lmax_; k0 += kU) {
+        double dd[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            dd[u] = k0 + u < L ? ld_stream(P.d + ENTRY(k0 + u)) : 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (k0 + u < L && k0 + u != dk) dsum += dd[u];
     }
     const double dii = -dsum;
     const double ti = valid_ ? P.mi[i] / (-2.0 * dii) : 0.0;
@@ -1154,11 +1162,12 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
 // halo did not fit gathers as above.
 
 // ------------------------------------------- indicator in the staged block
-// Step 1's indicator (Section 3.8) for the rows of a block whose halo is
-// staged: after the block's pairs, one lane per row sums the row's entries
-// in ascending column order from the staged records (U, p, eta/rho),
-// exactly as the diagonal sweep does.
-template <int D>
+// Step 1's indicator (Section 3.8) for the rows of a row block: after the
+// block's pairs, one lane per row sums the row's entries in ascending
+// column order, exactly as the diagonal sweep does, from the neighbours'
+// records (U, p, eta/rho: pack A's first 64 bytes) staged in LDS (STAGED)
+// or read from pack A (blocks whose halo did not fit).
+template <int D, bool STAGED>
 __device__ __forceinline__ void alpha_rows(const StageArgs &P, int64_t b, const double2 *halo)
 {
     constexpr int NC = D + 2;
@@ -1182,13 +1191,19 @@ __device__ __forceinline__ void alpha_rows(const StageArgs &P, int64_t b, const 
         const int64_t e = off + int64_t(k) * kSlice;
         double c[D];
         load_c_stream<D>(P, e, c);
-        const double2 *rec = halo + 4 * int(P.loc[e]);
         double a8[8];
+        if constexpr (STAGED) {
+            const double2 *rec = halo + 4 * int(P.loc[e]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double2 v = rec[q];
-            a8[2 * q] = v.x;
-            a8[2 * q + 1] = v.y;
+            for (int q = 0; q < 4; ++q) {
+                const double2 v = rec[q];
+                a8[2 * q] = v.x;
+                a8[2 * q + 1] = v.y;
+            }
+        } else {
+            const double *rec = P.packA + int64_t(P.scol[e]) * kPack;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a8[q] = rec[q];
         }
         NodeA<D> Aj;
 #pragma unroll
@@ -1220,14 +1235,14 @@ __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P, int with_alpha)
 {
     constexpr int NCH = (D + 5) / 2;   // gathered chunks per record
     // staged record: pack A's first 64 bytes (U, p, c, eta/rho), which the
-    // pairs and then the indicator read (51 KB per block in 3D, three
+    // pairs and then the indicator read (40 KB per block in 3D, four
     // blocks per CU)
     constexpr int NS = 4;
-    static_assert(kHaloMaxD<D> * NS >= (kBlock / kSlice) * NCH * kLdsRow, "gather tiles fit");
-    __shared__ double2 sh_[kHaloMaxD<D> * NS];
+    static_assert(kHaloPairD<D> * NS >= (kBlock / kSlice) * NCH * kLdsRow, "gather tiles fit");
+    __shared__ double2 sh_[kHaloPairD<D> * NS];
     const int64_t b = logical_block(P.per);
     const int64_t p0 = P.pair_blk[b], p1 = P.pair_blk[b + 1];
-    const bool staged = stage_halo<NS, NS - 1, kPack>(P, b, P.packA, sh_);
+    const bool staged = stage_halo<NS, NS - 1, kPack, kHaloPairD<D>>(P, b, P.packA, sh_);
     if (staged) {
         // block-uniform: the indicator phase below has block barriers
         if (__syncthreads_or(failed(P))) return;
@@ -1272,22 +1287,25 @@ __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P, int with_alpha)
             }
             dpair_eval<D>(P, p, e, t, c, ct, Ai, Aj);
         }
-        if (with_alpha) alpha_rows<D>(P, b, sh_);
+        if (with_alpha) alpha_rows<D, true>(P, b, sh_);
     } else {
         double2 *lw = sh_ + (threadIdx.x / kSlice) * NCH * kLdsRow;
         for (int64_t q0 = p0; q0 < p1; q0 += kBlock) dpair_sweep<D>(P, q0 + threadIdx.x, p1, lw);
+        if (with_alpha) alpha_rows<D, false>(P, b, nullptr);
     }
+}
+
+// d_ii and tau_i alone (the viscosity sweep computed the indicator): a
+// kernel of its own, whose few registers leave room for eight waves per SIMD
+__global__ void __launch_bounds__(kBlock) k_dsum(StageArgs P)
+{
+    diag_only(P, ROW_SLICE(P), P.nslices);
 }
 
 template <int D>
 __global__ void __launch_bounds__(kBlock, 4) k_diag(StageArgs P, int mode)
 {
     WAVE_LDS(kDiagChunks<D>)
-    if (mode >= 2 && P.halo_cnt[logical_block(P.per)] >= 0) {
-        // the staged viscosity sweep computed this block's indicator
-        if (mode == 2) diag_only(P, ROW_SLICE(P), P.nslices);
-        return;
-    }
     diag_sweep<D>(P, ROW_SLICE(P), P.nslices, mode != 0, nullptr,
                   GatherFetch<kDiagChunks<D>>{P.packA, lw});
 }
@@ -1861,7 +1879,10 @@ void launch_dpair(const StageArgs &P, hipStream_t st, int with_alpha)
 }
 void launch_diag(const StageArgs &P, hipStream_t st, int mode)
 {
-    LAUNCH_D(k_diag, grid_rows(P), P, mode);
+    if (mode == 2)
+        hipLaunchKernelGGL(k_dsum, dim3(grid_rows(P)), dim3(kBlock), 0, st, P);
+    else
+        LAUNCH_D(k_diag, grid_rows(P), P, mode);
 }
 void launch_low(const StageArgs &P, hipStream_t st, int with_diag)
 {

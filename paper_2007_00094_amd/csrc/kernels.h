@@ -21,11 +21,17 @@ constexpr int kRowU = 8;      // doubles per node: state after pass 1 (nc), the
 constexpr int kPackL = 8;     // doubles per node: the low-order sweep's neighbour
                               // record U (nc), p, phi, alpha [kPackLAlpha]
 constexpr int kPackLAlpha = 7;
-// records of a row block's neighbourhood staged in LDS (3D: about 700 at
+// records of a row block's neighbourhood staged in LDS (3D: about 600 at
 // Morton order, 2D: about 350), at most 6 chunks each (75 KB, 48 KB)
 constexpr int kHaloMax3 = 800;
 constexpr int kHaloMax2 = 512;
 template <int D> constexpr int kHaloMaxD = D == 3 ? kHaloMax3 : kHaloMax2;
+// the staged viscosity sweep's cap (64-byte records): 632 records in 3D
+// keep its LDS under 40 KB, four blocks per CU (Morton blocks of 256 rows
+// have 600 halo nodes in the bulk, 648 and more at faces of the Morton
+// tree); blocks with more gather instead
+constexpr int kHaloPair3 = 632;
+template <int D> constexpr int kHaloPairD = D == 3 ? kHaloPair3 : kHaloMax2;
 
 // status bits (device int)
 constexpr int kErrState = 1;
@@ -173,12 +179,11 @@ void launch_tau(const StageArgs &P, hipStream_t st, double dt_in, int mode, int 
 // that launch_tau with fold takes in
 void launch_tau_fold(const StageArgs &P, hipStream_t st, int reduce);
 void launch_node(const StageArgs &P, hipStream_t st, const double *U, int check);
-// with_alpha: the staged viscosity sweep also computes the indicator of the
-// rows of its staged blocks (the diagonal sweep then skips them)
+// with_alpha: the row-block viscosity sweep also computes the indicator of
+// its rows (the diagonal sweep then leaves it)
 void launch_dpair(const StageArgs &P, hipStream_t st, int with_alpha);
-// mode 0: d_ii and tau_i; 1: and the indicator; 2: blocks whose indicator
-// the staged viscosity sweep computed d_ii and tau_i only, the others as 1;
-// 3: those blocks nothing, the others as 1
+// mode 0: d_ii and tau_i; 1: and the indicator; 2: d_ii and tau_i from d
+// alone (the viscosity sweep computed the indicator)
 void launch_diag(const StageArgs &P, hipStream_t st, int mode);
 // with_diag: the low-order sweep also sums d_ii and tau_i (per-slice minima
 // into wmin), for stages whose tau is held

@@ -251,14 +251,15 @@ struct HaloFetch {
 // LDS staging of a row block's neighbourhood: the first NCH chunks of the
 // record (STRIDE doubles per node) of every node in the block's halo, in halo order.
 // Every thread of the block calls it (it ends in a block barrier); false
-// if the block's halo did not fit (its rows then gather from memory).
-template <int NCH, int LAST = NCH - 1, int STRIDE = kPack>
+// if the block's halo did not fit (its rows then gather from memory): more
+// than the host's cap (count -1) or than CAP records.
+template <int NCH, int LAST = NCH - 1, int STRIDE = kPack, int CAP = 0x7fffffff>
 __device__ __forceinline__ bool stage_halo(const StageArgs &P, int64_t b, const double *base,
                                            double2 *halo)
 {
     static_assert(NCH <= 6 && LAST >= NCH - 1, "halo record");
     const int cnt = P.halo_cnt[b];
-    if (cnt < 0) return false;
+    if (cnt < 0 || cnt > CAP) return false;
     const int64_t h0 = P.halo_start[b];
     const int tot = cnt * NCH;
 #pragma unroll 4
