@@ -5,7 +5,10 @@
 //   k_node    step 0   per node: p, c, eta/rho, v = m/rho, phi   (pack A)
 //   k_dpair   step 1   per pair: d_ij = d_ji (both orientations, the larger;
 //                       one where c_ji = -c_ij makes them mirror images)
-//   k_diag    step 2   per row: d_ii, tau_i, min tau; indicator alpha_i
+//   k_dpair_h step 1   the same by row block, and the indicator alpha_i of
+//                       the block's rows
+//   k_diag    step 2   per row: d_ii, tau_i, min tau; indicator alpha_i (k_dsum:
+//                       d_ii and tau_i alone, after k_dpair_h)
 //   k_low     step 3   per row: R_i, U^L_i, bounds rho_min, rho_max, phi_min
 //   k_lim1p   step 4   per pair: P_ij, P_ji (eq. def-p), l_ij, l_ji (Alg. 2),
 //                       s_ij = s_ji = min(l_ij, l_ji)
@@ -327,7 +330,7 @@ __device__ __forceinline__ void node_sweep(const StageArgs &P, int64_t i, int64_
         scatter<NCH>(P.packA, kPack, valid ? int(i) : -1, lw, A);
     else
         scatter<kDiagChunks<D>>(P.packA, kPack, valid ? int(i) : -1, lw, A);
-    // the low-order sweep's record: U, p, phi (alpha follows from k_diag)
+    // the low-order sweep's record: U, p, phi (alpha follows with the indicator)
     double L[kPackL];
 #pragma unroll
     for (int k = 0; k < NC; ++k) L[k] = u[k];
@@ -1159,7 +1162,8 @@ __global__ void __launch_bounds__(kBlock) k_dpair(StageArgs P)
 // rows, whose two nodes are both in the block's halo; with the halo's
 // records in LDS every node record is read from memory once per block
 // instead of once per pair (a node has 2 x 13 pairs in 3D).  A block whose
-// halo did not fit gathers as above.
+// halo did not fit gathers as above.  Then the block computes the indicator
+// of its rows.
 
 // ------------------------------------------- indicator in the staged block
 // Step 1's indicator (Section 3.8) for the rows of a row block: after the

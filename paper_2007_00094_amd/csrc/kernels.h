@@ -13,7 +13,7 @@ constexpr int kSlice = 64;    // SELL slice height = wavefront width
 constexpr int kXcd = 8;       // XCDs of an MI355X; blocks are renumbered so
                               // that each XCD walks a contiguous slice range
 constexpr int kPack = 16;     // doubles per node in the gather packs
-constexpr int kPackAlpha = 12;  // pack A slot of alpha_i (written by k_diag)
+constexpr int kPackAlpha = 12;  // pack A slot of alpha_i (written with the indicator)
 constexpr int kPackCoef = 12;   // pack B slot of tau/(lambda_i m_i)
 constexpr int kRowB = 8;      // doubles per node: U^L (nc), bounds (3)
 constexpr int kRowU = 8;      // doubles per node: state after pass 1 (nc), the
