@@ -580,6 +580,10 @@ int create_impl(idp_ctx **out, const idp_params &p, const std::vector<MeshIn> &m
         idp::Halos h;
         const int64_t nblk = int64_t(P.per) * idp::kXcd;
         TRY(idp::build_halos(g, nblk, dim == 3 ? idp::kHaloMax3 : idp::kHaloMax2, h));
+        // the viscosity sweep's smaller cap where few blocks exceed it
+        int64_t mid = 0;
+        for (int64_t q = 0; q < nblk; ++q) mid += h.cnt[size_t(q)] > idp::kHaloPair3;
+        P.dpair_cap = mid * 50 <= nblk ? idp::kHaloPair3 : idp::kHaloMax3;
         int64_t *hs;
         int32_t *hc, *hn;
         uint16_t *hl;

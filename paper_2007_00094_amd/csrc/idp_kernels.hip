@@ -1234,19 +1234,19 @@ __device__ __forceinline__ void alpha_rows(const StageArgs &P, int64_t b, const 
     if (P.argk) P.packA[int64_t(i) * kPack + kPackAlpha] = al;
 }
 
-template <int D>
+template <int D, int CAP>
 __global__ void __launch_bounds__(kBlock) k_dpair_h(StageArgs P, int with_alpha)
 {
     constexpr int NCH = (D + 5) / 2;   // gathered chunks per record
     // staged record: pack A's first 64 bytes (U, p, c, eta/rho), which the
-    // pairs and then the indicator read (40 KB per block in 3D, four
-    // blocks per CU)
+    // pairs and then the indicator read (3D: 40 KB per block and four
+    // blocks per CU at the smaller cap, 51 KB and three at the larger)
     constexpr int NS = 4;
-    static_assert(kHaloPairD<D> * NS >= (kBlock / kSlice) * NCH * kLdsRow, "gather tiles fit");
-    __shared__ double2 sh_[kHaloPairD<D> * NS];
+    static_assert(CAP * NS >= (kBlock / kSlice) * NCH * kLdsRow, "gather tiles fit");
+    __shared__ double2 sh_[CAP * NS];
     const int64_t b = logical_block(P.per);
     const int64_t p0 = P.pair_blk[b], p1 = P.pair_blk[b + 1];
-    const bool staged = stage_halo<NS, NS - 1, kPack, kHaloPairD<D>>(P, b, P.packA, sh_);
+    const bool staged = stage_halo<NS, NS - 1, kPack, CAP>(P, b, P.packA, sh_);
     if (staged) {
         // block-uniform: the indicator phase below has block barriers
         if (__syncthreads_or(failed(P))) return;
@@ -1876,9 +1876,15 @@ static inline int grid_pairs(const StageArgs &P) { return P.pper * kXcd; }
 
 void launch_dpair(const StageArgs &P, hipStream_t st, int with_alpha)
 {
-    if (P.halo_cnt && P.pair_blk)
-        LAUNCH_D(k_dpair_h, grid_rows(P), P, with_alpha);
-    else
+    const dim3 g(unsigned(grid_rows(P)));
+    if (P.halo_cnt && P.pair_blk) {
+        if (P.dim == 2)
+            hipLaunchKernelGGL((k_dpair_h<2, kHaloMax2>), g, dim3(kBlock), 0, st, P, with_alpha);
+        else if (P.dpair_cap == kHaloPair3)
+            hipLaunchKernelGGL((k_dpair_h<3, kHaloPair3>), g, dim3(kBlock), 0, st, P, with_alpha);
+        else
+            hipLaunchKernelGGL((k_dpair_h<3, kHaloMax3>), g, dim3(kBlock), 0, st, P, with_alpha);
+    } else
         LAUNCH_D(k_dpair, grid_pairs(P), P);
 }
 void launch_diag(const StageArgs &P, hipStream_t st, int mode)

@@ -26,12 +26,14 @@ constexpr int kPackLAlpha = 7;
 constexpr int kHaloMax3 = 800;
 constexpr int kHaloMax2 = 512;
 template <int D> constexpr int kHaloMaxD = D == 3 ? kHaloMax3 : kHaloMax2;
-// the staged viscosity sweep's cap (64-byte records): 632 records in 3D
-// keep its LDS under 40 KB, four blocks per CU (Morton blocks of 256 rows
-// have 600 halo nodes in the bulk, 648 and more at faces of the Morton
-// tree); blocks with more gather instead
+// a smaller cap for the staged viscosity sweep (64-byte records): 632
+// records in 3D keep its LDS under 40 KB, four blocks per CU instead of
+// three (Morton blocks of 256 rows have 600 halo nodes in the bulk, 648 and
+// more at faces of the Morton tree).  A context takes it when at most one
+// block in 50 has a halo between the two caps: those blocks gather instead,
+// several times slower (rows sorted by length over the whole mesh make
+// most blocks' halos larger)
 constexpr int kHaloPair3 = 632;
-template <int D> constexpr int kHaloPairD = D == 3 ? kHaloPair3 : kHaloMax2;
 
 // status bits (device int)
 constexpr int kErrState = 1;
@@ -105,6 +107,8 @@ struct StageArgs {
     const int64_t *halo_start;
     const int32_t *halo_cnt, *halo_node;
     const uint16_t *loc;
+    int dpair_cap;              // the staged viscosity sweep's cap in 3D:
+                                // kHaloPair3 or kHaloMax3
     // [per * 8 + 1] the pairs of each row block (those of its rows), and
     // [npairs] the halo position of each pair's node i, or null (the
     // viscosity sweep then gathers both records)
