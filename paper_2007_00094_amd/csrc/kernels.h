@@ -21,8 +21,9 @@ constexpr int kRowU = 8;      // doubles per node: state after pass 1 (nc), the
 constexpr int kPackL = 8;     // doubles per node: the low-order sweep's neighbour
                               // record U (nc), p, phi, alpha [kPackLAlpha]
 constexpr int kPackLAlpha = 7;
-// records of a row block's neighbourhood staged in LDS (3D: about 600 at
-// Morton order, 2D: about 350), at most 6 chunks each (75 KB, 48 KB)
+// records of a row block's neighbourhood staged in LDS (3D at Morton order:
+// about 600 with a 64-row SELL window, 700 with rows sorted over the whole
+// mesh; 2D: about 350), at most 6 chunks each (75 KB, 48 KB)
 constexpr int kHaloMax3 = 800;
 constexpr int kHaloMax2 = 512;
 template <int D> constexpr int kHaloMaxD = D == 3 ? kHaloMax3 : kHaloMax2;
