@@ -66,6 +66,27 @@ def test_sphere_65_per_step_full_mesh(torch, oracle_mod):
     s.close()
 
 
+def test_mach3_129_window64_whole_mesh(torch, oracle_mod):
+    """The launch configuration the benchmark times (Morton order, LDS
+    staging, SELL window of 64 rows) on a mesh the oracle steps whole.  At
+    129^3, 163 of the 8,386 row blocks have a halo beyond the viscosity
+    sweep's smaller cap (and 2 beyond the larger one), so staged and
+    gathering blocks meet in one sweep.  One CFL step: dt, status and every
+    node bit for bit the oracle's."""
+    announce("mach3_3d 129^3 Morton, SELL window 64: one CFL step, whole mesh vs oracle")
+    mesh, U0 = inputs.workload("mach3_3d", n=129, order="morton")
+    s = solver(mesh, staging=True, sell_sigma=64)
+    U = torch.tensor(U0, device="cuda")
+    dt, st = s.step(U)
+    Ug = U.cpu().numpy()
+    s.close()
+    o = oracle_mod.Oracle(mesh)
+    Uo, dto, sto = o.step(U0)
+    assert (dt, st) == (dto, sto)
+    assert np.max(rel_err(Ug, Uo)) <= 1e-12
+    assert np.array_equal(Ug, Uo)
+
+
 def _read_gold():
     g = {"sha": {}, "samples": {}}
     for line in open(GOLD):
